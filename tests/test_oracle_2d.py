@@ -1,0 +1,208 @@
+"""Pins of the 2D oracle (Sec. 4): the CAT2 closed form, reductions to 1D,
+symmetries, conservation, convergence order, and consistency of the
+sampled-cell path with the full step."""
+import numpy as np
+import pytest
+
+import oracle
+
+ADV, EUL = oracle.FLUX_ADVECTION, oracle.FLUX_EULER
+G = 1.4
+
+
+def prob2d(n1, n2, P, flux=EUL, bc=0, dx=0.1, dy=0.1, ax=1.0, ay=1.0, nvar=None):
+    nv = nvar or (4 if flux == EUL else 1)
+    return oracle.Problem(dim=2, nvar=nv, nx=n1, ny=n2, flux=flux, P=P, bc=bc, dx=dx, dy=dy, ax=ax, ay=ay)
+
+
+def euler2d_state(rng, n1, n2, jump=True):
+    rho = rng.uniform(0.6, 1.4, (n2, n1)); v = rng.uniform(-0.4, 0.4, (n2, n1))
+    w = rng.uniform(-0.4, 0.4, (n2, n1)); p = rng.uniform(0.6, 1.4, (n2, n1))
+    if jump:
+        rho[:, n1 // 2:] *= 2.5
+        p[n2 // 2:, :] *= 3.0
+    return np.stack([rho, rho * v, rho * w, p / (G - 1) + 0.5 * rho * (v * v + w * w)])
+
+
+def smooth_state(rng, n1, n2, jump=True):
+    """Smooth random Fourier data with a density/pressure jump along x."""
+    x = np.arange(n1) / n1; y = np.arange(n2) / n2
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    ph = rng.uniform(0, 2 * np.pi, 4)
+    rho = 1 + 0.2 * np.sin(2 * np.pi * X + ph[0]) * np.cos(2 * np.pi * Y + ph[1])
+    v = 0.3 * np.sin(2 * np.pi * Y + ph[2]); w = 0.3 * np.cos(2 * np.pi * X + ph[3])
+    p = 1 + 0.1 * np.cos(2 * np.pi * (X + Y) + ph[0])
+    if jump:
+        sel = (X > 0.3) & (X < 0.7)
+        rho = np.where(sel, 2.5 * rho, rho); p = np.where(sel, 3 * p, p)
+    return np.stack([rho, rho * v, rho * w, p / (G - 1) + 0.5 * rho * (v * v + w * w)])
+
+
+def fg(u):
+    rho, mx, my, E = u
+    v, w = mx / rho, my / rho
+    p = (G - 1) * (E - 0.5 * (mx * v + my * w))
+    return (np.array([mx, mx * v + p, my * v, v * (E + p)]), np.array([my, mx * w, my * w + p, w * (E + p)]))
+
+
+def maps_forced(pb, q):
+    nIx, nIy = pb.n_interfaces
+    return (np.full((pb.ny, nIx), q, np.int8), np.full((nIy, pb.nx), q, np.int8),
+            np.ones((pb.ny, nIx)), np.ones((nIy, pb.nx)), np.ones((pb.ny, nIx)), np.ones((nIy, pb.nx)))
+
+
+def test_2d_cat2_closed_form():
+    """q1 = q2 = 1: the recursion gives the 2D CAT2 fluxes of Sec. 4 built
+    from u~^(1) at 0, e1, e2."""
+    rng = np.random.default_rng(11)
+    n = 10
+    u = euler2d_state(rng, n, n, jump=False)
+    dx, dy, dt = 0.1, 0.12, 0.02
+    pb = prob2d(n, n, 1, dx=dx, dy=dy)
+    r = oracle.step2d(pb, u, dt, maps=maps_forced(pb, 1))
+    at = lambda a, b: u[:, b % n, a % n]
+    for i2 in range(n):
+        for i1 in range(n):
+            f = {k: fg(at(i1 + k[0], i2 + k[1])) for k in [(0, 0), (1, 0), (0, 1), (1, 1)]}
+            fo, go = f[(0, 0)]
+            u1_0 = -(f[(1, 0)][0] - fo) / dx - (f[(0, 1)][1] - go) / dy
+            u1_e1 = -(f[(1, 0)][0] - fo) / dx - (f[(1, 1)][1] - f[(1, 0)][1]) / dy
+            u1_e2 = -(f[(1, 1)][0] - f[(0, 1)][0]) / dx - (f[(0, 1)][1] - go) / dy
+            ff0, gg0 = fg(at(i1, i2) + dt * u1_0)
+            ffe1, _ = fg(at(i1 + 1, i2) + dt * u1_e1)
+            _, gge2 = fg(at(i1, i2 + 1) + dt * u1_e2)
+            F = 0.25 * (ff0 + ffe1 + fo + f[(1, 0)][0])
+            Gv = 0.25 * (gg0 + gge2 + go + f[(0, 1)][1])
+            assert np.allclose(r["F"][:, i2, i1], F, rtol=1e-13, atol=1e-14)
+            assert np.allclose(r["G"][:, i2, i1], Gv, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("P", [1, 2, 3])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_y_invariant_data_reproduces_1d(P, bc):
+    rng = np.random.default_rng(P + 10 * bc)
+    n1, n2 = 40, 8
+    rho = rng.uniform(0.5, 1.5, n1); v = rng.uniform(-0.5, 0.5, n1); p = rng.uniform(0.5, 1.5, n1)
+    rho[n1 // 2:] *= 3
+    u1 = np.stack([rho, rho * v, p / (G - 1) + 0.5 * rho * v * v])
+    u2 = np.stack([np.tile(rho, (n2, 1)), np.tile(rho * v, (n2, 1)), np.zeros((n2, n1)), np.tile(u1[2], (n2, 1))])
+    dt = 0.004
+    r1 = oracle.step1d(oracle.Problem(dim=1, nvar=3, nx=n1, flux=EUL, P=P, bc=bc, dx=0.02), u1, dt)
+    r2 = oracle.step2d(prob2d(n1, n2, P, bc=bc, dx=0.02, dy=0.05), u2, dt)
+    for i2 in range(n2):
+        assert np.array_equal(r2["ordx"][i2], r1["order"])
+        assert np.allclose(r2["u"][[0, 1, 3], i2], r1["u"], rtol=1e-13, atol=1e-13)
+    assert np.abs(r2["u"][2]).max() < 1e-13
+
+
+@pytest.mark.parametrize("P", [1, 2, 3])
+def test_transpose_symmetry(P):
+    rng = np.random.default_rng(20 + P)
+    n = 20
+    u = smooth_state(rng, n, n)
+    uT = np.stack([u[0].T, u[2].T, u[1].T, u[3].T])
+    pb = prob2d(n, n, P, dx=0.05, dy=0.05)
+    a = oracle.step2d(pb, u, 0.003)
+    b = oracle.step2d(pb, uT, 0.003)
+    bu = np.stack([b["u"][0].T, b["u"][2].T, b["u"][1].T, b["u"][3].T])
+    assert np.allclose(a["u"], bu, rtol=1e-13, atol=1e-13)
+    assert np.array_equal(a["ordx"], b["ordy"].T)
+    if P > 1:
+        assert (a["ordx"] != a["ordy"]).any()   # mixed rectangles were exercised
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_x_only_advection_is_row_lax_wendroff(p):
+    from fractions import Fraction as Fr
+    from oracle import rational as R
+    rng = np.random.default_rng(p)
+    n1, n2 = 20, 6
+    u = rng.standard_normal((1, n2, n1))
+    pb = prob2d(n1, n2, p, flux=ADV, dx=1.0, dy=1.0, ax=0.4, ay=0.0, nvar=1)
+    r = oracle.step2d(pb, u, 1.0, maps=maps_forced(pb, p))
+    w = [float(x) for x in R.weights(tuple(range(-p, p + 1)), Fr(-2, 5), 0)]
+    lw = sum(w[m + p] * np.roll(u[0], -m, axis=1) for m in range(-p, p + 1))
+    assert np.abs(r["u"][0] - lw).max() < 1e-13
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_free_stream_bitwise_2d(bc):
+    n = 12
+    u = np.tile(np.array([1.1, 0.3, -0.2, 2.5])[:, None, None], (1, n, n))
+    for P in (1, 2, 3):
+        r = oracle.step2d(prob2d(n, n, P, bc=bc), u, 0.01)
+        assert np.array_equal(r["u"], u)
+
+
+def test_periodic_conservation_2d():
+    rng = np.random.default_rng(5)
+    n = 20
+    u = euler2d_state(rng, n, n)
+    pb = prob2d(n, n, 3, dx=0.05, dy=0.05)
+    v = u
+    for _ in range(3):
+        v = oracle.step2d(pb, v, 0.5 * oracle.dt_cfl(pb, v, 0.4))["u"]
+    for c in range(4):
+        assert abs(v[c].sum() - u[c].sum()) < 1e-12 * np.abs(u[c]).sum()
+
+
+@pytest.mark.parametrize("P,Ns,T", [(2, (32, 64), 0.05), (3, (32, 64), 0.2)])
+def test_convergence_order_2d_entropy_wave(P, Ns, T):
+    """rho = 1 + 0.2 sin(pi(x+y)), v = w = 1, p = 1 translates along (1, 1).
+    (P = 2 is pinned on a short window: later the moving extremum crosses a
+    lateral sub-interval midpoint of every row at once, where psi^2 is known
+    to fail, Sec. 3.2.)"""
+    errs = []
+    for n in Ns:
+        x = (np.arange(n) + 0.5) * 2 / n
+        X, Y = np.meshgrid(x, x, indexing="xy")
+        mk = lambda s, t: (lambda r: np.stack([r, r, r, 1 / (G - 1) + r]))(1 + 0.2 * np.sin(np.pi * (s + t) + 0.3))
+        pb = prob2d(n, n, P, dx=2 / n, dy=2 / n)
+        u, t, _ = oracle.run(pb, mk(X, Y), 0.8, t_final=T)
+        errs.append(np.abs(u - mk(X - T, Y - T)).max())
+    rate = np.log2(errs[0] / errs[1])
+    assert rate > 2 * P - 0.5, (errs, rate)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_update_cells_matches_full_step(bc):
+    rng = np.random.default_rng(8)
+    n1, n2 = 18, 14
+    u = smooth_state(rng, n1, n2)
+    pb = prob2d(n1, n2, 3, bc=bc, dx=0.05, dy=0.04)
+    dt = 0.003
+    full = oracle.step2d(pb, u, dt)
+    cells = np.array([(i1, i2) for i2 in range(n2) for i1 in range(n1)])
+    vals, ords = oracle.update_cells(pb, u, dt, cells)
+    assert np.array_equal(vals.T.reshape(4, n2, n1), full["u"])
+    off = 0 if bc == 0 else 1
+    for s, (i1, i2) in enumerate(cells):
+        assert ords[s, 1] == full["ordx"][i2, i1 + off]
+        assert ords[s, 3] == full["ordy"][i2 + off, i1]
+
+
+def test_update_cells_matches_full_step_1d():
+    rng = np.random.default_rng(9)
+    n = 40
+    u = rng.uniform(-1, 1, (1, n)); u[0, 20:] += 2
+    for bc in (0, 1):
+        pb = oracle.Problem(dim=1, nvar=1, nx=n, flux=oracle.FLUX_BURGERS, P=3, bc=bc, dx=0.05)
+        full = oracle.step1d(pb, u, 0.01)
+        vals, _ = oracle.update_cells(pb, u, 0.01, np.array([(i, 0) for i in range(n)]))
+        assert np.array_equal(vals[:, 0], full["u"][0])
+
+
+def test_jvp_matches_central_difference_2d():
+    rng = np.random.default_rng(12)
+    n = 12
+    u = euler2d_state(rng, n, n)
+    pb = prob2d(n, n, 2, dx=0.05, dy=0.05)
+    dt = 0.5 * oracle.dt_cfl(pb, u, 0.4)
+    r = oracle.step2d(pb, u, dt)
+    maps = tuple(r[k] for k in ("ordx", "ordy", "psix", "psiy", "alx", "aly"))
+    d = rng.standard_normal(u.shape)
+    _, jv = oracle.jvp(pb, u, d, dt, maps)
+    h = 1e-6
+    up = oracle.step2d(pb, u + h * d, dt, maps=maps)["u"]
+    um = oracle.step2d(pb, u - h * d, dt, maps=maps)["u"]
+    assert np.abs((up - um) / (2 * h) - jv).max() < 1e-7 * np.abs(jv).max()
