@@ -34,6 +34,12 @@
 //     rectangular stencils); F is computed with Taylor order 2 q1 and time
 //     nodes J_{q1}, G with 2 q2 and J_{q2}; one recursion when q1 = q2.
 //   * boundaries: periodic wrap or transmissive zeroth-order extrapolation.
+//   * rounding: the paper fixes none.  Sums run in the index order the paper
+//     writes them; the weighted sums of the recursion use fused multiply-add
+//     (see mad below); nothing else is contracted.  With one fixed rounding,
+//     an implementation that follows it reproduces these results bit for
+//     bit, which matters because the limiter and the admissibility test are
+//     discontinuous in the data.
 //
 // Build: g++ -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math).
 #include <cmath>
@@ -205,11 +211,20 @@ inline Dual operator/(Dual a, Dual b) {
   return Dual(q, (a.d - q * b.d) / b.v);
 }
 inline Dual operator*(double s, Dual b) { return Dual(s * b.v, s * b.d); }
+inline Dual operator/(double s, Dual b) { return Dual(s, 0.0) / b; }
 inline Dual operator*(Dual b, double s) { return Dual(b.v * s, b.d * s); }
 inline Dual operator+(Dual a, double s) { return Dual(a.v + s, a.d); }
 inline Dual operator-(double s, Dual a) { return Dual(s - a.v, -a.d); }
 inline double val(double x) { return x; }
 inline double val(const Dual& x) { return x.v; }
+
+// a*b + c with one rounding.  Every weighted sum of the recursion (the
+// differentiation formulas in space and time, the Taylor predictions and
+// the final flux sum) accumulates in index order with this fused
+// multiply-add; all other arithmetic is plain IEEE operations, so the
+// rounding of every operation is fixed.
+inline double mad(double a, double b, double c) { return std::fma(a, b, c); }
+inline Dual mad(double a, const Dual& b, const Dual& c) { return Dual(std::fma(a, b.v, c.v), std::fma(a, b.d, c.d)); }
 
 // ---------------------------------------------------------------------------
 // Physics: fluxes and spectral radii.
@@ -247,9 +262,11 @@ void flux_f(const oracle_problem& pb, const T* u, T* f) {
     f[1] = m * v + p;
     f[2] = v * (E + p);
   } else {
-    // 2D Euler (Sec. 5.5): u = (rho, rho v, rho w, E)
+    // 2D Euler (Sec. 5.5): u = (rho, rho v, rho w, E); both velocity
+    // components use one reciprocal of the density
     T rho = u[0], mx = u[1], my = u[2], E = u[3];
-    T v = mx / rho, w = my / rho;
+    T ir = 1.0 / rho;
+    T v = mx * ir, w = my * ir;
     T p = (pb.gamma - 1.0) * (E - 0.5 * (mx * v + my * w));
     f[0] = mx;
     f[1] = mx * v + p;
@@ -265,7 +282,8 @@ void flux_g(const oracle_problem& pb, const T* u, T* g) {
     for (int c = 0; c < pb.nvar; ++c) g[c] = pb.ay * u[c];
   } else {
     T rho = u[0], mx = u[1], my = u[2], E = u[3];
-    T v = mx / rho, w = my / rho;
+    T ir = 1.0 / rho;
+    T v = mx * ir, w = my * ir;
     T p = (pb.gamma - 1.0) * (E - 0.5 * (mx * v + my * w));
     g[0] = my;
     g[1] = mx * w;
@@ -374,7 +392,7 @@ void cat_flux_1d(const oracle_problem& pb, int p, const T (*u)[VMAX], double lam
     for (int a = 0; a < nn; ++a)
       for (int c = 0; c < nv; ++c) {
         T s = 0.0;
-        for (int l = 0; l < nn; ++l) s = s + Tb.g1[p][a][l] * Fh[k - 2][l][c];
+        for (int l = 0; l < nn; ++l) s = mad(Tb.g1[p][a][l], Fh[k - 2][l][c], s);
         U[k - 1][a][c] = -lam * s;
       }
     // (b) flux at the Taylor-predicted states at the time nodes r, and
@@ -390,12 +408,12 @@ void cat_flux_1d(const oracle_problem& pb, int p, const T (*u)[VMAX], double lam
           T w[VMAX];
           for (int c = 0; c < nv; ++c) {
             T s = u[a][c];
-            for (int l = 1; l <= k - 1; ++l) s = s + Tb.taylor[r + PMAX - 1][l] * U[l][a][c];
+            for (int l = 1; l <= k - 1; ++l) s = mad(Tb.taylor[r + PMAX - 1][l], U[l][a][c], s);
             w[c] = s;
           }
           flux_f(pb, w, phi);
         }
-        for (int c = 0; c < nv; ++c) Fh[k - 1][a][c] = Fh[k - 1][a][c] + Tb.gt[p][k - 1][ri] * phi[c];
+        for (int c = 0; c < nv; ++c) Fh[k - 1][a][c] = mad(Tb.gt[p][k - 1][ri], phi[c], Fh[k - 1][a][c]);
       }
     }
   }
@@ -404,8 +422,8 @@ void cat_flux_1d(const oracle_problem& pb, int p, const T (*u)[VMAX], double lam
     T s = 0.0;
     for (int k = 1; k <= 2 * p; ++k) {
       T t = 0.0;
-      for (int a = 0; a < nn; ++a) t = t + Tb.eta[p][a] * Fh[k - 1][a][c];
-      s = s + Tb.invfact[k] * t;
+      for (int a = 0; a < nn; ++a) t = mad(Tb.eta[p][a], Fh[k - 1][a][c], t);
+      s = mad(Tb.invfact[k], t, s);
     }
     F[c] = s;
   }
@@ -533,8 +551,8 @@ void cat_corner_2d(const oracle_problem& pb, int q1, int q2, int qt, const T (*u
       for (int a2 = 0; a2 < n2; ++a2)
         for (int c = 0; c < nv; ++c) {
           T sx = 0.0, sy = 0.0;
-          for (int l = 0; l < n1; ++l) sx = sx + Tb.g1[q1][a1][l] * Fh[k - 2][l][a2][c];
-          for (int l = 0; l < n2; ++l) sy = sy + Tb.g1[q2][a2][l] * Gh[k - 2][a1][l][c];
+          for (int l = 0; l < n1; ++l) sx = mad(Tb.g1[q1][a1][l], Fh[k - 2][l][a2][c], sx);
+          for (int l = 0; l < n2; ++l) sy = mad(Tb.g1[q2][a2][l], Gh[k - 2][a1][l][c], sy);
           U[k - 1][a1][a2][c] = -lamx * sx - lamy * sy;
         }
     // (b), (c): f and g at the predicted states, time derivative at r = 0
@@ -550,15 +568,15 @@ void cat_corner_2d(const oracle_problem& pb, int q1, int q2, int qt, const T (*u
             T w[VMAX];
             for (int c = 0; c < nv; ++c) {
               T s = u[a1][a2][c];
-              for (int l = 1; l <= k - 1; ++l) s = s + Tb.taylor[r + PMAX - 1][l] * U[l][a1][a2][c];
+              for (int l = 1; l <= k - 1; ++l) s = mad(Tb.taylor[r + PMAX - 1][l], U[l][a1][a2][c], s);
               w[c] = s;
             }
             flux_f(pb, w, pf);
             flux_g(pb, w, pg);
           }
           for (int c = 0; c < nv; ++c) {
-            Fh[k - 1][a1][a2][c] = Fh[k - 1][a1][a2][c] + Tb.gt[qt][k - 1][ri] * pf[c];
-            Gh[k - 1][a1][a2][c] = Gh[k - 1][a1][a2][c] + Tb.gt[qt][k - 1][ri] * pg[c];
+            Fh[k - 1][a1][a2][c] = mad(Tb.gt[qt][k - 1][ri], pf[c], Fh[k - 1][a1][a2][c]);
+            Gh[k - 1][a1][a2][c] = mad(Tb.gt[qt][k - 1][ri], pg[c], Gh[k - 1][a1][a2][c]);
           }
         }
       }
@@ -569,8 +587,8 @@ void cat_corner_2d(const oracle_problem& pb, int q1, int q2, int qt, const T (*u
       T s = 0.0;
       for (int k = 1; k <= nt; ++k) {
         T t = 0.0;
-        for (int a = 0; a < n1; ++a) t = t + Tb.eta[q1][a] * Fh[k - 1][a][a2][c];
-        s = s + Tb.invfact[k] * t;
+        for (int a = 0; a < n1; ++a) t = mad(Tb.eta[q1][a], Fh[k - 1][a][a2][c], t);
+        s = mad(Tb.invfact[k], t, s);
       }
       F[c] = s;
     }
@@ -581,8 +599,8 @@ void cat_corner_2d(const oracle_problem& pb, int q1, int q2, int qt, const T (*u
       T s = 0.0;
       for (int k = 1; k <= nt; ++k) {
         T t = 0.0;
-        for (int a = 0; a < n2; ++a) t = t + Tb.eta[q2][a] * Gh[k - 1][a1][a][c];
-        s = s + Tb.invfact[k] * t;
+        for (int a = 0; a < n2; ++a) t = mad(Tb.eta[q2][a], Gh[k - 1][a1][a][c], t);
+        s = mad(Tb.invfact[k], t, s);
       }
       G[c] = s;
     }
