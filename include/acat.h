@@ -1,0 +1,144 @@
+/*
+ * acat.h -- C ABI of the MI355X (gfx950) ACAT library.
+ *
+ * One time step of the Adaptive Compact Approximate Taylor method of
+ * Carrillo, Macca, Pares, Russo and Zorio, "An order-adaptive compact
+ * approximation Taylor method for systems of conservation laws"
+ * (arXiv:2007.01416), for u_t + f(u)_x (+ g(u)_y) = 0 (Sec. 2, eq. of the
+ * 1D system; Sec. 4, the 2D system):
+ *
+ *   - per interface, smoothness indicators psi^p (Sec. 3.2, minimum over the
+ *     conserved components as in Sec. 3.4) choose the stencil half-width
+ *     p_s = max{p in 2..P : psi^p >= theta}, or the FL-CAT2 fallback when no
+ *     p qualifies (Sec. 3, admissible set and ACAT flux);
+ *   - the CAT2p numerical flux is the local Taylor recursion of Sec. 2.2
+ *     (centred differentiation in space and time on the 2p-point stencil in
+ *     place of the Cauchy-Kovalevskaya procedure); in 2D the corner
+ *     recursion of Sec. 4 on the rectangle J_q1 x J_q2 of the x- and
+ *     y-interface orders;
+ *   - the FL-CAT2 fallback blends CAT2 with the Rusanov flux through the
+ *     superbee limiter in its speed-free min form (Sec. 3.1);
+ *   - the conservative update (Sec. 2.1 conservative form; Sec. 3.3 in 1D;
+ *     the unsplit 2D scheme of Sec. 4).
+ *
+ * Conventions
+ *   - All arithmetic and all state arrays are IEEE binary64.
+ *   - Arrays are DEVICE pointers unless marked "host".  States are SoA
+ *     without ghost cells: 1D u[var][x], 2D u[var][y][x] (x fastest).
+ *   - Interfaces: 1D has nI = nx (periodic) or nx + 1 (transmissive)
+ *     interfaces; entry k is x_{i+1/2} with i = k (periodic) or i = k - 1
+ *     (transmissive).  2D x-interfaces are stored [ny][nIx], y-interfaces
+ *     [nIy][nx], with nIx, nIy defined the same way per direction.
+ *   - The caller owns every buffer (state, workspace, decision maps) and
+ *     allocates it; the library never allocates inside a step.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL is the
+ *     null stream) and captures into a HIP graph: no host synchronisation,
+ *     no allocation, no memset nodes.
+ *   - Functions return an acat_status and never abort or throw.  Argument
+ *     errors are detected on the host before any launch.  Non-finite
+ *     output, or non-positive density or pressure for Euler, set bits of a
+ *     device status word read by acat_device_status().
+ */
+#ifndef ACAT_H
+#define ACAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ACAT_OK = 0,
+  ACAT_ERR_NULL = -1,        /* a required pointer is NULL                     */
+  ACAT_ERR_ARG = -2,         /* invalid dim/nvar/flux/P/bc/sizes/dx/dt/theta   */
+  ACAT_ERR_ALIAS = -3,       /* u_in and u_out overlap                          */
+  ACAT_ERR_UNSUPPORTED = -4, /* valid problem the library has no kernel for    */
+  ACAT_ERR_DEVICE = -5,      /* a HIP call failed (launch or copy)              */
+  ACAT_ERR_WORKSPACE = -6    /* workspace missing or smaller than required      */
+} acat_status;
+
+enum { ACAT_FLUX_ADVECTION = 0, ACAT_FLUX_BURGERS = 1, ACAT_FLUX_EULER = 2 };
+enum { ACAT_BC_PERIODIC = 0, ACAT_BC_TRANSMISSIVE = 1 };
+
+/* Device status bits (acat_device_status). */
+enum { ACAT_DEV_NONFINITE = 1, ACAT_DEV_NONPHYSICAL = 2 };
+
+/* Problem description (host struct, passed by pointer, read at each call). */
+typedef struct {
+  int32_t dim;    /* 1 or 2                                                     */
+  int32_t nvar;   /* advection: 1; Burgers: 1 (1D only); Euler: 3 (1D), 4 (2D)   */
+  int64_t nx;     /* cells in x, >= 2 max(P, 2)                                  */
+  int64_t ny;     /* cells in y (2D), >= 2 max(P, 2); ignored in 1D              */
+  int32_t flux;   /* ACAT_FLUX_*                                                 */
+  int32_t P;      /* largest stencil half-width: 1..4 in 1D, 1..3 in 2D          */
+  int32_t bc;     /* ACAT_BC_PERIODIC (wrap) or ACAT_BC_TRANSMISSIVE (clamp)     */
+  int32_t flags;  /* reserved, must be 0                                         */
+  double gamma;   /* Euler: ratio of specific heats (Sec. 5.3 / 5.5 EOS)         */
+  double ax, ay;  /* advection speeds (f = ax u, g = ay u)                       */
+  double dx, dy;  /* grid spacings (> 0)                                         */
+  double eps;     /* epsilon of the lateral weights I_L, I_R (Sec. 3.2), >= 0    */
+  double theta;   /* admissibility threshold: psi^p >= theta, in (0, 1]          */
+} acat_problem;
+
+/* Per-interface decisions of one step (all device pointers).  order: p_s in
+ * 1..P (1 = FL-CAT2 fallback); psi1: superbee blend weight where order is 1,
+ * -1 elsewhere; alpha: Rusanov speed where order is 1, -1 elsewhere.  *_y
+ * are used in 2D only.  In acat_step any pointer may be NULL (not
+ * recorded); in acat_step_replay and acat_step_adjoint all used pointers
+ * must be set. */
+typedef struct {
+  int8_t* order_x;
+  double* psi1_x;
+  double* alpha_x;
+  int8_t* order_y;
+  double* psi1_y;
+  double* alpha_y;
+} acat_decisions;
+
+/* Bytes of device workspace acat_step / acat_step_replay need for `prob`. */
+acat_status acat_workspace_size(const acat_problem* prob, size_t* bytes /* host */);
+
+/* u_out = one ACAT step of u_in.  The time step is *dt_dev when dt_dev is
+ * not NULL (device scalar, e.g. from acat_cfl_dt), else `dt` (> 0 or 0).
+ * `dec` (nullable, host struct of device pointers) records the decisions. */
+acat_status acat_step(const acat_problem* prob, const double* u_in, double* u_out, double dt,
+                      const double* dt_dev, void* workspace, size_t workspace_bytes,
+                      const acat_decisions* dec, void* stream);
+
+/* The same step with the decisions frozen to `dec` (orders, psi1, alpha):
+ * a smooth function of u_in, the forward map differentiated by
+ * acat_step_adjoint. */
+acat_status acat_step_replay(const acat_problem* prob, const double* u_in, double* u_out, double dt,
+                             const double* dt_dev, void* workspace, size_t workspace_bytes,
+                             const acat_decisions* dec, void* stream);
+
+/* smax_dev[d] = max over cells of the spectral radius of the flux Jacobian
+ * in direction d (d < dim): |u| (Burgers), |a| (advection), |v|+c (Euler). */
+acat_status acat_max_wave_speed(const acat_problem* prob, const double* u, double* smax_dev, void* stream);
+
+/* dt_dev[0] = CFL time step from smax_dev: 1D cfl dx / s; 2D (Sec. 5.5)
+ * cfl/2 min(dx/s_x, dy/s_y).  With t_dev not NULL the step is clipped so
+ * that t does not pass t_final (0 once t >= t_final) and t_dev[0] += dt. */
+acat_status acat_cfl_dt(const acat_problem* prob, const double* smax_dev, double cfl, double t_final,
+                        double* t_dev, double* dt_dev, void* stream);
+
+/* Reads and clears the device status bits accumulated by steps on this
+ * device (synchronises `stream`).  flags_host receives ACAT_DEV_* bits. */
+acat_status acat_device_status(int32_t* flags_host, void* stream);
+
+/* Static description of a status code. */
+const char* acat_status_string(acat_status s);
+
+/* Coefficient tables the kernels use for half-width p (host arrays, row
+ * major): g1[2p][2p] first derivatives at the nodes, gt[2p][2p] k-th time
+ * derivatives at 0 (k = 0..2p-1), eta[2p] interface weights, tau[2p] the
+ * (2p-1)-th derivative weights.  For inspection and tests. */
+acat_status acat_coefficients(int32_t p, double* g1, double* gt, double* eta, double* tau);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACAT_H */

@@ -1,0 +1,237 @@
+"""MI355X-native ACAT (arXiv:2007.01416): Python binding of libacat.so.
+
+The binding only marshals arguments: every step of the method runs in the
+HIP kernels behind the C ABI of ``include/acat.h``.  PyTorch provides device
+memory and streams.  If the built library is missing, ``load()`` raises: there
+is no CPU fallback.
+
+Build first:  python -m paper_2007_01416_amd.build
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libacat.so")
+
+FLUX = {"advection": 0, "burgers": 1, "euler": 2}
+BC = {"periodic": 0, "transmissive": 1}
+STATUS = {0: "ok", -1: "null", -2: "arg", -3: "alias", -4: "unsupported", -5: "device", -6: "workspace"}
+DEV_NONFINITE, DEV_NONPHYSICAL = 1, 2
+
+
+class AcatError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__(f"{what}: acat status {code} ({STATUS.get(code, '?')})")
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("nvar", ctypes.c_int32),
+                ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
+                ("flux", ctypes.c_int32), ("P", ctypes.c_int32), ("bc", ctypes.c_int32),
+                ("flags", ctypes.c_int32),
+                ("gamma", ctypes.c_double), ("ax", ctypes.c_double), ("ay", ctypes.c_double),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("eps", ctypes.c_double), ("theta", ctypes.c_double)]
+
+
+class _Decisions(ctypes.Structure):
+    _fields_ = [("order_x", ctypes.c_void_p), ("psi1_x", ctypes.c_void_p), ("alpha_x", ctypes.c_void_p),
+                ("order_y", ctypes.c_void_p), ("psi1_y", ctypes.c_void_p), ("alpha_y", ctypes.c_void_p)]
+
+
+_lib = None
+
+_SIGS = {
+    "acat_workspace_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "acat_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                  ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p],
+    "acat_step_replay": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p],
+    "acat_max_wave_speed": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "acat_cfl_dt": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                    ctypes.c_void_p, ctypes.c_void_p],
+    "acat_device_status": [ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p],
+    "acat_status_string": [ctypes.c_int],
+    "acat_coefficients": [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load libacat.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} not built: run `python -m paper_2007_01416_amd.build`")
+        L = ctypes.CDLL(path)
+        for name, args in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.acat_status_string.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise AcatError(rc, what)
+
+
+@dataclass
+class Problem:
+    """Host-side problem description (mirrors acat_problem)."""
+    dim: int
+    nvar: int
+    nx: int
+    ny: int = 1
+    flux: str = "euler"
+    P: int = 2
+    bc: str = "periodic"
+    gamma: float = 1.4
+    ax: float = 1.0
+    ay: float = 1.0
+    dx: float = 1.0
+    dy: float = 1.0
+    eps: float = 1e-12
+    theta: float = 0.5
+    _c: _Problem = field(default=None, init=False, repr=False)
+
+    def c(self) -> _Problem:
+        self._c = _Problem(self.dim, self.nvar, self.nx, self.ny if self.dim == 2 else 1, FLUX[self.flux],
+                           self.P, BC[self.bc], 0, self.gamma, self.ax, self.ay, self.dx, self.dy, self.eps,
+                           self.theta)
+        return self._c
+
+    @property
+    def shape(self):
+        return (self.nvar, self.nx) if self.dim == 1 else (self.nvar, self.ny, self.nx)
+
+    @property
+    def interfaces(self):
+        ext = 0 if self.bc == "periodic" else 1
+        if self.dim == 1:
+            return (self.nx + ext,), None
+        return (self.ny, self.nx + ext), (self.ny + ext, self.nx)
+
+    @property
+    def cells(self):
+        return self.nx * (self.ny if self.dim == 2 else 1)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def workspace_bytes(prob: Problem) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load().acat_workspace_size(ctypes.byref(prob.c()), ctypes.byref(n)), "acat_workspace_size")
+    return n.value
+
+
+def workspace(prob: Problem, device="cuda") -> torch.Tensor:
+    return torch.empty(workspace_bytes(prob), dtype=torch.uint8, device=device)
+
+
+class Decisions:
+    """Device buffers for one step's decisions (order, psi^1, alpha per interface)."""
+
+    def __init__(self, prob: Problem, device="cuda"):
+        sx, sy = prob.interfaces
+        self.order_x = torch.zeros(sx, dtype=torch.int8, device=device)
+        self.psi1_x = torch.zeros(sx, dtype=torch.float64, device=device)
+        self.alpha_x = torch.zeros(sx, dtype=torch.float64, device=device)
+        if sy is not None:
+            self.order_y = torch.zeros(sy, dtype=torch.int8, device=device)
+            self.psi1_y = torch.zeros(sy, dtype=torch.float64, device=device)
+            self.alpha_y = torch.zeros(sy, dtype=torch.float64, device=device)
+        else:
+            self.order_y = self.psi1_y = self.alpha_y = None
+
+    def c(self) -> _Decisions:
+        self._c = _Decisions(*[t.data_ptr() if t is not None else None for t in
+                               (self.order_x, self.psi1_x, self.alpha_x, self.order_y, self.psi1_y, self.alpha_y)])
+        return self._c
+
+    def tensors(self):
+        return (self.order_x, self.psi1_x, self.alpha_x, self.order_y, self.psi1_y, self.alpha_y)
+
+    def copy_(self, other: "Decisions"):
+        for a, b in zip(self.tensors(), other.tensors()):
+            if a is not None:
+                a.copy_(b)
+        return self
+
+
+def _check_state(prob, t, name):
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != prob.shape:
+        raise ValueError(f"{name}: expected contiguous cuda float64 {prob.shape}, got {t.dtype} {tuple(t.shape)}")
+
+
+def step(prob: Problem, u: torch.Tensor, dt, out: torch.Tensor = None, ws: torch.Tensor = None,
+         dec: Decisions = None, stream=None) -> torch.Tensor:
+    """One ACAT step on the GPU.  dt: float or a 1-element cuda float64 tensor."""
+    _check_state(prob, u, "u")
+    out = torch.empty_like(u) if out is None else out
+    ws = workspace(prob, u.device) if ws is None else ws
+    dtv, dtp = (float(dt), None) if not torch.is_tensor(dt) else (0.0, _ptr(dt))
+    dc = ctypes.byref(dec.c()) if dec is not None else None
+    _check(load().acat_step(ctypes.byref(prob.c()), _ptr(u), _ptr(out), dtv, dtp, _ptr(ws), ws.numel(), dc,
+                            _stream(stream)), "acat_step")
+    return out
+
+
+def step_replay(prob: Problem, u: torch.Tensor, dt, dec: Decisions, out: torch.Tensor = None,
+                ws: torch.Tensor = None, stream=None) -> torch.Tensor:
+    """One ACAT step with frozen decisions."""
+    _check_state(prob, u, "u")
+    out = torch.empty_like(u) if out is None else out
+    ws = workspace(prob, u.device) if ws is None else ws
+    dtv, dtp = (float(dt), None) if not torch.is_tensor(dt) else (0.0, _ptr(dt))
+    _check(load().acat_step_replay(ctypes.byref(prob.c()), _ptr(u), _ptr(out), dtv, dtp, _ptr(ws), ws.numel(),
+                                   ctypes.byref(dec.c()), _stream(stream)), "acat_step_replay")
+    return out
+
+
+def max_wave_speed(prob: Problem, u: torch.Tensor, smax: torch.Tensor = None, stream=None) -> torch.Tensor:
+    _check_state(prob, u, "u")
+    smax = torch.empty(2, dtype=torch.float64, device=u.device) if smax is None else smax
+    _check(load().acat_max_wave_speed(ctypes.byref(prob.c()), _ptr(u), _ptr(smax), _stream(stream)),
+           "acat_max_wave_speed")
+    return smax
+
+
+def cfl_dt(prob: Problem, smax: torch.Tensor, cfl: float, dt: torch.Tensor, t: torch.Tensor = None,
+           t_final: float = float("inf"), stream=None) -> torch.Tensor:
+    _check(load().acat_cfl_dt(ctypes.byref(prob.c()), _ptr(smax), cfl, t_final, _ptr(t), _ptr(dt),
+                              _stream(stream)), "acat_cfl_dt")
+    return dt
+
+
+def device_status(stream=None) -> int:
+    v = ctypes.c_int32(0)
+    _check(load().acat_device_status(ctypes.byref(v), _stream(stream)), "acat_device_status")
+    return v.value
+
+
+def coefficients(p: int):
+    """The kernels' coefficient tables for half-width p (host numpy arrays)."""
+    import numpy as np
+    n = 2 * p
+    g1 = np.zeros((n, n)); gt = np.zeros((n, n)); eta = np.zeros(n); tau = np.zeros(n)
+    f = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _check(load().acat_coefficients(p, f(g1), f(gt), f(eta), f(tau)), "acat_coefficients")
+    return dict(g1=g1, gt=gt, eta=eta, tau=tau)
+
+
+from .runner import Solver  # noqa: E402  (time loop and graph capture)

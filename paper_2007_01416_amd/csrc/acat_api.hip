@@ -1,0 +1,242 @@
+// C ABI of the ACAT library: argument checks, workspace layout, launches.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "../../include/acat.h"
+#include "acat_internal.hpp"
+
+namespace acat {
+void copy_tables(int p, double* g1, double* gt, double* eta, double* tau);
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+acat_status check_problem(const acat_problem* pb) {
+  if (!pb) return ACAT_ERR_NULL;
+  if (pb->dim != 1 && pb->dim != 2) return ACAT_ERR_ARG;
+  if (pb->flags != 0) return ACAT_ERR_ARG;
+  if (pb->bc != ACAT_BC_PERIODIC && pb->bc != ACAT_BC_TRANSMISSIVE) return ACAT_ERR_ARG;
+  if (pb->flux < ACAT_FLUX_ADVECTION || pb->flux > ACAT_FLUX_EULER) return ACAT_ERR_ARG;
+  if (pb->P < 1 || pb->P > 4) return ACAT_ERR_ARG;
+  const int64_t G = pb->P > 2 ? pb->P : 2;
+  if (pb->nx < 2 * G || pb->nx > (int64_t)1 << 31) return ACAT_ERR_ARG;
+  if (pb->dim == 2 && (pb->ny < 2 * G || pb->ny > (int64_t)1 << 31)) return ACAT_ERR_ARG;
+  if (!(pb->dx > 0.0) || (pb->dim == 2 && !(pb->dy > 0.0))) return ACAT_ERR_ARG;
+  if (!(pb->eps >= 0.0) || !(pb->theta > 0.0 && pb->theta <= 1.0)) return ACAT_ERR_ARG;
+  if (pb->flux == ACAT_FLUX_EULER && pb->nvar != (pb->dim == 1 ? 3 : 4)) return ACAT_ERR_ARG;
+  if (pb->flux == ACAT_FLUX_EULER && !(pb->gamma > 1.0)) return ACAT_ERR_ARG;
+  if (pb->flux == ACAT_FLUX_BURGERS && (pb->nvar != 1 || pb->dim != 1)) return ACAT_ERR_ARG;
+  if (pb->flux == ACAT_FLUX_ADVECTION && pb->nvar < 1) return ACAT_ERR_ARG;
+  // valid problems without kernels
+  if (pb->flux == ACAT_FLUX_ADVECTION && pb->nvar != 1) return ACAT_ERR_UNSUPPORTED;
+  if (pb->dim == 2 && pb->P > 3) return ACAT_ERR_UNSUPPORTED;
+  const int64_t cells = pb->nx * (pb->dim == 2 ? pb->ny : 1);
+  const int64_t items = (pb->dim == 2) ? (pb->nx + 1) * (pb->ny + 1) : pb->nx + 1;
+  if (cells * pb->nvar >= ((int64_t)1 << 40) || items >= ((int64_t)1 << 31) - 1) return ACAT_ERR_UNSUPPORTED;
+  return ACAT_OK;
+}
+
+KProb make_kprob(const acat_problem* p) {
+  KProb k{};
+  k.dim = p->dim;
+  k.nvar = p->nvar;
+  k.flux = p->flux;
+  k.P = p->P;
+  k.bc = p->bc;
+  k.nx = p->nx;
+  k.ny = p->dim == 2 ? p->ny : 1;
+  const int64_t ext = p->bc == ACAT_BC_PERIODIC ? 0 : 1;
+  k.nIx = k.nx + ext;
+  k.nIy = p->dim == 2 ? k.ny + ext : 0;
+  k.ioff = -ext;
+  k.n1 = k.nx + ext;
+  k.n2 = p->dim == 2 ? k.ny + ext : 1;
+  k.ph.gamma = p->gamma;
+  k.ph.gm1 = p->gamma - 1.0;
+  k.ph.ax = p->ax;
+  k.ph.ay = p->ay;
+  k.dx = p->dx;
+  k.dy = p->dim == 2 ? p->dy : 1.0;
+  k.eps = p->eps;
+  k.theta = p->theta;
+  return k;
+}
+
+// Workspace layout (each part 256-byte aligned):
+//   counts  int32[MAX_CLASSES] + status uint32 (one 256-byte header)
+//   ordx, ordy    int8 decision maps     (used when the caller records none)
+//   psix, psiy    double
+//   alx, aly      double
+//   Fx, Gy        double interface fluxes
+//   lists         int32[nclass][n_items]
+struct Layout {
+  size_t hdr, ordx, ordy, psix, psiy, alx, aly, Fx, Gy, lists, total;
+  int64_t nItems, nclass;
+};
+
+Layout layout(const KProb& k) {
+  Layout L{};
+  const int64_t nx_if = k.ny * k.nIx;             // 1D: nI
+  const int64_t ny_if = k.dim == 2 ? k.nIy * k.nx : 0;
+  L.nItems = k.dim == 2 ? k.n1 * k.n2 : k.nIx;
+  L.nclass = k.dim == 2 ? (int64_t)k.P * k.P : k.P;
+  size_t o = 0;
+  L.hdr = o;   o += align_up(sizeof(int32_t) * MAX_CLASSES + sizeof(uint32_t) * 4);
+  L.ordx = o;  o += align_up((size_t)nx_if);
+  L.ordy = o;  o += align_up((size_t)ny_if);
+  L.psix = o;  o += align_up(sizeof(double) * nx_if);
+  L.psiy = o;  o += align_up(sizeof(double) * ny_if);
+  L.alx = o;   o += align_up(sizeof(double) * nx_if);
+  L.aly = o;   o += align_up(sizeof(double) * ny_if);
+  L.Fx = o;    o += align_up(sizeof(double) * k.nvar * nx_if);
+  L.Gy = o;    o += align_up(sizeof(double) * k.nvar * ny_if);
+  L.lists = o; o += align_up(sizeof(int32_t) * (size_t)(L.nclass * L.nItems));
+  L.total = o;
+  return L;
+}
+
+// Device status word: one per device, in the library's own static memory.
+__device__ uint32_t g_status;
+
+uint32_t* status_ptr() {
+  static uint32_t* ptrs[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  if (!ptrs[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_status)) != hipSuccess) return nullptr;
+    ptrs[dev] = static_cast<uint32_t*>(p);
+  }
+  return ptrs[dev];
+}
+
+bool overlaps(const void* a, const void* b, size_t n) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + n && y < x + n;
+}
+
+acat_status do_step(const acat_problem* prob, const double* u_in, double* u_out, double dt, const double* dt_dev,
+                    void* ws, size_t ws_bytes, const acat_decisions* dec, bool replay, void* stream) {
+  acat_status rc = check_problem(prob);
+  if (rc != ACAT_OK) return rc;
+  if (!u_in || !u_out) return ACAT_ERR_NULL;
+  if (!dt_dev && !(dt >= 0.0)) return ACAT_ERR_ARG;
+  const KProb k = make_kprob(prob);
+  const size_t state_bytes = sizeof(double) * (size_t)k.nvar * k.nx * k.ny;
+  if (overlaps(u_in, u_out, state_bytes)) return ACAT_ERR_ALIAS;
+  const Layout L = layout(k);
+  if (!ws || ws_bytes < L.total) return ACAT_ERR_WORKSPACE;
+  if (replay) {
+    if (!dec || !dec->order_x || !dec->psi1_x || !dec->alpha_x) return ACAT_ERR_NULL;
+    if (k.dim == 2 && (!dec->order_y || !dec->psi1_y || !dec->alpha_y)) return ACAT_ERR_NULL;
+  }
+  char* w = static_cast<char*>(ws);
+  KStep st{};
+  st.u = u_in;
+  st.uout = u_out;
+  st.dt = dt;
+  st.dt_dev = dt_dev;
+  st.ordx = (dec && dec->order_x) ? dec->order_x : reinterpret_cast<int8_t*>(w + L.ordx);
+  st.psix = (dec && dec->psi1_x) ? dec->psi1_x : reinterpret_cast<double*>(w + L.psix);
+  st.alx = (dec && dec->alpha_x) ? dec->alpha_x : reinterpret_cast<double*>(w + L.alx);
+  st.ordy = (dec && dec->order_y) ? dec->order_y : reinterpret_cast<int8_t*>(w + L.ordy);
+  st.psiy = (dec && dec->psi1_y) ? dec->psi1_y : reinterpret_cast<double*>(w + L.psiy);
+  st.aly = (dec && dec->alpha_y) ? dec->alpha_y : reinterpret_cast<double*>(w + L.aly);
+  st.Fx = reinterpret_cast<double*>(w + L.Fx);
+  st.Gy = reinterpret_cast<double*>(w + L.Gy);
+  st.counts = reinterpret_cast<int32_t*>(w + L.hdr);
+  st.lists = reinterpret_cast<int32_t*>(w + L.lists);
+  st.list_stride = L.nItems;
+  st.status = status_ptr();
+  if (!st.status) return ACAT_ERR_DEVICE;
+  st.replay = replay ? 1 : 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = k.dim == 1 ? launch_step_1d(k, st, 0, s) : launch_step_2d(k, st, 0, s);
+  return e == hipSuccess ? ACAT_OK : ACAT_ERR_DEVICE;
+}
+
+}  // namespace
+}  // namespace acat
+
+using namespace acat;
+
+extern "C" {
+
+acat_status acat_workspace_size(const acat_problem* prob, size_t* bytes) {
+  acat_status rc = check_problem(prob);
+  if (rc != ACAT_OK) return rc;
+  if (!bytes) return ACAT_ERR_NULL;
+  *bytes = layout(make_kprob(prob)).total;
+  return ACAT_OK;
+}
+
+acat_status acat_step(const acat_problem* prob, const double* u_in, double* u_out, double dt,
+                      const double* dt_dev, void* workspace, size_t workspace_bytes, const acat_decisions* dec,
+                      void* stream) {
+  return do_step(prob, u_in, u_out, dt, dt_dev, workspace, workspace_bytes, dec, false, stream);
+}
+
+acat_status acat_step_replay(const acat_problem* prob, const double* u_in, double* u_out, double dt,
+                             const double* dt_dev, void* workspace, size_t workspace_bytes,
+                             const acat_decisions* dec, void* stream) {
+  return do_step(prob, u_in, u_out, dt, dt_dev, workspace, workspace_bytes, dec, true, stream);
+}
+
+acat_status acat_max_wave_speed(const acat_problem* prob, const double* u, double* smax_dev, void* stream) {
+  acat_status rc = check_problem(prob);
+  if (rc != ACAT_OK) return rc;
+  if (!u || !smax_dev) return ACAT_ERR_NULL;
+  hipError_t e = launch_max_speed(make_kprob(prob), u, smax_dev, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? ACAT_OK : ACAT_ERR_DEVICE;
+}
+
+acat_status acat_cfl_dt(const acat_problem* prob, const double* smax_dev, double cfl, double t_final,
+                        double* t_dev, double* dt_dev, void* stream) {
+  acat_status rc = check_problem(prob);
+  if (rc != ACAT_OK) return rc;
+  if (!smax_dev || !dt_dev) return ACAT_ERR_NULL;
+  if (!(cfl > 0.0)) return ACAT_ERR_ARG;
+  hipError_t e = launch_cfl_dt(make_kprob(prob), smax_dev, cfl, t_final, t_dev, dt_dev,
+                               static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? ACAT_OK : ACAT_ERR_DEVICE;
+}
+
+acat_status acat_device_status(int32_t* flags_host, void* stream) {
+  if (!flags_host) return ACAT_ERR_NULL;
+  uint32_t* p = status_ptr();
+  if (!p) return ACAT_ERR_DEVICE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint32_t v = 0;
+  if (hipMemcpyAsync(&v, p, sizeof(v), hipMemcpyDeviceToHost, s) != hipSuccess) return ACAT_ERR_DEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return ACAT_ERR_DEVICE;
+  const uint32_t zero = 0;
+  if (hipMemcpyAsync(p, &zero, sizeof(zero), hipMemcpyHostToDevice, s) != hipSuccess) return ACAT_ERR_DEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return ACAT_ERR_DEVICE;
+  *flags_host = (int32_t)v;
+  return ACAT_OK;
+}
+
+const char* acat_status_string(acat_status s) {
+  switch (s) {
+    case ACAT_OK: return "ok";
+    case ACAT_ERR_NULL: return "required pointer is NULL";
+    case ACAT_ERR_ARG: return "invalid argument";
+    case ACAT_ERR_ALIAS: return "input and output states overlap";
+    case ACAT_ERR_UNSUPPORTED: return "problem not supported by the GPU kernels";
+    case ACAT_ERR_DEVICE: return "HIP runtime error";
+    case ACAT_ERR_WORKSPACE: return "workspace missing or too small";
+  }
+  return "unknown status";
+}
+
+acat_status acat_coefficients(int32_t p, double* g1, double* gt, double* eta, double* tau) {
+  if (p < 1 || p > 4) return ACAT_ERR_ARG;
+  copy_tables(p, g1, gt, eta, tau);
+  return ACAT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,57 @@
+// Internal structures shared by the ABI layer and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "physics.hpp"
+
+namespace acat {
+
+constexpr int BLOCK = 256;        // threads per block of every step kernel
+constexpr int MAX_CLASSES = 16;   // order classes: P in 1D, P*P in 2D
+
+// Problem geometry and parameters as the kernels see them.
+struct KProb {
+  int dim, nvar, flux, P, bc;
+  int64_t nx, ny;
+  int64_t nIx, nIy;   // x-interfaces per row, y-interfaces per column
+  int64_t ioff;       // interface entry k <-> cell i = k + ioff (0 or -1)
+  int64_t n1, n2;     // 2D corner grid extents: i1 in [ioff, nx), i2 in [ioff, ny)
+  Phys ph;
+  double dx, dy, eps, theta;
+};
+
+// Everything one step's kernels read and write.
+struct KStep {
+  const double* u;
+  double* uout;
+  double dt;
+  const double* dt_dev;   // device time step (overrides dt when not null)
+  int8_t* ordx;
+  double* psix;
+  double* alx;
+  int8_t* ordy;
+  double* psiy;
+  double* aly;
+  double* Fx;             // x-interface fluxes [nvar][ny][nIx] (1D: [nvar][nI])
+  double* Gy;             // y-interface fluxes [nvar][nIy][nx]
+  int32_t* counts;        // [MAX_CLASSES] items per order class
+  int32_t* lists;         // [nclass][list_stride] item ids per class
+  int64_t list_stride;
+  uint32_t* status;       // device status bits
+  int replay;             // decisions given in ord/psi/al
+};
+
+__device__ __forceinline__ double step_dt(const KStep& s) { return s.dt_dev ? *s.dt_dev : s.dt; }
+
+// Launchers (return the first HIP error).
+hipError_t launch_step_1d(const KProb& pb, const KStep& st, int grid_blocks, hipStream_t stream);
+hipError_t launch_step_2d(const KProb& pb, const KStep& st, int grid_blocks, hipStream_t stream);
+hipError_t launch_max_speed(const KProb& pb, const double* u, double* smax, hipStream_t stream);
+hipError_t launch_cfl_dt(const KProb& pb, const double* smax, double cfl, double t_final, double* t_dev,
+                         double* dt_dev, hipStream_t stream);
+
+}  // namespace acat

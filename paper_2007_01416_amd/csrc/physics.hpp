@@ -1,0 +1,106 @@
+// Fluxes and spectral radii of the supported conservation laws (device code).
+//   advection  f = ax u, g = ay u                  (Sec. 5.1 / 5.4)
+//   Burgers    f = u^2 / 2                          (Sec. 5.2)
+//   Euler 1D   u = (rho, rho v, E), ideal gas      (Sec. 5.3)
+//   Euler 2D   u = (rho, rho v, rho w, E)          (Sec. 5.5)
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace acat {
+
+enum FluxId { ADV = 0, BURG = 1, EUL = 2 };
+enum BcId { PERIODIC = 0, TRANSMISSIVE = 1 };
+
+struct Phys {
+  double gm1;   // gamma - 1
+  double gamma;
+  double ax, ay;
+};
+
+// x-direction flux of a 1D law
+template <int FLUX, int NV>
+__device__ __forceinline__ void flux1d(const Phys& ph, const double (&u)[NV], double (&f)[NV]) {
+  if constexpr (FLUX == ADV) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) f[c] = ph.ax * u[c];
+  } else if constexpr (FLUX == BURG) {
+    f[0] = 0.5 * (u[0] * u[0]);
+  } else {
+    static_assert(NV == 3, "1D Euler has 3 conserved variables");
+    const double v = u[1] / u[0];
+    const double p = ph.gm1 * (u[2] - 0.5 * (u[1] * v));
+    f[0] = u[1];
+    f[1] = u[1] * v + p;
+    f[2] = v * (u[2] + p);
+  }
+}
+
+// x- and y-direction fluxes of a 2D law at one state (shared primitives)
+template <int FLUX, int NV>
+__device__ __forceinline__ void flux2d(const Phys& ph, const double (&u)[NV], double (&f)[NV], double (&g)[NV]) {
+  if constexpr (FLUX == ADV) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      f[c] = ph.ax * u[c];
+      g[c] = ph.ay * u[c];
+    }
+  } else {
+    static_assert(FLUX == EUL && NV == 4, "2D Euler has 4 conserved variables");
+    const double ir = 1.0 / u[0];
+    const double v = u[1] * ir;
+    const double w = u[2] * ir;
+    const double p = ph.gm1 * (u[3] - 0.5 * (u[1] * v + u[2] * w));
+    const double ep = u[3] + p;
+    f[0] = u[1];
+    f[1] = u[1] * v + p;
+    f[2] = u[2] * v;
+    f[3] = v * ep;
+    g[0] = u[2];
+    g[1] = u[1] * w;
+    g[2] = u[2] * w + p;
+    g[3] = w * ep;
+  }
+}
+
+// spectral radius of the flux Jacobian in direction d (0: x, 1: y)
+template <int FLUX, int DIM, int NV>
+__device__ __forceinline__ double spectral_radius(const Phys& ph, const double (&u)[NV], int d) {
+  if constexpr (FLUX == ADV) {
+    return fabs(d == 0 ? ph.ax : ph.ay);
+  } else if constexpr (FLUX == BURG) {
+    return fabs(u[0]);
+  } else if constexpr (DIM == 1) {
+    const double v = u[1] / u[0];
+    const double p = ph.gm1 * (u[2] - 0.5 * u[0] * v * v);
+    return fabs(v) + sqrt(ph.gamma * p / u[0]);
+  } else {
+    const double v = u[1] / u[0], w = u[2] / u[0];
+    const double p = ph.gm1 * (u[3] - 0.5 * u[0] * (v * v + w * w));
+    return (d == 0 ? fabs(v) : fabs(w)) + sqrt(ph.gamma * p / u[0]);
+  }
+}
+
+// physical admissibility of an Euler state (density and pressure positive)
+template <int FLUX, int DIM, int NV>
+__device__ __forceinline__ bool physical(const Phys& ph, const double (&u)[NV]) {
+  if constexpr (FLUX != EUL) {
+    return true;
+  } else if constexpr (DIM == 1) {
+    const double p = ph.gm1 * (u[2] - 0.5 * u[1] * u[1] / u[0]);
+    return u[0] > 0.0 && p > 0.0;
+  } else {
+    const double p = ph.gm1 * (u[3] - 0.5 * (u[1] * u[1] + u[2] * u[2]) / u[0]);
+    return u[0] > 0.0 && p > 0.0;
+  }
+}
+
+// Boundary index map for a node index i in [-n, 2n) (every stencil offset is
+// at most max(P, 2) < n cells outside the grid): periodic wrap or
+// transmissive zeroth-order extrapolation (clamp).
+__device__ __forceinline__ int64_t bc_index(int64_t i, int64_t n, int bc) {
+  if (bc == PERIODIC) return i < 0 ? i + n : (i >= n ? i - n : i);
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+}  // namespace acat

@@ -1,0 +1,103 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/acat.h declares, rejects invalid arguments before
+any launch, and its compile-time coefficient tables equal the oracle's
+(independently derived) tables bit for bit."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2007_01416_amd", "libacat.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libacat.so not built")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2007_01416_amd as acat
+    return acat.load()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "acat.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(acat_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 8
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.acat_status_string(code)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_kernel_tables_equal_oracle_tables(p):
+    import paper_2007_01416_amd as acat
+    a = acat.coefficients(p)
+    o = oracle.coeffs(p)
+    for k in ("g1", "gt", "eta", "tau"):
+        assert np.array_equal(a[k], o[k]), k
+
+
+def _prob(**kw):
+    import paper_2007_01416_amd as acat
+    base = dict(dim=1, nvar=3, nx=64, flux="euler", P=2, bc="periodic", dx=0.1)
+    base.update(kw)
+    return acat.Problem(**base)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(dim=3), -2), (dict(P=0), -2), (dict(P=5), -2), (dict(nvar=2), -2), (dict(dx=0.0), -2),
+    (dict(nx=3), -2), (dict(theta=0.0), -2), (dict(theta=1.5), -2), (dict(eps=-1.0), -2),
+    (dict(flux="burgers", nvar=1, dim=2, ny=16, dy=0.1), -2),
+    (dict(flux="advection", nvar=2), -4), (dict(dim=2, nvar=4, ny=64, dy=0.1, P=4), -4),
+    (dict(gamma=1.0), -2),
+])
+def test_workspace_size_rejects_invalid_problems(lib, kw, code):
+    n = ctypes.c_size_t(0)
+    assert lib.acat_workspace_size(ctypes.byref(_prob(**kw).c()), ctypes.byref(n)) == code
+
+
+def test_step_argument_errors_before_launch(lib):
+    p = _prob()
+    pc = p.c()
+    ws = ctypes.create_string_buffer(16)
+    buf = (ctypes.c_double * (3 * 64))()
+    buf2 = (ctypes.c_double * (3 * 64))()
+    a, b = ctypes.cast(buf, ctypes.c_void_p), ctypes.cast(buf2, ctypes.c_void_p)
+    # null state
+    assert lib.acat_step(ctypes.byref(pc), None, b, 0.1, None, ws, 16, None, None) == -1
+    # aliasing input and output
+    assert lib.acat_step(ctypes.byref(pc), a, a, 0.1, None, ws, 16, None, None) == -3
+    # negative dt
+    assert lib.acat_step(ctypes.byref(pc), a, b, -1.0, None, ws, 16, None, None) == -2
+    # workspace too small
+    assert lib.acat_step(ctypes.byref(pc), a, b, 0.1, None, ws, 16, None, None) == -6
+    # replay needs decision maps
+    need = ctypes.c_size_t(0)
+    lib.acat_workspace_size(ctypes.byref(pc), ctypes.byref(need))
+    big = ctypes.create_string_buffer(need.value)
+    assert lib.acat_step_replay(ctypes.byref(pc), a, b, 0.1, None, big, need.value, None, None) == -1
+    # cfl: non-positive cfl
+    assert lib.acat_cfl_dt(ctypes.byref(pc), a, 0.0, 1.0, None, b, None) == -2
+    assert lib.acat_max_wave_speed(ctypes.byref(pc), None, b, None) == -1
+
+
+def test_workspace_grows_with_problem(lib):
+    import paper_2007_01416_amd as acat
+    small = acat.workspace_bytes(_prob(nx=64))
+    large = acat.workspace_bytes(_prob(nx=4096, P=4))
+    assert large > small > 0
+    w2 = acat.workspace_bytes(_prob(dim=2, nvar=4, nx=64, ny=32, dy=0.1, P=3))
+    assert w2 > 9 * 4 * 64 * 32

@@ -89,11 +89,18 @@ def _vortex_field(X, Y, L, centres_, eps, gamma):
     return dv, dw, dT
 
 
-def euler_2d(seed=DEFAULT_SEED + 2, n=2048, L=20.0, nvort=8, nbands=4, P=3, cfl=0.4):
+AXIS_BANDS = [(1, 0), (0, 1), (1, 0), (0, 1)]
+
+
+def euler_2d(seed=DEFAULT_SEED + 2, n=2048, L=20.0, nvort=8, nbands=4, P=3, cfl=0.4, dirs=None):
     """Uniform flow (1,1,1,1) + nvort isentropic vortices (strength U[1,5],
     centres at periodic distance >= 4, images over 3x3 periods) + nbands
-    straight bands along (1,0), (0,1), (1,1), (1,-1) with offset U[0,L) and
-    width U[0.1L, 0.3L], inside which p *= U[2,10] and rho *= U[0.5,2]."""
+    straight bands with offset U[0,L) and width U[0.1L, 0.3L], inside which
+    p *= U[2,10] and rho *= U[0.5,2]; each band gives two straight
+    contact/shock lines.  The lines are axis-aligned by default (dirs): the
+    2D indicators inspect only the row and the column through an interface,
+    which every axis-aligned line crossing a stencil also crosses, while a
+    diagonal line can cut a stencil corner unseen."""
     rng = _rng(seed)
     x, dx = centres(0.0, L, n)
     X, Y = np.meshgrid(x, x, indexing="xy")     # X[i2, i1] = x_{i1}
@@ -120,7 +127,7 @@ def euler_2d(seed=DEFAULT_SEED + 2, n=2048, L=20.0, nvort=8, nbands=4, P=3, cfl=
     p = rho * T
     v = 1.0 + dv
     w = 1.0 + dw
-    dirs = [(1, 0), (0, 1), (1, 1), (1, -1)]
+    dirs = dirs or AXIS_BANDS
     for b in range(nbands):
         d = dirs[b % 4]
         off = rng.uniform(0.0, L)
