@@ -1,0 +1,160 @@
+"""Benchmark: ACAT FP64 cell-updates/s on the 2D Euler 2048^2 workload (one GPU).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+One step is the whole hot path on the device: max wave speed reduction,
+CFL time step, classification (indicators, orders, limiter), the per-class
+flux kernels and the conservative update.  The state starts resident in
+HBM; W untimed steps run first, then K steps are timed between two device
+synchronisations.  Prints one JSON line (see the `roofline` and
+`cpu_baseline` objects for the dominant kernel and the CPU oracle).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector: 256 CU x 128 flop/clk x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+WORKLOAD = ("2D Euler gamma=1.4, 2048x2048, periodic, ACAT P=3, CFL 0.4, 8 isentropic vortices + "
+            "4 axis-aligned contact/shock lines (p jumps U[2,10])")
+
+
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_c3_counters.txt")
+    src = os.path.join(ROOT, "paper_2007_01416_amd", "csrc", "acat_step.hip")
+    if not os.path.exists(path):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != digest:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, nsteps_sample=1):
+    """The oracle, as it stands, on one full step of the same workload."""
+    import numpy as np
+    import oracle
+    n = w["u"].shape[-1]
+    cores = min(16, len(os.sched_getaffinity(0)))
+    po = oracle.Problem(dim=2, nvar=4, nx=n, ny=n, flux=oracle.FLUX_EULER, P=w["P"], bc=oracle.BC_PERIODIC,
+                        dx=w["dx"], dy=w["dy"], gamma=w["gamma"])
+    u = np.ascontiguousarray(w["u"])
+    t0 = time.perf_counter()
+    for _ in range(nsteps_sample):
+        dt = oracle.dt_cfl(po, u, w["cfl"])
+        u = oracle.step2d(po, u, dt, nthreads=cores)["u"]
+    el = time.perf_counter() - t0
+    return {"value": n * n * nsteps_sample / el, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{nsteps_sample} full {n}x{n} P={w['P']} step(s) of the same workload from its initial "
+                      f"state ({el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        sys.exit("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus must be 1)")
+
+    import numpy as np
+    import torch
+
+    import paper_2007_01416_amd as acat
+    from paper_2007_01416_amd import flops as F
+    import workloads
+
+    acat.load()
+    w = workloads.euler_2d(n=args.n)
+    n = args.n
+    prob = acat.Problem(dim=2, nvar=4, nx=n, ny=n, flux="euler", P=w["P"], bc="periodic", dx=w["dx"], dy=w["dy"],
+                        gamma=w["gamma"])
+    s = acat.Solver(prob, w["u"], w["cfl"])
+    for _ in range(args.warmup):
+        s.step()
+    counts = s.ws[:64].view(torch.int32)          # per-class item counts of the last step
+    hist = torch.zeros((args.steps, 16), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    acat.profile(True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        s.step()
+        hist[k].copy_(counts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = acat.profile_read()
+    acat.profile(False)
+    hist = hist.cpu().numpy().astype(np.int64)
+    flags = acat.device_status()
+
+    cells = n * n
+    value = cells * args.steps / el
+    P = w["P"]
+    class_flops = {}
+    for q1 in range(1, P + 1):
+        for q2 in range(1, P + 1):
+            cls = (q1 - 1) * P + (q2 - 1)
+            class_flops[f"flux2d_q{q1}{q2}"] = int(hist[:, cls].sum()) * F.corner_flops_2d(q1, q2)
+    kernels = {k: {"launches": c, "avg_us": 1e3 * ms / max(c, 1), "total_ms": ms} for k, (c, ms) in prof.items()}
+    dom = max((k for k in kernels if k.startswith("flux2d")), key=lambda k: kernels[k]["total_ms"])
+    dom_launches = kernels[dom]["launches"]
+    achieved = class_flops[dom] / (kernels[dom]["total_ms"] * 1e-3) / 1e12
+    traffic = traffic_from_profiles(dom)
+    alg_total = sum(class_flops.values()) + args.steps * cells * (F.classify_flops(P, 4, 2) + F.update_flops(4, 2))
+    kern_ms = sum(v["total_ms"] for v in kernels.values())
+    hist_cls = hist[:, :P * P].sum(0)
+    out = {
+        "metric": "ACAT FP64 cell-updates/s, 2D Euler 2048^2",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded generator, workloads.euler_2d)",
+        "config": {"workload": WORKLOAD, "nx": n, "ny": n, "P": P, "cfl": w["cfl"],
+                   "first_timed_step": args.warmup},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": traffic, "launches": dom_launches,
+                     "avg_launch_us": kernels[dom]["avg_us"],
+                     "alg_flops_per_launch": class_flops[dom] / max(dom_launches, 1)},
+        "step_alg_tflops": alg_total / el / 1e12,
+        "kernel_time_fraction": kern_ms / (1e3 * el),
+        "order_classes": {f"q{q1}{q2}": int(hist_cls[(q1 - 1) * P + (q2 - 1)]) for q1 in range(1, P + 1)
+                          for q2 in range(1, P + 1)},
+        "kernels": {k: {"launches": v["launches"], "avg_us": round(v["avg_us"], 2)} for k, v in kernels.items()},
+        "device_status": flags,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

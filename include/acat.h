@@ -131,6 +131,18 @@ acat_status acat_device_status(int32_t* flags_host, void* stream);
 /* Static description of a status code. */
 const char* acat_status_string(acat_status s);
 
+/* Kernel timer.  acat_profile_enable(1) clears the record and starts
+ * bracketing every kernel launch of the library with two HIP events on the
+ * launch stream (launches into a capturing stream are not timed);
+ * acat_profile_enable(0) clears and stops.  acat_profile_read() waits for
+ * the recorded events and returns, per kernel name (at most max_kernels, in
+ * order of first launch), the total time in ms and the number of launches;
+ * names receives 64-byte NUL-terminated strings.  *n_kernels is the number of
+ * distinct kernels recorded (may exceed max_kernels). */
+acat_status acat_profile_enable(int32_t on);
+acat_status acat_profile_read(int32_t max_kernels, char* names /* host [max][64] */, double* total_ms,
+                              int64_t* launches, int32_t* n_kernels);
+
 /* Coefficient tables the kernels use for half-width p (host arrays, row
  * major): g1[2p][2p] first derivatives at the nodes, gt[2p][2p] k-th time
  * derivatives at 0 (k = 0..2p-1), eta[2p] interface weights, tau[2p] the

@@ -59,6 +59,9 @@ _SIGS = {
     "acat_device_status": [ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p],
     "acat_status_string": [ctypes.c_int],
     "acat_coefficients": [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "acat_profile_enable": [ctypes.c_int32],
+    "acat_profile_read": [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                          ctypes.POINTER(ctypes.c_int32)],
 }
 
 
@@ -232,6 +235,25 @@ def coefficients(p: int):
     f = lambda a: a.ctypes.data_as(ctypes.c_void_p)
     _check(load().acat_coefficients(p, f(g1), f(gt), f(eta), f(tau)), "acat_coefficients")
     return dict(g1=g1, gt=gt, eta=eta, tau=tau)
+
+
+def profile(on: bool = True):
+    """Start (clear) or stop the library's kernel timer."""
+    _check(load().acat_profile_enable(1 if on else 0), "acat_profile_enable")
+
+
+def profile_read(max_kernels: int = 64) -> dict:
+    """{kernel name: (launches, total ms)} of the launches timed since profile(True)."""
+    names = ctypes.create_string_buffer(64 * max_kernels)
+    ms = (ctypes.c_double * max_kernels)()
+    cnt = (ctypes.c_int64 * max_kernels)()
+    n = ctypes.c_int32(0)
+    _check(load().acat_profile_read(max_kernels, names, ms, cnt, ctypes.byref(n)), "acat_profile_read")
+    out = {}
+    for k in range(min(n.value, max_kernels)):
+        nm = names.raw[64 * k:64 * (k + 1)].split(b"\0")[0].decode()
+        out[nm] = (int(cnt[k]), float(ms[k]))
+    return out
 
 
 from .runner import Solver  # noqa: E402  (time loop and graph capture)

@@ -47,6 +47,16 @@ struct KStep {
 
 __device__ __forceinline__ double step_dt(const KStep& s) { return s.dt_dev ? *s.dt_dev : s.dt; }
 
+// Kernel timer: when enabled, every launch of the library is bracketed by
+// two HIP events on its own stream (not while the stream is being captured
+// into a graph).  acat_profile_read() reports per-kernel totals.
+struct ProfScope {
+  int slot;
+  hipStream_t stream;
+  ProfScope(const char* name, hipStream_t s);
+  ~ProfScope();
+};
+
 // Launchers (return the first HIP error).
 hipError_t launch_step_1d(const KProb& pb, const KStep& st, int grid_blocks, hipStream_t stream);
 hipError_t launch_step_2d(const KProb& pb, const KStep& st, int grid_blocks, hipStream_t stream);

@@ -667,26 +667,41 @@ int flux_grid(int64_t nitems, int per_block, int cap) {
 
 template <int FLUX, int NV, int P>
 hipError_t step1d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s) {
-  k_zero_i32<<<1, 64, 0, s>>>(st.counts, MAX_CLASSES);
+  {
+    ProfScope ps("zero", s);
+    k_zero_i32<<<1, 64, 0, s>>>(st.counts, MAX_CLASSES);
+  }
   ACAT_CHECK_LAUNCH();
   const int64_t nI = pb.nIx;
-  k_classify1d<FLUX, NV, P><<<(unsigned)((nI + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st);
+  {
+    ProfScope ps("classify1d", s);
+    k_classify1d<FLUX, NV, P><<<(unsigned)((nI + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st);
+  }
   ACAT_CHECK_LAUNCH();
-  k_flux1d<FLUX, NV, 1><<<flux_grid(nI, BLOCK / 2, cap), BLOCK, 0, s>>>(pb, st);
+  {
+    ProfScope ps("flux1d_p1", s);
+    k_flux1d<FLUX, NV, 1><<<flux_grid(nI, BLOCK / 2, cap), BLOCK, 0, s>>>(pb, st);
+  }
   ACAT_CHECK_LAUNCH();
   if constexpr (P >= 2) {
+    ProfScope ps("flux1d_p2", s);
     k_flux1d<FLUX, NV, 2><<<flux_grid(nI, BLOCK / 4, cap), BLOCK, 0, s>>>(pb, st);
-    ACAT_CHECK_LAUNCH();
   }
+  ACAT_CHECK_LAUNCH();
   if constexpr (P >= 3) {
+    ProfScope ps("flux1d_p3", s);
     k_flux1d<FLUX, NV, 3><<<flux_grid(nI, BLOCK / 6, cap), BLOCK, 0, s>>>(pb, st);
-    ACAT_CHECK_LAUNCH();
   }
+  ACAT_CHECK_LAUNCH();
   if constexpr (P >= 4) {
+    ProfScope ps("flux1d_p4", s);
     k_flux1d<FLUX, NV, 4><<<flux_grid(nI, BLOCK / 8, cap), BLOCK, 0, s>>>(pb, st);
-    ACAT_CHECK_LAUNCH();
   }
-  k_update1d<FLUX, NV><<<(unsigned)((pb.nx + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st);
+  ACAT_CHECK_LAUNCH();
+  {
+    ProfScope ps("update1d", s);
+    k_update1d<FLUX, NV><<<(unsigned)((pb.nx + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st);
+  }
   ACAT_CHECK_LAUNCH();
   return hipSuccess;
 }
@@ -695,7 +710,14 @@ template <int FLUX, int NV, int P, int Q1, int Q2>
 hipError_t launch_class2d(const KProb& pb, const KStep& st, int64_t ncorner, int cap, hipStream_t s) {
   if constexpr (Q1 <= P && Q2 <= P) {
     constexpr int L = 4 * Q1 * Q2;
-    k_flux2d<FLUX, NV, Q1, Q2><<<flux_grid(ncorner, BLOCK / L, cap), BLOCK, 0, s>>>(pb, st);
+    static const char* names[4][4] = {{"", "", "", ""},
+                                      {"", "flux2d_q11", "flux2d_q12", "flux2d_q13"},
+                                      {"", "flux2d_q21", "flux2d_q22", "flux2d_q23"},
+                                      {"", "flux2d_q31", "flux2d_q32", "flux2d_q33"}};
+    {
+      ProfScope ps(names[Q1][Q2], s);
+      k_flux2d<FLUX, NV, Q1, Q2><<<flux_grid(ncorner, BLOCK / L, cap), BLOCK, 0, s>>>(pb, st);
+    }
     ACAT_CHECK_LAUNCH();
   }
   return hipSuccess;
@@ -703,10 +725,16 @@ hipError_t launch_class2d(const KProb& pb, const KStep& st, int64_t ncorner, int
 
 template <int FLUX, int NV, int P>
 hipError_t step2d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s) {
-  k_zero_i32<<<1, 64, 0, s>>>(st.counts, MAX_CLASSES);
+  {
+    ProfScope ps("zero", s);
+    k_zero_i32<<<1, 64, 0, s>>>(st.counts, MAX_CLASSES);
+  }
   ACAT_CHECK_LAUNCH();
   const int64_t nc = pb.n1 * pb.n2;
-  k_classify2d<FLUX, NV, P><<<(unsigned)((nc + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st);
+  {
+    ProfScope ps("classify2d", s);
+    k_classify2d<FLUX, NV, P><<<(unsigned)((nc + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st);
+  }
   ACAT_CHECK_LAUNCH();
   hipError_t e;
   if ((e = launch_class2d<FLUX, NV, P, 1, 1>(pb, st, nc, cap, s)) != hipSuccess) return e;
@@ -718,7 +746,10 @@ hipError_t step2d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s)
   if ((e = launch_class2d<FLUX, NV, P, 2, 3>(pb, st, nc, cap, s)) != hipSuccess) return e;
   if ((e = launch_class2d<FLUX, NV, P, 3, 2>(pb, st, nc, cap, s)) != hipSuccess) return e;
   if ((e = launch_class2d<FLUX, NV, P, 3, 3>(pb, st, nc, cap, s)) != hipSuccess) return e;
-  k_update2d<FLUX, NV><<<(unsigned)((pb.nx * pb.ny + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st);
+  {
+    ProfScope ps("update2d", s);
+    k_update2d<FLUX, NV><<<(unsigned)((pb.nx * pb.ny + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st);
+  }
   ACAT_CHECK_LAUNCH();
   return hipSuccess;
 }
@@ -774,6 +805,7 @@ hipError_t launch_step_2d(const KProb& pb, const KStep& st, int grid_blocks, hip
 
 hipError_t launch_max_speed(const KProb& pb, const double* u, double* smax, hipStream_t s) {
   unsigned long long* sm = reinterpret_cast<unsigned long long*>(smax);
+  ProfScope ps("max_speed", s);
   k_zero_u64<<<1, 64, 0, s>>>(sm, pb.dim);
   ACAT_CHECK_LAUNCH();
   const int64_t n = pb.nx * (pb.dim == 2 ? pb.ny : 1);
@@ -794,6 +826,7 @@ hipError_t launch_max_speed(const KProb& pb, const double* u, double* smax, hipS
 
 hipError_t launch_cfl_dt(const KProb& pb, const double* smax, double cfl, double t_final, double* t_dev,
                          double* dt_dev, hipStream_t s) {
+  ProfScope ps("cfl_dt", s);
   k_cfl_dt<<<1, 1, 0, s>>>(pb.dim, pb.dx, pb.dy, smax, cfl, t_final, t_dev, dt_dev);
   ACAT_CHECK_LAUNCH();
   return hipSuccess;
