@@ -62,8 +62,10 @@ typedef enum {
 enum { ACAT_FLUX_ADVECTION = 0, ACAT_FLUX_BURGERS = 1, ACAT_FLUX_EULER = 2 };
 enum { ACAT_BC_PERIODIC = 0, ACAT_BC_TRANSMISSIVE = 1 };
 
-/* Device status bits (acat_device_status). */
-enum { ACAT_DEV_NONFINITE = 1, ACAT_DEV_NONPHYSICAL = 2 };
+/* Device status bits (acat_device_status): non-finite output state,
+ * non-positive density or pressure (Euler), and (replay) a recorded order
+ * outside 1..P, replaced by 1. */
+enum { ACAT_DEV_NONFINITE = 1, ACAT_DEV_NONPHYSICAL = 2, ACAT_DEV_BAD_ORDER = 4 };
 
 /* Problem description (host struct, passed by pointer, read at each call). */
 typedef struct {

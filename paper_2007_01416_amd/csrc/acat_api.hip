@@ -71,10 +71,13 @@ KProb make_kprob(const acat_problem* p) {
 //   psix, psiy    double
 //   alx, aly      double
 //   Fx, Gy        double interface fluxes
-//   lists         int32[nclass][n_items]
+//   cls           int8 order class of every 2D corner
+//   hist          int32[tiles][MAX_CLASSES]
+//   offs          int32[MAX_CLASSES][tiles + 1]
+//   list          int32[items]
 struct Layout {
-  size_t hdr, ordx, ordy, psix, psiy, alx, aly, Fx, Gy, lists, total;
-  int64_t nItems, nclass;
+  size_t hdr, ordx, ordy, psix, psiy, alx, aly, Fx, Gy, cls, hist, offs, list, total;
+  int64_t nItems;
 };
 
 Layout layout(const KProb& k) {
@@ -82,7 +85,7 @@ Layout layout(const KProb& k) {
   const int64_t nx_if = k.ny * k.nIx;             // 1D: nI
   const int64_t ny_if = k.dim == 2 ? k.nIy * k.nx : 0;
   L.nItems = k.dim == 2 ? k.n1 * k.n2 : k.nIx;
-  L.nclass = k.dim == 2 ? (int64_t)k.P * k.P : k.P;
+  const int64_t cblocks = (L.nItems + BLOCK - 1) / BLOCK;
   size_t o = 0;
   L.hdr = o;   o += align_up(sizeof(int32_t) * MAX_CLASSES + sizeof(uint32_t) * 4);
   L.ordx = o;  o += align_up((size_t)nx_if);
@@ -93,7 +96,10 @@ Layout layout(const KProb& k) {
   L.aly = o;   o += align_up(sizeof(double) * ny_if);
   L.Fx = o;    o += align_up(sizeof(double) * k.nvar * nx_if);
   L.Gy = o;    o += align_up(sizeof(double) * k.nvar * ny_if);
-  L.lists = o; o += align_up(sizeof(int32_t) * (size_t)(L.nclass * L.nItems));
+  L.cls = o;   o += align_up(k.dim == 2 ? (size_t)L.nItems : 0);
+  L.hist = o;  o += align_up(sizeof(int32_t) * MAX_CLASSES * (size_t)cblocks);
+  L.offs = o;  o += align_up(sizeof(int32_t) * MAX_CLASSES * (size_t)(cblocks + 1));
+  L.list = o;  o += align_up(sizeof(int32_t) * (size_t)L.nItems);
   L.total = o;
   return L;
 }
@@ -149,8 +155,10 @@ acat_status do_step(const acat_problem* prob, const double* u_in, double* u_out,
   st.Fx = reinterpret_cast<double*>(w + L.Fx);
   st.Gy = reinterpret_cast<double*>(w + L.Gy);
   st.counts = reinterpret_cast<int32_t*>(w + L.hdr);
-  st.lists = reinterpret_cast<int32_t*>(w + L.lists);
-  st.list_stride = L.nItems;
+  st.cls = reinterpret_cast<int8_t*>(w + L.cls);
+  st.hist = reinterpret_cast<int32_t*>(w + L.hist);
+  st.offs = reinterpret_cast<int32_t*>(w + L.offs);
+  st.list = reinterpret_cast<int32_t*>(w + L.list);
   st.status = status_ptr();
   if (!st.status) return ACAT_ERR_DEVICE;
   st.replay = replay ? 1 : 0;

@@ -38,9 +38,11 @@ struct KStep {
   double* aly;
   double* Fx;             // x-interface fluxes [nvar][ny][nIx] (1D: [nvar][nI])
   double* Gy;             // y-interface fluxes [nvar][nIy][nx]
+  int8_t* cls;            // 2D: order class (q1-1)*P + (q2-1) of every corner [n2][n1]
+  int32_t* hist;          // per-tile class histograms of the classification kernel [tiles][MAX_CLASSES]
+  int32_t* offs;          // per-class exclusive prefix of hist over tiles [MAX_CLASSES][tiles + 1]
   int32_t* counts;        // [MAX_CLASSES] items per order class
-  int32_t* lists;         // [nclass][list_stride] item ids per class
-  int64_t list_stride;
+  int32_t* list;          // item ids grouped by class, spatial order within a class [items]
   uint32_t* status;       // device status bits
   int replay;             // decisions given in ord/psi/al
 };

@@ -2,21 +2,24 @@
 // conservative update, CFL reduction.
 //
 // Data flow of one step (all on one stream, no host synchronisation):
-//   k_zero         clears the per-class counters
 //   k_classify*    one thread per 1D interface / 2D corner: smoothness
 //                  indicators psi^p (Sec. 3.2, minimum over components,
 //                  Sec. 3.4), order p_s (Sec. 3, admissible set), and where
 //                  p_s = 1 the superbee weight psi^1 (Sec. 3.1) and the
-//                  Rusanov speed; appends the item to the work list of its
-//                  order class (wave ballot + one atomic per wave and class)
-//   k_flux*<class> persistent kernels, one per order class: one LANE PER
-//                  STENCIL NODE, so a 1D interface of order p occupies 2p
-//                  lanes and a 2D corner of orders (q1, q2) occupies
+//                  Rusanov speed; writes the order (1D) or the corner's
+//                  order class (2D) as one byte, and a per-block histogram
+//   k_sum_hist     per-class item counts (instrumentation)
+//   k_flux*<class> persistent kernels, one per order class.  A block walks
+//                  tiles of the class map, compacts the matching items into
+//                  an LDS ring (wave ballots, no global atomics; items keep
+//                  their spatial order) and processes them in rounds with
+//                  one LANE PER STENCIL NODE: a 1D interface of order p
+//                  occupies 2p lanes, a 2D corner of orders (q1, q2)
 //                  2q1 x 2q2 lanes.  Each lane keeps its node's state and
 //                  Taylor history in registers and evaluates the flux at its
-//                  own predicted states; the only cross-lane step, the
-//                  spatial derivative of the time-derivative fluxes, goes
-//                  through LDS (Sec. 2.2 recursion, Sec. 4 corner recursion)
+//                  own predicted states; the spatial derivatives of the
+//                  time-derivative fluxes go through LDS (Sec. 2.2
+//                  recursion, Sec. 4 corner recursion)
 //   k_update*      conservative flux-difference update + status bits
 #include <hip/hip_runtime.h>
 
@@ -91,42 +94,88 @@ __device__ __forceinline__ double limiter(const double (&v)[NV][2 * G]) {
   return psi;
 }
 
-// Append `id` to the list of class `cls` (all lanes of the wave call this).
-__device__ __forceinline__ void append(int32_t* counts, int32_t* lists, int64_t stride, int ncls, bool valid,
-                                       int cls, int32_t id) {
-  const int lane = __lane_id();
-  for (int c = 0; c < ncls; ++c) {
-    const unsigned long long m = __ballot(valid && cls == c);
-    if (m == 0ull) continue;
-    const int leader = __ffsll((long long)m) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&counts[c], __popcll(m));
-    base = __shfl(base, leader);
-    if (valid && cls == c) {
-      const unsigned long long below = m & ((1ull << lane) - 1ull);
-      lists[(int64_t)c * stride + base + __popcll(below)] = id;
-    }
-  }
-}
-
-// Persistent-loop partition: blocks on XCD x (blockIdx % 8) walk a contiguous
-// eighth of the work list, so neighbouring items share that XCD's L2.
-struct Part {
-  int64_t beg, end, first, step;
-  __device__ Part(int32_t count, int per_block) {
-    const int xcd = blockIdx.x % NXCD;
+// Balanced slice of one class list: the n items of class c (spatial order)
+// are cut into gridDim.x contiguous slices, and the slices of the blocks on
+// XCD x (blockIdx % 8) are adjacent, so neighbouring items share that XCD's L2.
+struct Slice {
+  const int32_t* items;
+  int64_t lo, hi;
+  __device__ Slice(const KStep& st, int c) {
+    int64_t base = 0;
+    for (int k = 0; k < c; ++k) base += st.counts[k];
+    const int64_t n = st.counts[c];
     const int nb = gridDim.x / NXCD;
-    const int bx = blockIdx.x / NXCD;
-    beg = (int64_t)count * xcd / NXCD;
-    end = (int64_t)count * (xcd + 1) / NXCD;
-    first = beg + (int64_t)bx * per_block;
-    step = (int64_t)nb * per_block;
+    const int r = (blockIdx.x % NXCD) * nb + blockIdx.x / NXCD;
+    lo = n * r / gridDim.x;
+    hi = n * (r + 1) / gridDim.x;
+    items = st.list + base;
   }
 };
 
-__global__ void k_zero_i32(int32_t* p, int n) {
-  const int t = threadIdx.x;
-  if (t < n) p[t] = 0;
+// Per-block class histogram (LDS atomics), written without global atomics.
+__device__ __forceinline__ void block_hist(int* sh, bool valid, int cls, int32_t* out) {
+  if (threadIdx.x < MAX_CLASSES) sh[threadIdx.x] = 0;
+  __syncthreads();
+  if (valid) atomicAdd(&sh[cls], 1);
+  __syncthreads();
+  if (threadIdx.x < MAX_CLASSES) out[(int64_t)blockIdx.x * MAX_CLASSES + threadIdx.x] = sh[threadIdx.x];
+}
+
+// offs[c][t] = items of class c in tiles < t, counts[c] = total; one block per class.
+__global__ __launch_bounds__(BLOCK) void k_scan_hist(const int32_t* hist, int ntiles, int32_t* offs,
+                                                     int32_t* counts) {
+  __shared__ int part[BLOCK];
+  const int c = blockIdx.x;
+  const int per = (ntiles + BLOCK - 1) / BLOCK;
+  const int t0 = threadIdx.x * per;
+  int acc = 0;
+  for (int t = t0; t < t0 + per && t < ntiles; ++t) acc += hist[(int64_t)t * MAX_CLASSES + c];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int k = 0; k < BLOCK; ++k) {
+      const int v = part[k];
+      part[k] = run;
+      run += v;
+    }
+    counts[c] = run;
+    offs[(int64_t)c * (ntiles + 1) + ntiles] = run;
+  }
+  __syncthreads();
+  int run = part[threadIdx.x];
+  for (int t = t0; t < t0 + per && t < ntiles; ++t) {
+    offs[(int64_t)c * (ntiles + 1) + t] = run;
+    run += hist[(int64_t)t * MAX_CLASSES + c];
+  }
+}
+
+// list[base_c + offs[c][tile] + rank] = item, for the item of every thread
+// (rank among the tile's items of the same class, in thread order).  One
+// block per tile of the classification; no atomics, deterministic.
+template <int NCLS>
+__global__ __launch_bounds__(BLOCK) void k_scatter(const int8_t* map, int map_bias, int64_t nitems, int ntiles,
+                                                   const int32_t* offs, const int32_t* counts, int32_t* list) {
+  __shared__ int wc[NCLS][BLOCK / 64];
+  const int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int c = e < nitems ? map[e] - map_bias : -1;
+  const int lane = __lane_id(), wid = threadIdx.x >> 6;
+  unsigned long long mine = 0ull;
+#pragma unroll
+  for (int k = 0; k < NCLS; ++k) {
+    const unsigned long long m = __ballot(c == k);
+    if (c == k) mine = m;
+    if (lane == 0) wc[k][wid] = __popcll(m);
+  }
+  __syncthreads();
+  if (c >= 0 && c < NCLS) {
+    int64_t pos = 0;
+    for (int k = 0; k < c; ++k) pos += counts[k];
+    pos += offs[(int64_t)c * (ntiles + 1) + blockIdx.x];
+    for (int w = 0; w < wid; ++w) pos += wc[c][w];
+    pos += __popcll(mine & ((1ull << lane) - 1ull));
+    list[pos] = (int32_t)e;
+  }
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int n) {
@@ -144,6 +193,10 @@ __global__ __launch_bounds__(BLOCK) void k_classify1d(KProb pb, KStep st) {
   if (valid) {
     if (st.replay) {
       ps = st.ordx[k];
+      if (ps < 1 || ps > P) {   // invalid recorded order: fall back to 1, flag it
+        ps = 1;
+        atomicOr(st.status, 4u);
+      }
     } else {
       const int64_t i = k + pb.ioff;
       double v[NV][2 * G];
@@ -170,128 +223,140 @@ __global__ __launch_bounds__(BLOCK) void k_classify1d(KProb pb, KStep st) {
       st.alx[k] = al;
     }
   }
-  append(st.counts, st.lists, st.list_stride, P, valid, ps - 1, (int32_t)k);
+  __shared__ int sh[MAX_CLASSES];
+  block_hist(sh, valid, ps - 1, st.hist);
 }
 
-// CAT2p flux of the interfaces of order class p (p = 1: FL-CAT2 blend).
+// CAT2p flux of the interfaces of order p (p = 1: FL-CAT2 blend).
 // Rounding follows one fixed order: every weighted sum of the recursion is a
 // chain of fused multiply-adds in index order, nothing else is contracted
 // (the library is built with -ffp-contract=off).
 template <int FLUX, int NV, int p>
 __global__ __launch_bounds__(BLOCK) void k_flux1d(KProb pb, KStep st) {
   constexpr int L = 2 * p;            // lanes per interface = stencil nodes
-  constexpr int GPB = BLOCK / L;      // interfaces per block
-  __shared__ double xs[2][(BLOCK + L) * NV];
+  constexpr int GPB = BLOCK / L;      // interfaces per round
+  constexpr int SL = L + 1;           // LDS slots per interface (one pad slot against bank conflicts)
+  constexpr int NS = GPB * SL + SL;   // slots per component, idle lanes included
+  __shared__ double xs[2][NV][NS];
 
   const int tid = threadIdx.x;
   const int g = tid / L;
   const int a = tid - g * L;          // node index, offset j = a - p + 1
+  const int slot = g * SL + a;
   const bool inblk = g < GPB;
-  const int32_t count = st.counts[p - 1];
-  const int32_t* list = st.lists + (int64_t)(p - 1) * st.list_stride;
   const double lam = step_dt(st) / pb.dx;
-  const int64_t nx = pb.nx;
+  const int64_t nx = pb.nx, nI = pb.nIx;
 
   double g1[L];
 #pragma unroll
   for (int l = 0; l < L; ++l) g1[l] = TB.G1[p][a][l];
 
   int buf = 0;
-  const Part part(count, GPB);
-  for (int64_t base = part.first; base < part.end; base += part.step) {
-    const int64_t item = base + g;
-    const bool valid = inblk && item < part.end;
-    const bool lead = valid && a == 0;   // lane that assembles the interface flux
-    const int32_t k = valid ? list[item] : 0;
-    const int64_t i = k + pb.ioff;
-    const int64_t node = bc_index(i + (a - p + 1), nx, pb.bc);
-    double u[NV];
+  const Slice sl(st, p - 1);
+  for (int64_t base = sl.lo; base < sl.hi; base += GPB) {
+    {
+      const bool valid = inblk && base + g < sl.hi;
+      const int32_t k = valid ? sl.items[base + g] : 0;
+      const int64_t i = k + pb.ioff;
+      const int64_t node = bc_index(i + (a - p + 1), nx, pb.bc);
+      double u[NV];
 #pragma unroll
-    for (int c = 0; c < NV; ++c) u[c] = valid ? st.u[c * nx + node] : 1.0;
+      for (int c = 0; c < NV; ++c) u[c] = valid ? st.u[c * nx + node] : 1.0;
 
-    double fh0[NV], cur[NV], F[NV];
-    flux1d<FLUX, NV>(pb.ph, u, fh0);
+      double fh0[NV], cur[NV];
+      flux1d<FLUX, NV>(pb.ph, u, fh0);
 #pragma unroll
-    for (int c = 0; c < NV; ++c) {
-      cur[c] = fh0[c];
-      F[c] = 0.0;
-    }
-    double U[L][NV];   // U[l] = dt^l u~^(l) at this node, l = 1 .. 2p-1
+      for (int c = 0; c < NV; ++c) cur[c] = fh0[c];
+      // assembly of the flux: lane a < NV sums component a (and a + L, ...)
+      double F0 = 0.0, F1 = 0.0;
+      double U[L][NV];   // U[l] = dt^l u~^(l) at this node, l = 1 .. 2p-1
 #pragma unroll
-    for (int kk = 2; kk <= 2 * p + 1; ++kk) {
-      // share Fh^{kk-2} of every node of the stencil
+      for (int kk = 2; kk <= 2 * p + 1; ++kk) {
+        // share Fh^{kk-2} of every node of the stencil
 #pragma unroll
-      for (int c = 0; c < NV; ++c) xs[buf][tid * NV + c] = cur[c];
-      __syncthreads();
-      const double* row = &xs[buf][g * L * NV];
-      if (lead) {
+        for (int c = 0; c < NV; ++c) xs[buf][c][slot] = cur[c];
+        __syncthreads();
         // F += (1/(kk-1)!) sum_j eta_j Fh^{kk-2}_j  (the CAT flux, Sec. 2.2)
+        if (valid && a < NV) {
+          double tsum = 0.0;
+#pragma unroll
+          for (int l = 0; l < L; ++l) tsum = fma(TB.ETA[p][l], xs[buf][a][g * SL + l], tsum);
+          F0 = fma(TB.INVFACT[kk - 1], tsum, F0);
+        }
+        if (NV > L && valid && a + L < NV) {
+          double tsum = 0.0;
+#pragma unroll
+          for (int l = 0; l < L; ++l) tsum = fma(TB.ETA[p][l], xs[buf][(a + L) % NV][g * SL + l], tsum);
+          F1 = fma(TB.INVFACT[kk - 1], tsum, F1);
+        }
+        if (kk == 2 * p + 1) break;
+        // U^{kk-1} = -lambda * (spatial derivative of Fh^{kk-2} at this node)
 #pragma unroll
         for (int c = 0; c < NV; ++c) {
-          double t = 0.0;
+          double sacc = 0.0;
 #pragma unroll
-          for (int l = 0; l < L; ++l) t = fma(TB.ETA[p][l], row[l * NV + c], t);
-          F[c] = fma(TB.INVFACT[kk - 1], t, F[c]);
+          for (int l = 0; l < L; ++l) sacc = fma(g1[l], xs[buf][c][g * SL + l], sacc);
+          U[kk - 1][c] = -lam * sacc;
         }
-      }
-      if (kk == 2 * p + 1) break;
-      // U^{kk-1} = -lambda * (spatial derivative of Fh^{kk-2} at this node)
+        buf ^= 1;
+        // flux at the Taylor-predicted states of the time nodes r, and its
+        // (kk-1)-th time derivative at r = 0
+        double nxt[NV];
 #pragma unroll
-      for (int c = 0; c < NV; ++c) {
-        double sacc = 0.0;
+        for (int c = 0; c < NV; ++c) nxt[c] = 0.0;
 #pragma unroll
-        for (int l = 0; l < L; ++l) sacc = fma(g1[l], row[l * NV + c], sacc);
-        U[kk - 1][c] = -lam * sacc;
-      }
-      buf ^= 1;
-      // flux at the Taylor-predicted states of the time nodes r, and its
-      // (kk-1)-th time derivative at r = 0
-      double nxt[NV];
+        for (int ri = 0; ri < L; ++ri) {
+          const int r = ri - p + 1;
+          double ph[NV];
+          if (r == 0) {
 #pragma unroll
-      for (int c = 0; c < NV; ++c) nxt[c] = 0.0;
+            for (int c = 0; c < NV; ++c) ph[c] = fh0[c];
+          } else {
+            double w[NV];
 #pragma unroll
-      for (int ri = 0; ri < L; ++ri) {
-        const int r = ri - p + 1;
-        double ph[NV];
-        if (r == 0) {
+            for (int c = 0; c < NV; ++c) {
+              double sacc = u[c];
 #pragma unroll
-          for (int c = 0; c < NV; ++c) ph[c] = fh0[c];
-        } else {
-          double w[NV];
-#pragma unroll
-          for (int c = 0; c < NV; ++c) {
-            double sacc = u[c];
-#pragma unroll
-            for (int l = 1; l <= kk - 1; ++l) sacc = fma(TB.TAYLOR[r + PMAX - 1][l], U[l][c], sacc);
-            w[c] = sacc;
+              for (int l = 1; l <= kk - 1; ++l) sacc = fma(TB.TAYLOR[r + PMAX - 1][l], U[l][c], sacc);
+              w[c] = sacc;
+            }
+            flux1d<FLUX, NV>(pb.ph, w, ph);
           }
-          flux1d<FLUX, NV>(pb.ph, w, ph);
+#pragma unroll
+          for (int c = 0; c < NV; ++c) nxt[c] = fma(TB.GT[p][kk - 1][ri], ph[c], nxt[c]);
         }
 #pragma unroll
-        for (int c = 0; c < NV; ++c) nxt[c] = fma(TB.GT[p][kk - 1][ri], ph[c], nxt[c]);
+        for (int c = 0; c < NV; ++c) cur[c] = nxt[c];
       }
+      buf ^= 1;   // the assembly above may still read the last buffer
+      if (valid && a < NV) {
+        for (int task = 0; task < 2; ++task) {
+          const int c = a + task * L;
+          if (c >= NV) break;
+          double F = task == 0 ? F0 : F1;
+          if constexpr (p == 1) {
+            // FL-CAT2 (Sec. 3.1): psi^1 CAT2 + (1 - psi^1) Rusanov
+            const double psi = st.psix[k], al = st.alx[k];
+            const int64_t nl = bc_index(i, nx, pb.bc), nr = bc_index(i + 1, nx, pb.bc);
+            double uL[NV], uR[NV], fL[NV], fR[NV];
 #pragma unroll
-      for (int c = 0; c < NV; ++c) cur[c] = nxt[c];
-    }
-    if (lead) {
-      if constexpr (p == 1) {
-        // FL-CAT2 (Sec. 3.1): psi^1 CAT2 + (1 - psi^1) Rusanov
-        const double psi = st.psix[k], al = st.alx[k];
-        const int64_t nr = bc_index(i + 1, nx, pb.bc);
-        double uR[NV], fR[NV];
+            for (int cc = 0; cc < NV; ++cc) {
+              uL[cc] = st.u[cc * nx + nl];
+              uR[cc] = st.u[cc * nx + nr];
+            }
+            flux1d<FLUX, NV>(pb.ph, uL, fL);
+            flux1d<FLUX, NV>(pb.ph, uR, fR);
+            double flo = 0.0, ul = 0.0, ur = 0.0, fl = 0.0, fr = 0.0;
 #pragma unroll
-        for (int c = 0; c < NV; ++c) uR[c] = st.u[c * nx + nr];
-        flux1d<FLUX, NV>(pb.ph, uR, fR);
-#pragma unroll
-        for (int c = 0; c < NV; ++c) {
-          const double flo = 0.5 * (fh0[c] + fR[c]) - (0.5 * al) * (uR[c] - u[c]);
-          F[c] = psi * F[c] + (1.0 - psi) * flo;
+            for (int cc = 0; cc < NV; ++cc)
+              if (cc == c) { ul = uL[cc]; ur = uR[cc]; fl = fL[cc]; fr = fR[cc]; }
+            flo = 0.5 * (fl + fr) - (0.5 * al) * (ur - ul);
+            F = psi * F + (1.0 - psi) * flo;
+          }
+          st.Fx[c * nI + k] = F;
         }
       }
-#pragma unroll
-      for (int c = 0; c < NV; ++c) st.Fx[c * pb.nIx + k] = F[c];
     }
-    buf ^= 1;
   }
 }
 
@@ -331,6 +396,11 @@ __global__ __launch_bounds__(BLOCK) void k_classify2d(KProb pb, KStep st) {
     if (st.replay) {
       q1 = st.ordx[r2 * pb.nIx + (i1 - pb.ioff)];
       q2 = st.ordy[(i2 - pb.ioff) * nx + r1];
+      if (q1 < 1 || q1 > P || q2 < 1 || q2 > P) {   // invalid recorded order: fall back to 1, flag it
+        q1 = (q1 < 1 || q1 > P) ? 1 : q1;
+        q2 = (q2 < 1 || q2 > P) ? 1 : q2;
+        atomicOr(st.status, 4u);
+      }
     } else {
       double v[NV][2 * G];
       // x-interface (i1 + 1/2, i2)
@@ -385,57 +455,91 @@ __global__ __launch_bounds__(BLOCK) void k_classify2d(KProb pb, KStep st) {
       }
     }
   }
-  append(st.counts, st.lists, st.list_stride, P * P, valid, (q1 - 1) * P + (q2 - 1), (int32_t)e);
+  const int cls = (q1 - 1) * P + (q2 - 1);
+  if (e < pb.n1 * pb.n2) st.cls[e] = valid ? (int8_t)cls : (int8_t)-1;
+  __shared__ int sh[MAX_CLASSES];
+  block_hist(sh, valid, cls, st.hist);
 }
 
+// LDS exchange of the time-derivative fluxes of a 2D corner: per node, the
+// NV components of Fh and of Gh stored as double2 pairs in component-major
+// planes (consecutive lanes write consecutive 16-byte words).
+//   NV = 4: planes (F0,F1) (F2,F3) (G0,G1) (G2,G3);   NV = 1: plane (F0,G0)
+template <int NV>
+struct Xch {
+  static constexpr int NP = NV == 1 ? 1 : NV;
+  static __device__ __forceinline__ void put(double2* plane0, int stride, int slot, const double (&f)[NV],
+                                             const double (&g)[NV]) {
+    if constexpr (NV == 1) {
+      plane0[slot] = make_double2(f[0], g[0]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < NV; c += 2) {
+        plane0[(c / 2) * stride + slot] = make_double2(f[c], f[c + 1]);
+        plane0[(NV / 2 + c / 2) * stride + slot] = make_double2(g[c], g[c + 1]);
+      }
+    }
+  }
+  // component c of Fh (G = false) or Gh (G = true) at a slot
+  static __device__ __forceinline__ double get(const double* planes, int stride, int slot, int c, bool G) {
+    if constexpr (NV == 1) {
+      return planes[2 * slot + (G ? 1 : 0)];
+    } else {
+      const int pl = (G ? NV / 2 : 0) + c / 2;
+      return planes[2 * (pl * stride + slot) + (c & 1)];
+    }
+  }
+};
+
 // One recursion over the rectangle J_Q1 x J_Q2 with time nodes J_QT
-// (Taylor order 2 QT).  Each lane is one node (a1, a2); the lead lane (node
-// (0, 0)) assembles F from row j2 = 0 (DOF) and G from column j1 = 0 (DOG).
-// Same fixed rounding as the 1D kernel.
+// (Taylor order 2 QT).  Each lane is one node (a1, a2).  The flux F (row
+// j2 = 0, DOF) and G (column j1 = 0, DOG) are assembled on 2 NV lanes, one
+// component each (task = nd for F, nd - NV for G; lanes with L < 2 NV take
+// a second task nd + L).  Same fixed rounding as the 1D kernel.
 template <int FLUX, int NV, int Q1, int Q2, int QT, bool DOF, bool DOG>
 __device__ __forceinline__ void corner_pass(const Phys& ph, double lamx, double lamy, const double (&u)[NV],
                                             const double (&f0)[NV], const double (&g0)[NV],
                                             const double (&g1x)[2 * Q1], const double (&g1y)[2 * Q2],
-                                            double (*xs)[(BLOCK + 4 * Q1 * Q2) * 2 * NV], int& buf, int tid,
-                                            int gbase, int a1, int a2, bool lead, double (&F)[NV],
-                                            double (&G)[NV]) {
-  constexpr int N1 = 2 * Q1, N2 = 2 * Q2, S = 2 * NV;
+                                            double2* xsb0, double2* xsb1, int stride, int& buf, int tid,
+                                            int gbase, int a1, int a2, int nd, bool valid, double (&acc)[2]) {
+  constexpr int N1 = 2 * Q1, N2 = 2 * Q2, L = N1 * N2;
   double fc[NV], gc[NV];
 #pragma unroll
   for (int c = 0; c < NV; ++c) {
     fc[c] = f0[c];
     gc[c] = g0[c];
-    if (DOF) F[c] = 0.0;
-    if (DOG) G[c] = 0.0;
   }
+  // tasks of this lane: task < NV is F component task, else G component task - NV
+  const int task0 = nd, task1 = nd + L;
+  const bool do0 = valid && task0 < 2 * NV && ((task0 < NV) ? DOF : DOG);
+  const bool do1 = valid && task1 < 2 * NV && ((task1 < NV) ? DOF : DOG);
+  if (do0) acc[0] = 0.0;
+  if (do1) acc[1] = 0.0;
   double U[2 * QT][NV];
 #pragma unroll
   for (int kk = 2; kk <= 2 * QT + 1; ++kk) {
-#pragma unroll
-    for (int c = 0; c < NV; ++c) {
-      xs[buf][tid * S + c] = fc[c];
-      xs[buf][tid * S + NV + c] = gc[c];
-    }
+    double2* xsw = buf ? xsb1 : xsb0;
+    Xch<NV>::put(xsw, stride, tid, fc, gc);
     __syncthreads();
-    const double* rowp = &xs[buf][(gbase + a2 * N1) * S];   // this node's row  (l, j2)
-    const double* colp = &xs[buf][(gbase + a1) * S + NV];   // this node's column (j1, l)
-    if (lead) {
-      // F += (1/(kk-1)!) sum_l eta_l Fh^{kk-2}_(l,0);  G likewise on column 0
+    const double* xr = reinterpret_cast<const double*>(xsw);
+    // assembly: acc += (1/(kk-1)!) sum_l eta_l Fh^{kk-2}_(l,0)   (or Gh on column 0)
 #pragma unroll
-      for (int c = 0; c < NV; ++c) {
-        if (DOF) {
-          double t = 0.0;
+    for (int tk = 0; tk < 2; ++tk) {
+      const int task = tk == 0 ? task0 : task1;
+      if (!(tk == 0 ? do0 : do1)) continue;
+      const bool isG = task >= NV;
+      const int c = isG ? task - NV : task;
+      double tsum = 0.0;
+      if (!isG) {
 #pragma unroll
-          for (int l = 0; l < N1; ++l) t = fma(TB.ETA[Q1][l], rowp[l * S + c], t);
-          F[c] = fma(TB.INVFACT[kk - 1], t, F[c]);
-        }
-        if (DOG) {
-          double t = 0.0;
+        for (int l = 0; l < N1; ++l)
+          tsum = fma(TB.ETA[Q1][l], Xch<NV>::get(xr, stride, gbase + (Q2 - 1) * N1 + l, c, false), tsum);
+      } else {
 #pragma unroll
-          for (int l = 0; l < N2; ++l) t = fma(TB.ETA[Q2][l], colp[l * N1 * S + c], t);
-          G[c] = fma(TB.INVFACT[kk - 1], t, G[c]);
-        }
+        for (int l = 0; l < N2; ++l)
+          tsum = fma(TB.ETA[Q2][l], Xch<NV>::get(xr, stride, gbase + l * N1 + (Q1 - 1), c, true), tsum);
       }
+      acc[tk] = fma(TB.INVFACT[kk - 1], tsum, acc[tk]);
     }
     if (kk == 2 * QT + 1) break;
     // U^{kk-1} = -lamx d_x Fh^{kk-2} - lamy d_y Gh^{kk-2} at this node
@@ -443,9 +547,9 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, double lamx, double 
     for (int c = 0; c < NV; ++c) {
       double sx = 0.0, sy = 0.0;
 #pragma unroll
-      for (int l = 0; l < N1; ++l) sx = fma(g1x[l], rowp[l * S + c], sx);
+      for (int l = 0; l < N1; ++l) sx = fma(g1x[l], Xch<NV>::get(xr, stride, gbase + a2 * N1 + l, c, false), sx);
 #pragma unroll
-      for (int l = 0; l < N2; ++l) sy = fma(g1y[l], colp[l * N1 * S + c], sy);
+      for (int l = 0; l < N2; ++l) sy = fma(g1y[l], Xch<NV>::get(xr, stride, gbase + l * N1 + a1, c, true), sy);
       U[kk - 1][c] = -lamx * sx - lamy * sy;
     }
     buf ^= 1;
@@ -488,29 +592,28 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, double lamx, double 
       gc[c] = ng[c];
     }
   }
-  // the lead lane may still read the buffer of the final exchange: the next
-  // writer (a second pass or the next corner) must use the other one
+  // the assembly may still read the buffer of the final exchange: the next
+  // writer (a second pass or the next round) must use the other one
   buf ^= 1;
 }
 
 // Fluxes of the corners of order class (Q1, Q2) (Sec. 4; rectangle J_Q1 x J_Q2).
 template <int FLUX, int NV, int Q1, int Q2>
 __global__ __launch_bounds__(BLOCK) void k_flux2d(KProb pb, KStep st) {
-  constexpr int N1 = 2 * Q1, N2 = 2 * Q2, L = N1 * N2, CPB = BLOCK / L, S = 2 * NV;
-  __shared__ double xs[2][(BLOCK + L) * S];
+  constexpr int N1 = 2 * Q1, N2 = 2 * Q2, L = N1 * N2, CPB = BLOCK / L;
+  constexpr int NP = Xch<NV>::NP;
+  constexpr int STRIDE = BLOCK + L;        // slots per plane (idle lanes included)
+  __shared__ double2 xs[2][NP * STRIDE];
 
   const int tid = threadIdx.x;
   const int g = tid / L;
   const int nd = tid - g * L;
   const int a1 = nd % N1, a2 = nd / N1;     // node (j1, j2) = (a1 - Q1 + 1, a2 - Q2 + 1)
   const bool inblk = g < CPB;
-  const int P = pb.P;
-  const int cls = (Q1 - 1) * P + (Q2 - 1);
-  const int32_t count = st.counts[cls];
-  const int32_t* list = st.lists + (int64_t)cls * st.list_stride;
+  const int cls = (Q1 - 1) * pb.P + (Q2 - 1);
   const double dt = step_dt(st);
   const double lamx = dt / pb.dx, lamy = dt / pb.dy;
-  const int64_t nx = pb.nx, ny = pb.ny;
+  const int64_t nx = pb.nx, ny = pb.ny, nc = pb.n1 * pb.n2;
 
   double g1x[N1], g1y[N2];
 #pragma unroll
@@ -519,70 +622,69 @@ __global__ __launch_bounds__(BLOCK) void k_flux2d(KProb pb, KStep st) {
   for (int l = 0; l < N2; ++l) g1y[l] = TB.G1[Q2][a2][l];
 
   int buf = 0;
-  const Part part(count, CPB);
-  for (int64_t base = part.first; base < part.end; base += part.step) {
-    const int64_t item = base + g;
-    const bool valid = inblk && item < part.end;
-    const bool lead = valid && a1 == Q1 - 1 && a2 == Q2 - 1;
-    const int32_t e = valid ? list[item] : 0;
-    const int64_t i1 = e % pb.n1 + pb.ioff, i2 = e / pb.n1 + pb.ioff;
-    const int64_t x = bc_index(i1 + (a1 - Q1 + 1), nx, pb.bc);
-    const int64_t y = bc_index(i2 + (a2 - Q2 + 1), ny, pb.bc);
-    double u[NV];
+  const Slice sl(st, cls);
+  for (int64_t base = sl.lo; base < sl.hi; base += CPB) {
+    {
+      const bool valid = inblk && base + g < sl.hi;
+      const int32_t e = valid ? sl.items[base + g] : 0;
+      const int64_t i1 = e % pb.n1 + pb.ioff, i2 = e / pb.n1 + pb.ioff;
+      const int64_t x = bc_index(i1 + (a1 - Q1 + 1), nx, pb.bc);
+      const int64_t y = bc_index(i2 + (a2 - Q2 + 1), ny, pb.bc);
+      double u[NV];
 #pragma unroll
-    for (int c = 0; c < NV; ++c) u[c] = valid ? st.u[(c * ny + y) * nx + x] : 1.0;
-    double f0[NV], g0[NV], F[NV], Gv[NV];
-    flux2d<FLUX, NV>(pb.ph, u, f0, g0);
-    if constexpr (Q1 == Q2) {
-      corner_pass<FLUX, NV, Q1, Q2, Q1, true, true>(pb.ph, lamx, lamy, u, f0, g0, g1x, g1y, xs, buf, tid, g * L,
-                                                    a1, a2, lead, F, Gv);
-    } else {
-      corner_pass<FLUX, NV, Q1, Q2, Q1, true, false>(pb.ph, lamx, lamy, u, f0, g0, g1x, g1y, xs, buf, tid, g * L,
-                                                     a1, a2, lead, F, Gv);
-      corner_pass<FLUX, NV, Q1, Q2, Q2, false, true>(pb.ph, lamx, lamy, u, f0, g0, g1x, g1y, xs, buf, tid, g * L,
-                                                     a1, a2, lead, F, Gv);
-    }
-    if (lead) {
-      const bool needF = i2 >= 0, needG = i1 >= 0;
-      if constexpr (Q1 == 1) {
-        if (needF) {   // 2D FL-CAT2 in x (Sec. 4)
-          const int64_t ex = i2 * pb.nIx + (i1 - pb.ioff);
-          const double psi = st.psix[ex], al = st.alx[ex];
-          const int64_t xr = bc_index(i1 + 1, nx, pb.bc);
-          double uR[NV], fR[NV], gR[NV];
+      for (int c = 0; c < NV; ++c) u[c] = valid ? st.u[(c * ny + y) * nx + x] : 1.0;
+      double f0[NV], g0[NV];
+      flux2d<FLUX, NV>(pb.ph, u, f0, g0);
+      double acc[2] = {0.0, 0.0};
+      if constexpr (Q1 == Q2) {
+        corner_pass<FLUX, NV, Q1, Q2, Q1, true, true>(pb.ph, lamx, lamy, u, f0, g0, g1x, g1y, xs[0], xs[1],
+                                                      STRIDE, buf, tid, g * L, a1, a2, nd, valid, acc);
+      } else {
+        corner_pass<FLUX, NV, Q1, Q2, Q1, true, false>(pb.ph, lamx, lamy, u, f0, g0, g1x, g1y, xs[0], xs[1],
+                                                       STRIDE, buf, tid, g * L, a1, a2, nd, valid, acc);
+        corner_pass<FLUX, NV, Q1, Q2, Q2, false, true>(pb.ph, lamx, lamy, u, f0, g0, g1x, g1y, xs[0], xs[1],
+                                                       STRIDE, buf, tid, g * L, a1, a2, nd, valid, acc);
+      }
+      // finish and store the assembled components
 #pragma unroll
-          for (int c = 0; c < NV; ++c) uR[c] = st.u[(c * ny + y) * nx + xr];
-          flux2d<FLUX, NV>(pb.ph, uR, fR, gR);
+      for (int tk = 0; tk < 2; ++tk) {
+        const int task = nd + tk * L;
+        if (!valid || task >= 2 * NV) continue;
+        const bool isG = task >= NV;
+        const int c = isG ? task - NV : task;
+        const bool need = isG ? (i1 >= 0) : (i2 >= 0);   // transmissive ghost corners need one flux only
+        if (!need) continue;
+        double v = acc[tk];
+        if ((!isG && Q1 == 1) || (isG && Q2 == 1)) {
+          // 2D FL-CAT2 (Sec. 4): psi^1 CAT2 + (1 - psi^1) Rusanov in this direction
+          const int64_t x0 = bc_index(i1, nx, pb.bc), y0 = bc_index(i2, ny, pb.bc);
+          const int64_t xr = isG ? x0 : bc_index(i1 + 1, nx, pb.bc);
+          const int64_t yr = isG ? bc_index(i2 + 1, ny, pb.bc) : y0;
+          const int64_t ei = isG ? (i2 - pb.ioff) * nx + i1 : i2 * pb.nIx + (i1 - pb.ioff);
+          const double psi = isG ? st.psiy[ei] : st.psix[ei];
+          const double al = isG ? st.aly[ei] : st.alx[ei];
+          double uL[NV], uR[NV], fL[NV], gL[NV], fR[NV], gR[NV];
 #pragma unroll
-          for (int c = 0; c < NV; ++c) {
-            const double flo = 0.5 * (f0[c] + fR[c]) - (0.5 * al) * (uR[c] - u[c]);
-            F[c] = psi * F[c] + (1.0 - psi) * flo;
+          for (int cc = 0; cc < NV; ++cc) {
+            uL[cc] = st.u[(cc * ny + y0) * nx + x0];
+            uR[cc] = st.u[(cc * ny + yr) * nx + xr];
           }
-        }
-      }
-      if constexpr (Q2 == 1) {
-        if (needG) {   // 2D FL-CAT2 in y
-          const int64_t ey = (i2 - pb.ioff) * nx + i1;
-          const double psi = st.psiy[ey], al = st.aly[ey];
-          const int64_t yr = bc_index(i2 + 1, ny, pb.bc);
-          double uR[NV], fR[NV], gR[NV];
-#pragma unroll
-          for (int c = 0; c < NV; ++c) uR[c] = st.u[(c * ny + yr) * nx + x];
+          flux2d<FLUX, NV>(pb.ph, uL, fL, gL);
           flux2d<FLUX, NV>(pb.ph, uR, fR, gR);
+          double ul = 0.0, ur = 0.0, hl = 0.0, hr = 0.0;
 #pragma unroll
-          for (int c = 0; c < NV; ++c) {
-            const double glo = 0.5 * (g0[c] + gR[c]) - (0.5 * al) * (uR[c] - u[c]);
-            Gv[c] = psi * Gv[c] + (1.0 - psi) * glo;
-          }
+          for (int cc = 0; cc < NV; ++cc)
+            if (cc == c) {
+              ul = uL[cc];
+              ur = uR[cc];
+              hl = isG ? gL[cc] : fL[cc];
+              hr = isG ? gR[cc] : fR[cc];
+            }
+          const double lo = 0.5 * (hl + hr) - (0.5 * al) * (ur - ul);
+          v = psi * v + (1.0 - psi) * lo;
         }
-      }
-      if (needF) {
-#pragma unroll
-        for (int c = 0; c < NV; ++c) st.Fx[(c * ny + i2) * pb.nIx + (i1 - pb.ioff)] = F[c];
-      }
-      if (needG) {
-#pragma unroll
-        for (int c = 0; c < NV; ++c) st.Gy[(c * pb.nIy + (i2 - pb.ioff)) * nx + i1] = Gv[c];
+        if (isG) st.Gy[(c * pb.nIy + (i2 - pb.ioff)) * nx + i1] = v;
+        else st.Fx[(c * ny + i2) * pb.nIx + (i1 - pb.ioff)] = v;
       }
     }
   }
@@ -631,8 +733,19 @@ __global__ __launch_bounds__(BLOCK) void k_max_speed(KProb pb, const double* __r
     m0 = fmax(m0, __shfl_xor(m0, off));
     m1 = fmax(m1, __shfl_xor(m1, off));
   }
-  // the bit patterns of non-negative doubles order like the values
+  __shared__ double red[2][BLOCK / 64];
   if (__lane_id() == 0) {
+    red[0][threadIdx.x >> 6] = m0;
+    red[1][threadIdx.x >> 6] = m1;
+  }
+  __syncthreads();
+  // one atomic per block; the bit patterns of non-negative doubles order like the values
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 1; w < BLOCK / 64; ++w) {
+      m0 = fmax(m0, red[0][w]);
+      m1 = fmax(m1, red[1][w]);
+    }
     atomicMax(&smax[0], (unsigned long long)__double_as_longlong(m0));
     if (DIM == 2) atomicMax(&smax[1], (unsigned long long)__double_as_longlong(m1));
   }
@@ -651,53 +764,70 @@ __global__ void k_cfl_dt(int dim, double dx, double dy, const double* smax, doub
 }
 
 // ================================================================ launchers
-int flux_grid(int64_t nitems, int per_block, int cap) {
-  int64_t b = (nitems + per_block - 1) / per_block;
-  if (b > cap) b = cap;
-  if (b < 1) b = 1;
-  b = (b + NXCD - 1) / NXCD * NXCD;   // whole XCD rounds
-  return (int)b;
-}
-
 #define ACAT_CHECK_LAUNCH()                  \
   do {                                       \
     hipError_t e_ = hipGetLastError();       \
     if (e_ != hipSuccess) return e_;         \
   } while (0)
 
+int num_cus() {
+  static int n = 0;
+  if (!n) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+      n = 256;
+  }
+  return n;
+}
+
+// Persistent grid of a tile-walking kernel: enough blocks to fill every CU
+// at the kernel's occupancy (cap > 0 overrides), never more than the tiles,
+// a multiple of the XCD count.
+template <typename K>
+int persistent_grid(K kernel, int64_t nitems, int cap) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, BLOCK, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  int64_t b = cap > 0 ? cap : (int64_t)per_cu * num_cus();
+  const int64_t ntiles = (nitems + BLOCK - 1) / BLOCK;
+  if (b > ntiles) b = ntiles;
+  b = (b + NXCD - 1) / NXCD * NXCD;
+  return (int)(b < NXCD ? NXCD : b);
+}
+
+template <int FLUX, int NV, int P, int p>
+hipError_t launch_class1d(const KProb& pb, const KStep& st, int cap, hipStream_t s) {
+  if constexpr (p <= P) {
+    static const char* names[5] = {"", "flux1d_p1", "flux1d_p2", "flux1d_p3", "flux1d_p4"};
+    auto kern = k_flux1d<FLUX, NV, p>;
+    const int grid = persistent_grid(kern, pb.nIx, cap);
+    {
+      ProfScope ps(names[p], s);
+      kern<<<grid, BLOCK, 0, s>>>(pb, st);
+    }
+    ACAT_CHECK_LAUNCH();
+  }
+  return hipSuccess;
+}
+
 template <int FLUX, int NV, int P>
 hipError_t step1d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s) {
-  {
-    ProfScope ps("zero", s);
-    k_zero_i32<<<1, 64, 0, s>>>(st.counts, MAX_CLASSES);
-  }
-  ACAT_CHECK_LAUNCH();
   const int64_t nI = pb.nIx;
+  const int cblocks = (int)((nI + BLOCK - 1) / BLOCK);
   {
     ProfScope ps("classify1d", s);
-    k_classify1d<FLUX, NV, P><<<(unsigned)((nI + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st);
+    k_classify1d<FLUX, NV, P><<<cblocks, BLOCK, 0, s>>>(pb, st);
   }
   ACAT_CHECK_LAUNCH();
-  {
-    ProfScope ps("flux1d_p1", s);
-    k_flux1d<FLUX, NV, 1><<<flux_grid(nI, BLOCK / 2, cap), BLOCK, 0, s>>>(pb, st);
-  }
+  k_scan_hist<<<P, BLOCK, 0, s>>>(st.hist, cblocks, st.offs, st.counts);
   ACAT_CHECK_LAUNCH();
-  if constexpr (P >= 2) {
-    ProfScope ps("flux1d_p2", s);
-    k_flux1d<FLUX, NV, 2><<<flux_grid(nI, BLOCK / 4, cap), BLOCK, 0, s>>>(pb, st);
-  }
+  k_scatter<P><<<cblocks, BLOCK, 0, s>>>(st.ordx, 1, nI, cblocks, st.offs, st.counts, st.list);
   ACAT_CHECK_LAUNCH();
-  if constexpr (P >= 3) {
-    ProfScope ps("flux1d_p3", s);
-    k_flux1d<FLUX, NV, 3><<<flux_grid(nI, BLOCK / 6, cap), BLOCK, 0, s>>>(pb, st);
-  }
-  ACAT_CHECK_LAUNCH();
-  if constexpr (P >= 4) {
-    ProfScope ps("flux1d_p4", s);
-    k_flux1d<FLUX, NV, 4><<<flux_grid(nI, BLOCK / 8, cap), BLOCK, 0, s>>>(pb, st);
-  }
-  ACAT_CHECK_LAUNCH();
+  hipError_t e;
+  if ((e = launch_class1d<FLUX, NV, P, 1>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class1d<FLUX, NV, P, 2>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class1d<FLUX, NV, P, 3>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class1d<FLUX, NV, P, 4>(pb, st, cap, s)) != hipSuccess) return e;
   {
     ProfScope ps("update1d", s);
     k_update1d<FLUX, NV><<<(unsigned)((pb.nx + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st);
@@ -707,16 +837,17 @@ hipError_t step1d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s)
 }
 
 template <int FLUX, int NV, int P, int Q1, int Q2>
-hipError_t launch_class2d(const KProb& pb, const KStep& st, int64_t ncorner, int cap, hipStream_t s) {
+hipError_t launch_class2d(const KProb& pb, const KStep& st, int cap, hipStream_t s) {
   if constexpr (Q1 <= P && Q2 <= P) {
-    constexpr int L = 4 * Q1 * Q2;
     static const char* names[4][4] = {{"", "", "", ""},
                                       {"", "flux2d_q11", "flux2d_q12", "flux2d_q13"},
                                       {"", "flux2d_q21", "flux2d_q22", "flux2d_q23"},
                                       {"", "flux2d_q31", "flux2d_q32", "flux2d_q33"}};
+    auto kern = k_flux2d<FLUX, NV, Q1, Q2>;
+    const int grid = persistent_grid(kern, pb.n1 * pb.n2, cap);
     {
       ProfScope ps(names[Q1][Q2], s);
-      k_flux2d<FLUX, NV, Q1, Q2><<<flux_grid(ncorner, BLOCK / L, cap), BLOCK, 0, s>>>(pb, st);
+      kern<<<grid, BLOCK, 0, s>>>(pb, st);
     }
     ACAT_CHECK_LAUNCH();
   }
@@ -725,27 +856,27 @@ hipError_t launch_class2d(const KProb& pb, const KStep& st, int64_t ncorner, int
 
 template <int FLUX, int NV, int P>
 hipError_t step2d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s) {
-  {
-    ProfScope ps("zero", s);
-    k_zero_i32<<<1, 64, 0, s>>>(st.counts, MAX_CLASSES);
-  }
-  ACAT_CHECK_LAUNCH();
   const int64_t nc = pb.n1 * pb.n2;
+  const int cblocks = (int)((nc + BLOCK - 1) / BLOCK);
   {
     ProfScope ps("classify2d", s);
-    k_classify2d<FLUX, NV, P><<<(unsigned)((nc + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st);
+    k_classify2d<FLUX, NV, P><<<cblocks, BLOCK, 0, s>>>(pb, st);
   }
   ACAT_CHECK_LAUNCH();
+  k_scan_hist<<<P * P, BLOCK, 0, s>>>(st.hist, cblocks, st.offs, st.counts);
+  ACAT_CHECK_LAUNCH();
+  k_scatter<P * P><<<cblocks, BLOCK, 0, s>>>(st.cls, 0, nc, cblocks, st.offs, st.counts, st.list);
+  ACAT_CHECK_LAUNCH();
   hipError_t e;
-  if ((e = launch_class2d<FLUX, NV, P, 1, 1>(pb, st, nc, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 1, 2>(pb, st, nc, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 2, 1>(pb, st, nc, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 2, 2>(pb, st, nc, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 1, 3>(pb, st, nc, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 3, 1>(pb, st, nc, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 2, 3>(pb, st, nc, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 3, 2>(pb, st, nc, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 3, 3>(pb, st, nc, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 1, 1>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 1, 2>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 2, 1>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 2, 2>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 1, 3>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 3, 1>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 2, 3>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 3, 2>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 3, 3>(pb, st, cap, s)) != hipSuccess) return e;
   {
     ProfScope ps("update2d", s);
     k_update2d<FLUX, NV><<<(unsigned)((pb.nx * pb.ny + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st);
@@ -754,12 +885,10 @@ hipError_t step2d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s)
   return hipSuccess;
 }
 
-constexpr int kFluxBlockCap = 256 * 8;   // persistent grid: at most 8 blocks per CU
-
 }  // namespace
 
 hipError_t launch_step_1d(const KProb& pb, const KStep& st, int grid_blocks, hipStream_t s) {
-  const int cap = grid_blocks > 0 ? grid_blocks : kFluxBlockCap;
+  const int cap = grid_blocks;
   if (pb.flux == EUL) {
     switch (pb.P) {
       case 1: return step1d_impl<EUL, 3, 1>(pb, st, cap, s);
@@ -786,7 +915,7 @@ hipError_t launch_step_1d(const KProb& pb, const KStep& st, int grid_blocks, hip
 }
 
 hipError_t launch_step_2d(const KProb& pb, const KStep& st, int grid_blocks, hipStream_t s) {
-  const int cap = grid_blocks > 0 ? grid_blocks : kFluxBlockCap;
+  const int cap = grid_blocks;
   if (pb.flux == EUL) {
     switch (pb.P) {
       case 1: return step2d_impl<EUL, 4, 1>(pb, st, cap, s);
@@ -810,7 +939,7 @@ hipError_t launch_max_speed(const KProb& pb, const double* u, double* smax, hipS
   ACAT_CHECK_LAUNCH();
   const int64_t n = pb.nx * (pb.dim == 2 ? pb.ny : 1);
   int64_t blocks = (n + BLOCK - 1) / BLOCK;
-  if (blocks > 2048) blocks = 2048;
+  if (blocks > 4 * num_cus()) blocks = 4 * num_cus();
   const unsigned gb = (unsigned)blocks;
   if (pb.dim == 1) {
     if (pb.flux == EUL) k_max_speed<EUL, 1, 3><<<gb, BLOCK, 0, s>>>(pb, u, sm);
