@@ -417,13 +417,14 @@ void cat_flux_1d(const oracle_problem& pb, int p, const T (*u)[VMAX], double lam
       }
     }
   }
-  // F = sum_{k=1}^{2p} 1/k! sum_l eta_l Fh^{k-1}_l
+  // F = sum_{k=1}^{2p} 1/k! sum_l eta_l Fh^{k-1}_l, summed node by node:
+  // F = sum_l eta_l (sum_k Fh^{k-1}_l / k!)
   for (int c = 0; c < nv; ++c) {
     T s = 0.0;
-    for (int k = 1; k <= 2 * p; ++k) {
+    for (int a = 0; a < nn; ++a) {
       T t = 0.0;
-      for (int a = 0; a < nn; ++a) t = mad(Tb.eta[p][a], Fh[k - 1][a][c], t);
-      s = mad(Tb.invfact[k], t, s);
+      for (int k = 1; k <= 2 * p; ++k) t = mad(Tb.invfact[k], Fh[k - 1][a][c], t);
+      s = mad(Tb.eta[p][a], t, s);
     }
     F[c] = s;
   }
@@ -581,26 +582,28 @@ void cat_corner_2d(const oracle_problem& pb, int q1, int q2, int qt, const T (*u
         }
       }
   }
+  // F = sum_k 1/k! sum_l eta_l Fh^{k-1}_(l,0), summed node by node (row j2 = 0)
   if (F) {
-    const int a2 = q2 - 1;   // row j2 = 0
+    const int a2 = q2 - 1;
     for (int c = 0; c < nv; ++c) {
       T s = 0.0;
-      for (int k = 1; k <= nt; ++k) {
+      for (int a = 0; a < n1; ++a) {
         T t = 0.0;
-        for (int a = 0; a < n1; ++a) t = mad(Tb.eta[q1][a], Fh[k - 1][a][a2][c], t);
-        s = mad(Tb.invfact[k], t, s);
+        for (int k = 1; k <= nt; ++k) t = mad(Tb.invfact[k], Fh[k - 1][a][a2][c], t);
+        s = mad(Tb.eta[q1][a], t, s);
       }
       F[c] = s;
     }
   }
+  // G likewise on column j1 = 0
   if (G) {
-    const int a1 = q1 - 1;   // column j1 = 0
+    const int a1 = q1 - 1;
     for (int c = 0; c < nv; ++c) {
       T s = 0.0;
-      for (int k = 1; k <= nt; ++k) {
+      for (int a = 0; a < n2; ++a) {
         T t = 0.0;
-        for (int a = 0; a < n2; ++a) t = mad(Tb.eta[q2][a], Gh[k - 1][a1][a][c], t);
-        s = mad(Tb.invfact[k], t, s);
+        for (int k = 1; k <= nt; ++k) t = mad(Tb.invfact[k], Gh[k - 1][a1][a][c], t);
+        s = mad(Tb.eta[q2][a], t, s);
       }
       G[c] = s;
     }
