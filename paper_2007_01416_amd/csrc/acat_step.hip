@@ -263,33 +263,21 @@ __global__ __launch_bounds__(BLOCK) void k_flux1d(KProb pb, KStep st) {
 #pragma unroll
       for (int c = 0; c < NV; ++c) u[c] = valid ? st.u[c * nx + node] : 1.0;
 
-      double fh0[NV], cur[NV];
+      double fh0[NV], cur[NV], S[NV];
       flux1d<FLUX, NV>(pb.ph, u, fh0);
+      // S = sum_k Fh^{k-1} / k! at this node (the CAT flux, Sec. 2.2, summed node by node)
 #pragma unroll
-      for (int c = 0; c < NV; ++c) cur[c] = fh0[c];
-      // assembly of the flux: lane a < NV sums component a (and a + L, ...)
-      double F0 = 0.0, F1 = 0.0;
+      for (int c = 0; c < NV; ++c) {
+        cur[c] = fh0[c];
+        S[c] = fma(TB.INVFACT[1], fh0[c], 0.0);
+      }
       double U[L][NV];   // U[l] = dt^l u~^(l) at this node, l = 1 .. 2p-1
 #pragma unroll
-      for (int kk = 2; kk <= 2 * p + 1; ++kk) {
+      for (int kk = 2; kk <= 2 * p; ++kk) {
         // share Fh^{kk-2} of every node of the stencil
 #pragma unroll
         for (int c = 0; c < NV; ++c) xs[buf][c][slot] = cur[c];
         __syncthreads();
-        // F += (1/(kk-1)!) sum_j eta_j Fh^{kk-2}_j  (the CAT flux, Sec. 2.2)
-        if (valid && a < NV) {
-          double tsum = 0.0;
-#pragma unroll
-          for (int l = 0; l < L; ++l) tsum = fma(TB.ETA[p][l], xs[buf][a][g * SL + l], tsum);
-          F0 = fma(TB.INVFACT[kk - 1], tsum, F0);
-        }
-        if (NV > L && valid && a + L < NV) {
-          double tsum = 0.0;
-#pragma unroll
-          for (int l = 0; l < L; ++l) tsum = fma(TB.ETA[p][l], xs[buf][(a + L) % NV][g * SL + l], tsum);
-          F1 = fma(TB.INVFACT[kk - 1], tsum, F1);
-        }
-        if (kk == 2 * p + 1) break;
         // U^{kk-1} = -lambda * (spatial derivative of Fh^{kk-2} at this node)
 #pragma unroll
         for (int c = 0; c < NV; ++c) {
@@ -326,9 +314,25 @@ __global__ __launch_bounds__(BLOCK) void k_flux1d(KProb pb, KStep st) {
           for (int c = 0; c < NV; ++c) nxt[c] = fma(TB.GT[p][kk - 1][ri], ph[c], nxt[c]);
         }
 #pragma unroll
-        for (int c = 0; c < NV; ++c) cur[c] = nxt[c];
+        for (int c = 0; c < NV; ++c) {
+          cur[c] = nxt[c];
+          S[c] = fma(TB.INVFACT[kk], nxt[c], S[c]);
+        }
       }
-      buf ^= 1;   // the assembly above may still read the last buffer
+      // F_c = sum_j eta_j S_j,c on lane a = c (and a + L when NV > L)
+#pragma unroll
+      for (int c = 0; c < NV; ++c) xs[buf][c][slot] = S[c];
+      __syncthreads();
+      double F0 = 0.0, F1 = 0.0;
+      if (valid && a < NV) {
+#pragma unroll
+        for (int l = 0; l < L; ++l) F0 = fma(TB.ETA[p][l], xs[buf][a][g * SL + l], F0);
+        if (NV > L && a + L < NV) {
+#pragma unroll
+          for (int l = 0; l < L; ++l) F1 = fma(TB.ETA[p][l], xs[buf][(a + L) % NV][g * SL + l], F1);
+        }
+      }
+      buf ^= 1;   // the assembly above may still read this buffer
       if (valid && a < NV) {
         for (int task = 0; task < 2; ++task) {
           const int c = a + task * L;
@@ -492,56 +496,33 @@ struct Xch {
 };
 
 // One recursion over the rectangle J_Q1 x J_Q2 with time nodes J_QT
-// (Taylor order 2 QT).  Each lane is one node (a1, a2).  The flux F (row
-// j2 = 0, DOF) and G (column j1 = 0, DOG) are assembled on 2 NV lanes, one
-// component each (task = nd for F, nd - NV for G; lanes with L < 2 NV take
-// a second task nd + L).  Same fixed rounding as the 1D kernel.
+// (Taylor order 2 QT).  Each lane is one node (a1, a2) and accumulates the
+// series SF = sum_k Fh^{k-1} / k! (DOF) and SG = sum_k Gh^{k-1} / k! (DOG)
+// of its node; the fluxes are the eta-weighted sums of SF over row j2 = 0
+// and of SG over column j1 = 0.  Same fixed rounding as the 1D kernel.
 template <int FLUX, int NV, int Q1, int Q2, int QT, bool DOF, bool DOG>
 __device__ __forceinline__ void corner_pass(const Phys& ph, double lamx, double lamy, const double (&u)[NV],
                                             const double (&f0)[NV], const double (&g0)[NV],
                                             const double (&g1x)[2 * Q1], const double (&g1y)[2 * Q2],
-                                            double2* xsb0, double2* xsb1, int stride, int& buf, int tid,
-                                            int gbase, int a1, int a2, int nd, bool valid, double (&acc)[2]) {
-  constexpr int N1 = 2 * Q1, N2 = 2 * Q2, L = N1 * N2;
+                                            double2* xsb0, double2* xsb1, int stride, int& buf, int slot,
+                                            int gbase, int a1, int a2, double (&SF)[NV], double (&SG)[NV]) {
+  constexpr int N1 = 2 * Q1;
+  constexpr int N2 = 2 * Q2;
   double fc[NV], gc[NV];
 #pragma unroll
   for (int c = 0; c < NV; ++c) {
     fc[c] = f0[c];
     gc[c] = g0[c];
+    if (DOF) SF[c] = fma(TB.INVFACT[1], f0[c], 0.0);
+    if (DOG) SG[c] = fma(TB.INVFACT[1], g0[c], 0.0);
   }
-  // tasks of this lane: task < NV is F component task, else G component task - NV
-  const int task0 = nd, task1 = nd + L;
-  const bool do0 = valid && task0 < 2 * NV && ((task0 < NV) ? DOF : DOG);
-  const bool do1 = valid && task1 < 2 * NV && ((task1 < NV) ? DOF : DOG);
-  if (do0) acc[0] = 0.0;
-  if (do1) acc[1] = 0.0;
   double U[2 * QT][NV];
 #pragma unroll
-  for (int kk = 2; kk <= 2 * QT + 1; ++kk) {
+  for (int kk = 2; kk <= 2 * QT; ++kk) {
     double2* xsw = buf ? xsb1 : xsb0;
-    Xch<NV>::put(xsw, stride, tid, fc, gc);
+    Xch<NV>::put(xsw, stride, slot, fc, gc);
     __syncthreads();
     const double* xr = reinterpret_cast<const double*>(xsw);
-    // assembly: acc += (1/(kk-1)!) sum_l eta_l Fh^{kk-2}_(l,0)   (or Gh on column 0)
-#pragma unroll
-    for (int tk = 0; tk < 2; ++tk) {
-      const int task = tk == 0 ? task0 : task1;
-      if (!(tk == 0 ? do0 : do1)) continue;
-      const bool isG = task >= NV;
-      const int c = isG ? task - NV : task;
-      double tsum = 0.0;
-      if (!isG) {
-#pragma unroll
-        for (int l = 0; l < N1; ++l)
-          tsum = fma(TB.ETA[Q1][l], Xch<NV>::get(xr, stride, gbase + (Q2 - 1) * N1 + l, c, false), tsum);
-      } else {
-#pragma unroll
-        for (int l = 0; l < N2; ++l)
-          tsum = fma(TB.ETA[Q2][l], Xch<NV>::get(xr, stride, gbase + l * N1 + (Q1 - 1), c, true), tsum);
-      }
-      acc[tk] = fma(TB.INVFACT[kk - 1], tsum, acc[tk]);
-    }
-    if (kk == 2 * QT + 1) break;
     // U^{kk-1} = -lamx d_x Fh^{kk-2} - lamy d_y Gh^{kk-2} at this node
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
@@ -590,11 +571,10 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, double lamx, double 
     for (int c = 0; c < NV; ++c) {
       fc[c] = nf[c];
       gc[c] = ng[c];
+      if (DOF) SF[c] = fma(TB.INVFACT[kk], nf[c], SF[c]);
+      if (DOG) SG[c] = fma(TB.INVFACT[kk], ng[c], SG[c]);
     }
   }
-  // the assembly may still read the buffer of the final exchange: the next
-  // writer (a second pass or the next round) must use the other one
-  buf ^= 1;
 }
 
 // Fluxes of the corners of order class (Q1, Q2) (Sec. 4; rectangle J_Q1 x J_Q2).
@@ -635,16 +615,42 @@ __global__ __launch_bounds__(BLOCK) void k_flux2d(KProb pb, KStep st) {
       for (int c = 0; c < NV; ++c) u[c] = valid ? st.u[(c * ny + y) * nx + x] : 1.0;
       double f0[NV], g0[NV];
       flux2d<FLUX, NV>(pb.ph, u, f0, g0);
-      double acc[2] = {0.0, 0.0};
+      double SF[NV], SG[NV];
+      const int slot = g * L + nd;
       if constexpr (Q1 == Q2) {
         corner_pass<FLUX, NV, Q1, Q2, Q1, true, true>(pb.ph, lamx, lamy, u, f0, g0, g1x, g1y, xs[0], xs[1],
-                                                      STRIDE, buf, tid, g * L, a1, a2, nd, valid, acc);
+                                                      STRIDE, buf, slot, g * L, a1, a2, SF, SG);
       } else {
         corner_pass<FLUX, NV, Q1, Q2, Q1, true, false>(pb.ph, lamx, lamy, u, f0, g0, g1x, g1y, xs[0], xs[1],
-                                                       STRIDE, buf, tid, g * L, a1, a2, nd, valid, acc);
+                                                       STRIDE, buf, slot, g * L, a1, a2, SF, SG);
         corner_pass<FLUX, NV, Q1, Q2, Q2, false, true>(pb.ph, lamx, lamy, u, f0, g0, g1x, g1y, xs[0], xs[1],
-                                                       STRIDE, buf, tid, g * L, a1, a2, nd, valid, acc);
+                                                       STRIDE, buf, slot, g * L, a1, a2, SF, SG);
       }
+      // F_c = sum_l eta_l SF_(l,0),c and G_c = sum_l eta_l SG_(0,l),c on 2 NV lanes
+      {
+        double2* xsw = buf ? xs[1] : xs[0];
+        Xch<NV>::put(xsw, STRIDE, slot, SF, SG);
+        __syncthreads();
+      }
+      const double* xr = reinterpret_cast<const double*>(buf ? xs[1] : xs[0]);
+      double acc[2] = {0.0, 0.0};
+#pragma unroll
+      for (int tk = 0; tk < 2; ++tk) {
+        const int task = nd + tk * L;
+        if (!valid || task >= 2 * NV) continue;
+        const bool isG = task >= NV;
+        const int c = isG ? task - NV : task;
+        double t = 0.0;
+        if (!isG) {
+#pragma unroll
+          for (int l = 0; l < N1; ++l) t = fma(TB.ETA[Q1][l], Xch<NV>::get(xr, STRIDE, g * L + (Q2 - 1) * N1 + l, c, false), t);
+        } else {
+#pragma unroll
+          for (int l = 0; l < N2; ++l) t = fma(TB.ETA[Q2][l], Xch<NV>::get(xr, STRIDE, g * L + l * N1 + (Q1 - 1), c, true), t);
+        }
+        acc[tk] = t;
+      }
+      buf ^= 1;   // the assembly may still read this buffer
       // finish and store the assembled components
 #pragma unroll
       for (int tk = 0; tk < 2; ++tk) {
