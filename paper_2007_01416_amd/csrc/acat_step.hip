@@ -257,8 +257,8 @@ __global__ __launch_bounds__(BLOCK) void k_flux1d(KProb pb, KStep st) {
     {
       const bool valid = inblk && base + g < sl.hi;
       const int32_t k = valid ? sl.items[base + g] : 0;
-      const int64_t i = k + pb.ioff;
-      const int64_t node = bc_index(i + (a - p + 1), nx, pb.bc);
+      const int i = k + (int)pb.ioff;
+      const int node = bc_index32(i + (a - p + 1), (int)nx, pb.bc);
       double u[NV];
 #pragma unroll
       for (int c = 0; c < NV; ++c) u[c] = valid ? st.u[c * nx + node] : 1.0;
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(BLOCK) void k_flux1d(KProb pb, KStep st) {
           if constexpr (p == 1) {
             // FL-CAT2 (Sec. 3.1): psi^1 CAT2 + (1 - psi^1) Rusanov
             const double psi = st.psix[k], al = st.alx[k];
-            const int64_t nl = bc_index(i, nx, pb.bc), nr = bc_index(i + 1, nx, pb.bc);
+            const int64_t nl = bc_index32(i, (int)nx, pb.bc), nr = bc_index32(i + 1, (int)nx, pb.bc);
             double uL[NV], uR[NV], fL[NV], fR[NV];
 #pragma unroll
             for (int cc = 0; cc < NV; ++cc) {
@@ -593,7 +593,9 @@ __global__ __launch_bounds__(BLOCK) void k_flux2d(KProb pb, KStep st) {
   const int cls = (Q1 - 1) * pb.P + (Q2 - 1);
   const double dt = step_dt(st);
   const double lamx = dt / pb.dx, lamy = dt / pb.dy;
-  const int64_t nx = pb.nx, ny = pb.ny, nc = pb.n1 * pb.n2;
+  const int64_t nx = pb.nx, ny = pb.ny, plane = pb.nx * pb.ny;
+  const int nx32 = (int)pb.nx, ny32 = (int)pb.ny, ioff = (int)pb.ioff;
+  const uint32_t n1u = (uint32_t)pb.n1;
 
   double g1x[N1], g1y[N2];
 #pragma unroll
@@ -607,12 +609,14 @@ __global__ __launch_bounds__(BLOCK) void k_flux2d(KProb pb, KStep st) {
     {
       const bool valid = inblk && base + g < sl.hi;
       const int32_t e = valid ? sl.items[base + g] : 0;
-      const int64_t i1 = e % pb.n1 + pb.ioff, i2 = e / pb.n1 + pb.ioff;
-      const int64_t x = bc_index(i1 + (a1 - Q1 + 1), nx, pb.bc);
-      const int64_t y = bc_index(i2 + (a2 - Q2 + 1), ny, pb.bc);
+      const uint32_t eq = (uint32_t)e / n1u;
+      const int i2 = (int)eq + ioff, i1 = (int)((uint32_t)e - eq * n1u) + ioff;
+      const int x = bc_index32(i1 + (a1 - Q1 + 1), nx32, pb.bc);
+      const int y = bc_index32(i2 + (a2 - Q2 + 1), ny32, pb.bc);
+      const double* un = st.u + ((int64_t)y * nx + x);
       double u[NV];
 #pragma unroll
-      for (int c = 0; c < NV; ++c) u[c] = valid ? st.u[(c * ny + y) * nx + x] : 1.0;
+      for (int c = 0; c < NV; ++c) u[c] = valid ? un[c * plane] : 1.0;
       double f0[NV], g0[NV];
       flux2d<FLUX, NV>(pb.ph, u, f0, g0);
       double SF[NV], SG[NV];
@@ -663,10 +667,10 @@ __global__ __launch_bounds__(BLOCK) void k_flux2d(KProb pb, KStep st) {
         double v = acc[tk];
         if ((!isG && Q1 == 1) || (isG && Q2 == 1)) {
           // 2D FL-CAT2 (Sec. 4): psi^1 CAT2 + (1 - psi^1) Rusanov in this direction
-          const int64_t x0 = bc_index(i1, nx, pb.bc), y0 = bc_index(i2, ny, pb.bc);
-          const int64_t xr = isG ? x0 : bc_index(i1 + 1, nx, pb.bc);
-          const int64_t yr = isG ? bc_index(i2 + 1, ny, pb.bc) : y0;
-          const int64_t ei = isG ? (i2 - pb.ioff) * nx + i1 : i2 * pb.nIx + (i1 - pb.ioff);
+          const int64_t x0 = bc_index32(i1, nx32, pb.bc), y0 = bc_index32(i2, ny32, pb.bc);
+          const int64_t xr = isG ? x0 : bc_index32(i1 + 1, nx32, pb.bc);
+          const int64_t yr = isG ? bc_index32(i2 + 1, ny32, pb.bc) : y0;
+          const int64_t ei = isG ? (int64_t)(i2 - ioff) * nx + i1 : (int64_t)i2 * pb.nIx + (i1 - ioff);
           const double psi = isG ? st.psiy[ei] : st.psix[ei];
           const double al = isG ? st.aly[ei] : st.alx[ei];
           double uL[NV], uR[NV], fL[NV], gL[NV], fR[NV], gR[NV];
@@ -689,8 +693,8 @@ __global__ __launch_bounds__(BLOCK) void k_flux2d(KProb pb, KStep st) {
           const double lo = 0.5 * (hl + hr) - (0.5 * al) * (ur - ul);
           v = psi * v + (1.0 - psi) * lo;
         }
-        if (isG) st.Gy[(c * pb.nIy + (i2 - pb.ioff)) * nx + i1] = v;
-        else st.Fx[(c * ny + i2) * pb.nIx + (i1 - pb.ioff)] = v;
+        if (isG) st.Gy[((int64_t)c * pb.nIy + (i2 - ioff)) * nx + i1] = v;
+        else st.Fx[((int64_t)c * ny + i2) * pb.nIx + (i1 - ioff)] = v;
       }
     }
   }

@@ -36,6 +36,21 @@ __device__ __forceinline__ void flux1d(const Phys& ph, const double (&u)[NV], do
   }
 }
 
+// 1/x, correctly rounded, for |x| in [2^-700, 2^700]: the compiler's IEEE
+// division sequence (reciprocal estimate, two Newton steps, residual
+// correction) without its exponent scaling and special-case fix-up, which
+// are identities in that range.  (Outside it, e.g. x = 0, the result is not
+// the IEEE one; such densities are non-physical.)
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  const double rem = fma(-x, r, 1.0);
+  return fma(rem, r, r);
+}
+
 // x- and y-direction fluxes of a 2D law at one state (shared primitives)
 template <int FLUX, int NV>
 __device__ __forceinline__ void flux2d(const Phys& ph, const double (&u)[NV], double (&f)[NV], double (&g)[NV]) {
@@ -47,7 +62,7 @@ __device__ __forceinline__ void flux2d(const Phys& ph, const double (&u)[NV], do
     }
   } else {
     static_assert(FLUX == EUL && NV == 4, "2D Euler has 4 conserved variables");
-    const double ir = 1.0 / u[0];
+    const double ir = recip(u[0]);
     const double v = u[1] * ir;
     const double w = u[2] * ir;
     const double p = ph.gm1 * (u[3] - 0.5 * (u[1] * v + u[2] * w));
@@ -99,6 +114,12 @@ __device__ __forceinline__ bool physical(const Phys& ph, const double (&u)[NV]) 
 // at most max(P, 2) < n cells outside the grid): periodic wrap or
 // transmissive zeroth-order extrapolation (clamp).
 __device__ __forceinline__ int64_t bc_index(int64_t i, int64_t n, int bc) {
+  if (bc == PERIODIC) return i < 0 ? i + n : (i >= n ? i - n : i);
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// 32-bit form of bc_index for per-item index math (every extent is below 2^31).
+__device__ __forceinline__ int bc_index32(int i, int n, int bc) {
   if (bc == PERIODIC) return i < 0 ? i + n : (i >= n ? i - n : i);
   return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
