@@ -126,6 +126,39 @@ acat_status acat_max_wave_speed(const acat_problem* prob, const double* u, doubl
 acat_status acat_cfl_dt(const acat_problem* prob, const double* smax_dev, double cfl, double t_final,
                         double* t_dev, double* dt_dev, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Batched step: nprob independent 1D problems with one flux, each with its
+ * own cell count n[b], largest half-width P[b], boundary bc[b], spacing
+ * dx[b] and time step dt[b], advanced together (one classification launch,
+ * one persistent launch per order class over all problems).  Per problem
+ * the result equals acat_step bit for bit.
+ *   States: SoA over the concatenated cells, u[var][coff_b + i] with
+ *   coff_b = n[0] + ... + n[b-1] (total C cells: arrays of nvar * C).
+ * The descriptor is a host struct of host arrays; acat_batch_init copies
+ * it into the workspace once (synchronously); every later call takes the
+ * same descriptor and workspace.
+ * --------------------------------------------------------------------- */
+typedef struct {
+  int32_t nvar;         /* as in acat_problem (1D)                             */
+  int32_t flux;
+  double gamma, ax;
+  double eps, theta;
+  int32_t nprob;        /* >= 1                                               */
+  const int64_t* n;     /* host [nprob] cells, >= max(8, 2 max(P[b], 2))      */
+  const int32_t* P;     /* host [nprob] 1..4                                   */
+  const int32_t* bc;    /* host [nprob] ACAT_BC_*                              */
+  const double* dx;     /* host [nprob] > 0                                    */
+} acat_batch;
+
+acat_status acat_batch_workspace_size(const acat_batch* batch, size_t* bytes /* host */);
+acat_status acat_batch_init(const acat_batch* batch, void* workspace, size_t workspace_bytes);
+/* u_out = one ACAT step of every problem with dt_dev[b] (device [nprob]). */
+acat_status acat_step_batched(const acat_batch* batch, const double* u_in, double* u_out, const double* dt_dev,
+                              void* workspace, size_t workspace_bytes, void* stream);
+/* dt_dev[b] = cfl dx[b] / (max spectral radius over problem b of u). */
+acat_status acat_batched_cfl_dt(const acat_batch* batch, const double* u, double cfl, double* dt_dev,
+                                void* workspace, size_t workspace_bytes, void* stream);
+
 /* Reads and clears the device status bits accumulated by steps on this
  * device (synchronises `stream`).  flags_host receives ACAT_DEV_* bits. */
 acat_status acat_device_status(int32_t* flags_host, void* stream);

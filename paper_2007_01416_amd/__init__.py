@@ -59,6 +59,12 @@ _SIGS = {
     "acat_device_status": [ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p],
     "acat_status_string": [ctypes.c_int],
     "acat_coefficients": [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "acat_batch_workspace_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "acat_batch_init": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t],
+    "acat_step_batched": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                          ctypes.c_size_t, ctypes.c_void_p],
+    "acat_batched_cfl_dt": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                            ctypes.c_size_t, ctypes.c_void_p],
     "acat_profile_enable": [ctypes.c_int32],
     "acat_profile_read": [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                           ctypes.POINTER(ctypes.c_int32)],
@@ -237,6 +243,62 @@ def coefficients(p: int):
     return dict(g1=g1, gt=gt, eta=eta, tau=tau)
 
 
+class _Batch(ctypes.Structure):
+    _fields_ = [("nvar", ctypes.c_int32), ("flux", ctypes.c_int32),
+                ("gamma", ctypes.c_double), ("ax", ctypes.c_double),
+                ("eps", ctypes.c_double), ("theta", ctypes.c_double),
+                ("nprob", ctypes.c_int32),
+                ("n", ctypes.POINTER(ctypes.c_int64)), ("P", ctypes.POINTER(ctypes.c_int32)),
+                ("bc", ctypes.POINTER(ctypes.c_int32)), ("dx", ctypes.POINTER(ctypes.c_double))]
+
+
+class Batch:
+    """A batch of independent 1D problems advanced together (acat_step_batched).
+
+    States are SoA over the concatenated cells: shape (nvar, sum(n))."""
+
+    def __init__(self, n, P, bc, dx, flux="euler", nvar=3, gamma=1.4, ax=1.0, eps=1e-12, theta=0.5,
+                 device="cuda"):
+        import numpy as np
+        self.n = np.ascontiguousarray(n, dtype=np.int64)
+        self.P = np.ascontiguousarray(P, dtype=np.int32)
+        self.bc = np.ascontiguousarray([BC[b] if isinstance(b, str) else int(b) for b in bc], dtype=np.int32)
+        self.dx = np.ascontiguousarray(dx, dtype=np.float64)
+        self.nprob = len(self.n)
+        self.nvar = nvar
+        self.offsets = np.concatenate([[0], np.cumsum(self.n)])
+        self.ncell = int(self.offsets[-1])
+        self._c = _Batch(nvar, FLUX[flux], gamma, ax, eps, theta, self.nprob,
+                         self.n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                         self.P.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         self.bc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         self.dx.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        nb = ctypes.c_size_t(0)
+        _check(load().acat_batch_workspace_size(ctypes.byref(self._c), ctypes.byref(nb)), "acat_batch_workspace_size")
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=device)
+        torch.cuda.synchronize()
+        _check(load().acat_batch_init(ctypes.byref(self._c), _ptr(self.ws), self.ws.numel()), "acat_batch_init")
+
+    @property
+    def shape(self):
+        return (self.nvar, self.ncell)
+
+    def split(self, u):
+        """Per-problem views of a batched state."""
+        return [u[:, self.offsets[b]:self.offsets[b + 1]] for b in range(self.nprob)]
+
+    def step(self, u: torch.Tensor, dt: torch.Tensor, out: torch.Tensor = None, stream=None) -> torch.Tensor:
+        out = torch.empty_like(u) if out is None else out
+        _check(load().acat_step_batched(ctypes.byref(self._c), _ptr(u), _ptr(out), _ptr(dt), _ptr(self.ws),
+                                        self.ws.numel(), _stream(stream)), "acat_step_batched")
+        return out
+
+    def cfl_dt(self, u: torch.Tensor, cfl: float, dt: torch.Tensor, stream=None) -> torch.Tensor:
+        _check(load().acat_batched_cfl_dt(ctypes.byref(self._c), _ptr(u), cfl, _ptr(dt), _ptr(self.ws),
+                                          self.ws.numel(), _stream(stream)), "acat_batched_cfl_dt")
+        return dt
+
+
 def profile(on: bool = True):
     """Start (clear) or stop the library's kernel timer."""
     _check(load().acat_profile_enable(1 if on else 0), "acat_profile_enable")
@@ -256,4 +318,4 @@ def profile_read(max_kernels: int = 64) -> dict:
     return out
 
 
-from .runner import Solver  # noqa: E402  (time loop and graph capture)
+from .runner import BatchSolver, Solver  # noqa: E402  (time loops and graph capture)

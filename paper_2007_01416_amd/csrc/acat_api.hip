@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <vector>
 
 #include "../../include/acat.h"
 #include "acat_internal.hpp"
@@ -167,6 +168,89 @@ acat_status do_step(const acat_problem* prob, const double* u_in, double* u_out,
   return e == hipSuccess ? ACAT_OK : ACAT_ERR_DEVICE;
 }
 
+// ------------------------------------------------------------------ batch
+acat_status check_batch(const acat_batch* bt) {
+  if (!bt) return ACAT_ERR_NULL;
+  if (bt->nprob < 1) return ACAT_ERR_ARG;
+  if (!bt->n || !bt->P || !bt->bc || !bt->dx) return ACAT_ERR_NULL;
+  if (bt->flux < ACAT_FLUX_ADVECTION || bt->flux > ACAT_FLUX_EULER) return ACAT_ERR_ARG;
+  if (bt->flux == ACAT_FLUX_EULER && (bt->nvar != 3 || !(bt->gamma > 1.0))) return ACAT_ERR_ARG;
+  if (bt->flux != ACAT_FLUX_EULER && bt->nvar != 1) return bt->nvar < 1 ? ACAT_ERR_ARG : ACAT_ERR_UNSUPPORTED;
+  if (!(bt->eps >= 0.0) || !(bt->theta > 0.0 && bt->theta <= 1.0)) return ACAT_ERR_ARG;
+  int64_t cells = 0, ifs = 0;
+  for (int b = 0; b < bt->nprob; ++b) {
+    const int P = bt->P[b];
+    if (P < 1 || P > 4) return ACAT_ERR_ARG;
+    const int64_t G = P > 2 ? P : 2;
+    if (bt->n[b] < 8 || bt->n[b] < 2 * G) return ACAT_ERR_ARG;
+    if (bt->bc[b] != ACAT_BC_PERIODIC && bt->bc[b] != ACAT_BC_TRANSMISSIVE) return ACAT_ERR_ARG;
+    if (!(bt->dx[b] > 0.0)) return ACAT_ERR_ARG;
+    cells += bt->n[b];
+    ifs += bt->n[b] + (bt->bc[b] == ACAT_BC_PERIODIC ? 0 : 1);
+    if (ifs >= ((int64_t)1 << 31) - 1) return ACAT_ERR_UNSUPPORTED;
+  }
+  return ACAT_OK;
+}
+
+struct BLayout {
+  size_t hdr, coff, ioffs, N, P, bc, dx, smax, ord, psi, al, F, hist, offs, list, total;
+  int64_t ncell, nif;
+  int Pmax;
+};
+
+BLayout blayout(const acat_batch* bt) {
+  BLayout L{};
+  const int np = bt->nprob;
+  L.Pmax = 1;
+  for (int b = 0; b < np; ++b) {
+    L.ncell += bt->n[b];
+    L.nif += bt->n[b] + (bt->bc[b] == ACAT_BC_PERIODIC ? 0 : 1);
+    if (bt->P[b] > L.Pmax) L.Pmax = bt->P[b];
+  }
+  const int64_t tiles = (L.nif + BLOCK - 1) / BLOCK;
+  size_t o = 0;
+  L.hdr = o;   o += align_up(sizeof(int32_t) * MAX_CLASSES);
+  L.coff = o;  o += align_up(sizeof(int64_t) * (np + 1));
+  L.ioffs = o; o += align_up(sizeof(int64_t) * (np + 1));
+  L.N = o;     o += align_up(sizeof(int32_t) * np);
+  L.P = o;     o += align_up(sizeof(int32_t) * np);
+  L.bc = o;    o += align_up(sizeof(int32_t) * np);
+  L.dx = o;    o += align_up(sizeof(double) * np);
+  L.smax = o;  o += align_up(sizeof(double) * np);
+  L.ord = o;   o += align_up((size_t)L.nif);
+  L.psi = o;   o += align_up(sizeof(double) * L.nif);
+  L.al = o;    o += align_up(sizeof(double) * L.nif);
+  L.F = o;     o += align_up(sizeof(double) * bt->nvar * L.nif);
+  L.hist = o;  o += align_up(sizeof(int32_t) * MAX_CLASSES * tiles);
+  L.offs = o;  o += align_up(sizeof(int32_t) * MAX_CLASSES * (tiles + 1));
+  L.list = o;  o += align_up(sizeof(int32_t) * L.nif);
+  L.total = o;
+  return L;
+}
+
+KBatch make_kbatch(const acat_batch* bt, const BLayout& L, char* w) {
+  KBatch k{};
+  k.nvar = bt->nvar;
+  k.flux = bt->flux;
+  k.nprob = bt->nprob;
+  k.Pmax = L.Pmax;
+  k.ph.gamma = bt->gamma;
+  k.ph.gm1 = bt->gamma - 1.0;
+  k.ph.ax = bt->ax;
+  k.ph.ay = 0.0;
+  k.eps = bt->eps;
+  k.theta = bt->theta;
+  k.ncell = L.ncell;
+  k.nif = L.nif;
+  k.coff = reinterpret_cast<const int64_t*>(w + L.coff);
+  k.ioffs = reinterpret_cast<const int64_t*>(w + L.ioffs);
+  k.N = reinterpret_cast<const int32_t*>(w + L.N);
+  k.P = reinterpret_cast<const int32_t*>(w + L.P);
+  k.bc = reinterpret_cast<const int32_t*>(w + L.bc);
+  k.dx = reinterpret_cast<const double*>(w + L.dx);
+  return k;
+}
+
 }  // namespace
 }  // namespace acat
 
@@ -210,6 +294,85 @@ acat_status acat_cfl_dt(const acat_problem* prob, const double* smax_dev, double
   if (!(cfl > 0.0)) return ACAT_ERR_ARG;
   hipError_t e = launch_cfl_dt(make_kprob(prob), smax_dev, cfl, t_final, t_dev, dt_dev,
                                static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? ACAT_OK : ACAT_ERR_DEVICE;
+}
+
+acat_status acat_batch_workspace_size(const acat_batch* batch, size_t* bytes) {
+  acat_status rc = check_batch(batch);
+  if (rc != ACAT_OK) return rc;
+  if (!bytes) return ACAT_ERR_NULL;
+  *bytes = blayout(batch).total;
+  return ACAT_OK;
+}
+
+acat_status acat_batch_init(const acat_batch* batch, void* workspace, size_t workspace_bytes) {
+  acat_status rc = check_batch(batch);
+  if (rc != ACAT_OK) return rc;
+  const BLayout L = blayout(batch);
+  if (!workspace || workspace_bytes < L.total) return ACAT_ERR_WORKSPACE;
+  const int np = batch->nprob;
+  std::vector<char> host(L.smax - L.coff, 0);
+  auto put = [&](size_t off, const void* src, size_t n) { std::memcpy(host.data() + (off - L.coff), src, n); };
+  std::vector<int64_t> coff(np + 1, 0), ioffs(np + 1, 0);
+  std::vector<int32_t> N(np), P(np), bc(np);
+  for (int b = 0; b < np; ++b) {
+    coff[b + 1] = coff[b] + batch->n[b];
+    ioffs[b + 1] = ioffs[b] + batch->n[b] + (batch->bc[b] == ACAT_BC_PERIODIC ? 0 : 1);
+    N[b] = (int32_t)batch->n[b];
+    P[b] = batch->P[b];
+    bc[b] = batch->bc[b];
+  }
+  put(L.coff, coff.data(), sizeof(int64_t) * (np + 1));
+  put(L.ioffs, ioffs.data(), sizeof(int64_t) * (np + 1));
+  put(L.N, N.data(), sizeof(int32_t) * np);
+  put(L.P, P.data(), sizeof(int32_t) * np);
+  put(L.bc, bc.data(), sizeof(int32_t) * np);
+  put(L.dx, batch->dx, sizeof(double) * np);
+  char* w = static_cast<char*>(workspace);
+  if (hipMemcpy(w + L.coff, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) return ACAT_ERR_DEVICE;
+  return ACAT_OK;
+}
+
+acat_status acat_step_batched(const acat_batch* batch, const double* u_in, double* u_out, const double* dt_dev,
+                              void* workspace, size_t workspace_bytes, void* stream) {
+  acat_status rc = check_batch(batch);
+  if (rc != ACAT_OK) return rc;
+  if (!u_in || !u_out || !dt_dev) return ACAT_ERR_NULL;
+  const BLayout L = blayout(batch);
+  if (!workspace || workspace_bytes < L.total) return ACAT_ERR_WORKSPACE;
+  if (overlaps(u_in, u_out, sizeof(double) * batch->nvar * (size_t)L.ncell)) return ACAT_ERR_ALIAS;
+  char* w = static_cast<char*>(workspace);
+  const KBatch bt = make_kbatch(batch, L, w);
+  KBStep st{};
+  st.u = u_in;
+  st.uout = u_out;
+  st.dt = dt_dev;
+  st.ord = reinterpret_cast<int8_t*>(w + L.ord);
+  st.psi = reinterpret_cast<double*>(w + L.psi);
+  st.al = reinterpret_cast<double*>(w + L.al);
+  st.F = reinterpret_cast<double*>(w + L.F);
+  st.hist = reinterpret_cast<int32_t*>(w + L.hist);
+  st.offs = reinterpret_cast<int32_t*>(w + L.offs);
+  st.counts = reinterpret_cast<int32_t*>(w + L.hdr);
+  st.list = reinterpret_cast<int32_t*>(w + L.list);
+  st.status = status_ptr();
+  if (!st.status) return ACAT_ERR_DEVICE;
+  hipError_t e = launch_step_batched(bt, st, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? ACAT_OK : ACAT_ERR_DEVICE;
+}
+
+acat_status acat_batched_cfl_dt(const acat_batch* batch, const double* u, double cfl, double* dt_dev,
+                                void* workspace, size_t workspace_bytes, void* stream) {
+  acat_status rc = check_batch(batch);
+  if (rc != ACAT_OK) return rc;
+  if (!u || !dt_dev) return ACAT_ERR_NULL;
+  if (!(cfl > 0.0)) return ACAT_ERR_ARG;
+  const BLayout L = blayout(batch);
+  if (!workspace || workspace_bytes < L.total) return ACAT_ERR_WORKSPACE;
+  char* w = static_cast<char*>(workspace);
+  const KBatch bt = make_kbatch(batch, L, w);
+  hipError_t e = launch_cfl_batched(bt, u, cfl, reinterpret_cast<double*>(w + L.smax), dt_dev,
+                                    static_cast<hipStream_t>(stream));
   return e == hipSuccess ? ACAT_OK : ACAT_ERR_DEVICE;
 }
 

@@ -1,0 +1,320 @@
+// Batched ACAT step: many independent 1D problems (own size N_b, largest
+// half-width P_b, boundary, dx_b and time step dt_b; common flux) advanced
+// together.  The interfaces of all problems are classified in one launch,
+// grouped into per-order work lists shared by all problems, and each order
+// class is one persistent launch over every problem, so the small problems
+// of a batch fill the GPU together.  Per interface the arithmetic is that of
+// the single-problem kernels (same rounding), so a batched step equals the
+// per-problem steps bit for bit.
+//
+// Layout: states are SoA over the concatenated cells, u[var][coff_b + i];
+// interface arrays are concatenated the same way with offsets ioff_b.
+#include <hip/hip_runtime.h>
+
+#include "acat_internal.hpp"
+#include "coeffs.hpp"
+#include "step_common.hpp"
+
+namespace acat {
+
+namespace {
+
+// largest b with off[b] <= x (off nondecreasing, off[0] = 0 <= x)
+__device__ __forceinline__ int find_seg(const int64_t* off, int n, int64_t x) {
+  int a = 0, b = n;
+  while (b - a > 1) {
+    const int m = (a + b) >> 1;
+    if (off[m] <= x) a = m;
+    else b = m;
+  }
+  return a;
+}
+
+constexpr int GW = PMAX;   // indicator window half-width for every problem (offsets -3 .. 4)
+
+template <int FLUX, int NV>
+__global__ __launch_bounds__(BLOCK) void k_classify_b(KBatch bt, KBStep st) {
+  const int64_t kg = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const bool valid = kg < bt.nif;
+  int ps = 1;
+  if (valid) {
+    const int b = find_seg(bt.ioffs, bt.nprob, kg);
+    const int n = bt.N[b], bc = bt.bc[b];
+    const int i = (int)(kg - bt.ioffs[b]) - (bc == PERIODIC ? 0 : 1);
+    const double* ub = st.u + bt.coff[b];
+    double v[NV][2 * GW];
+#pragma unroll
+    for (int a = 0; a < 2 * GW; ++a) {
+      const int node = bc_index32(i - GW + 1 + a, n, bc);
+#pragma unroll
+      for (int c = 0; c < NV; ++c) v[c][a] = ub[c * bt.ncell + node];
+    }
+    ps = SelectRT<NV, GW, PMAX>::run(v, bt.P[b], bt.eps, bt.theta);
+    double psi1 = -1.0, al = -1.0;
+    if (ps == 1) {
+      psi1 = limiter<NV, GW>(v);
+      double uL[NV], uR[NV];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        uL[c] = v[c][GW - 1];
+        uR[c] = v[c][GW];
+      }
+      al = fmax(spectral_radius<FLUX, 1, NV>(bt.ph, uL, 0), spectral_radius<FLUX, 1, NV>(bt.ph, uR, 0));
+    }
+    st.ord[kg] = (int8_t)ps;
+    st.psi[kg] = psi1;
+    st.al[kg] = al;
+  }
+  __shared__ int sh[MAX_CLASSES];
+  block_hist(sh, valid, ps - 1, st.hist);
+}
+
+// Interfaces of order p of every problem (same arithmetic as k_flux1d).
+template <int FLUX, int NV, int p>
+__global__ __launch_bounds__(BLOCK) void k_flux_b(KBatch bt, KBStep st) {
+  constexpr int L = 2 * p;
+  constexpr int GPB = BLOCK / L;
+  constexpr int SL = L + 1;
+  constexpr int NS = GPB * SL + SL;
+  __shared__ double xs[2][NV][NS];
+
+  const int tid = threadIdx.x;
+  const int g = tid / L;
+  const int a = tid - g * L;
+  const int slot = g * SL + a;
+  const bool inblk = g < GPB;
+
+  double g1[L];
+#pragma unroll
+  for (int l = 0; l < L; ++l) g1[l] = TB.G1[p][a][l];
+
+  int buf = 0;
+  const Slice sl(st.counts, st.list, p - 1);
+  for (int64_t base = sl.lo; base < sl.hi; base += GPB) {
+    const bool valid = inblk && base + g < sl.hi;
+    const int64_t kg = valid ? sl.items[base + g] : 0;
+    const int b = find_seg(bt.ioffs, bt.nprob, kg);
+    const int n = bt.N[b], bc = bt.bc[b];
+    const int i = (int)(kg - bt.ioffs[b]) - (bc == PERIODIC ? 0 : 1);
+    const double* ub = st.u + bt.coff[b];
+    const double lam = st.dt[b] / bt.dx[b];
+    const int node = bc_index32(i + (a - p + 1), n, bc);
+    double u[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) u[c] = valid ? ub[c * bt.ncell + node] : 1.0;
+
+    double fh0[NV], cur[NV], S[NV];
+    flux1d<FLUX, NV>(bt.ph, u, fh0);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      cur[c] = fh0[c];
+      S[c] = fma(TB.INVFACT[1], fh0[c], 0.0);
+    }
+    double U[L][NV];
+#pragma unroll
+    for (int kk = 2; kk <= 2 * p; ++kk) {
+#pragma unroll
+      for (int c = 0; c < NV; ++c) xs[buf][c][slot] = cur[c];
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int l = 0; l < L; ++l) sacc = fma(g1[l], xs[buf][c][g * SL + l], sacc);
+        U[kk - 1][c] = -lam * sacc;
+      }
+      buf ^= 1;
+      double nxt[NV];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) nxt[c] = 0.0;
+#pragma unroll
+      for (int ri = 0; ri < L; ++ri) {
+        const int r = ri - p + 1;
+        double ph[NV];
+        if (r == 0) {
+#pragma unroll
+          for (int c = 0; c < NV; ++c) ph[c] = fh0[c];
+        } else {
+          double w[NV];
+#pragma unroll
+          for (int c = 0; c < NV; ++c) {
+            double sacc = u[c];
+#pragma unroll
+            for (int l = 1; l <= kk - 1; ++l) sacc = fma(TB.TAYLOR[r + PMAX - 1][l], U[l][c], sacc);
+            w[c] = sacc;
+          }
+          flux1d<FLUX, NV>(bt.ph, w, ph);
+        }
+#pragma unroll
+        for (int c = 0; c < NV; ++c) nxt[c] = fma(TB.GT[p][kk - 1][ri], ph[c], nxt[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        cur[c] = nxt[c];
+        S[c] = fma(TB.INVFACT[kk], nxt[c], S[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NV; ++c) xs[buf][c][slot] = S[c];
+    __syncthreads();
+    if (valid && a < NV) {
+      for (int task = 0; task < 2; ++task) {
+        const int c = a + task * L;
+        if (c >= NV) break;
+        double F = 0.0;
+#pragma unroll
+        for (int l = 0; l < L; ++l) F = fma(TB.ETA[p][l], xs[buf][c % NV][g * SL + l], F);
+        if constexpr (p == 1) {
+          const double psi = st.psi[kg], al = st.al[kg];
+          const int nl = bc_index32(i, n, bc), nr = bc_index32(i + 1, n, bc);
+          double uL[NV], uR[NV], fL[NV], fR[NV];
+#pragma unroll
+          for (int cc = 0; cc < NV; ++cc) {
+            uL[cc] = ub[cc * bt.ncell + nl];
+            uR[cc] = ub[cc * bt.ncell + nr];
+          }
+          flux1d<FLUX, NV>(bt.ph, uL, fL);
+          flux1d<FLUX, NV>(bt.ph, uR, fR);
+          double ul = 0.0, ur = 0.0, fl = 0.0, fr = 0.0;
+#pragma unroll
+          for (int cc = 0; cc < NV; ++cc)
+            if (cc == c) {
+              ul = uL[cc];
+              ur = uR[cc];
+              fl = fL[cc];
+              fr = fR[cc];
+            }
+          const double flo = 0.5 * (fl + fr) - (0.5 * al) * (ur - ul);
+          F = psi * F + (1.0 - psi) * flo;
+        }
+        st.F[c * bt.nif + kg] = F;
+      }
+    }
+    buf ^= 1;
+  }
+}
+
+template <int FLUX, int NV>
+__global__ __launch_bounds__(BLOCK) void k_update_b(KBatch bt, KBStep st) {
+  const int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (e >= bt.ncell) return;
+  const int b = find_seg(bt.coff, bt.nprob, e);
+  const int n = bt.N[b], bc = bt.bc[b];
+  const int i = (int)(e - bt.coff[b]);
+  const double lam = st.dt[b] / bt.dx[b];
+  const int64_t kr = bt.ioffs[b] + i + (bc == PERIODIC ? 0 : 1);
+  const int64_t kl = bt.ioffs[b] + ((bc == PERIODIC) ? (i == 0 ? n - 1 : i - 1) : i);
+  double w[NV];
+  bool finite = true;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    w[c] = st.u[c * bt.ncell + e] + lam * (st.F[c * bt.nif + kl] - st.F[c * bt.nif + kr]);
+    st.uout[c * bt.ncell + e] = w[c];
+    finite = finite && isfinite(w[c]);
+  }
+  const uint32_t bad = (finite ? 0u : 1u) | (physical<FLUX, 1, NV>(bt.ph, w) ? 0u : 2u);
+  if (bad) atomicOr(st.status, bad);
+}
+
+// smax[b] = max spectral radius over problem b: one block per problem, no atomics.
+template <int FLUX, int NV>
+__global__ __launch_bounds__(BLOCK) void k_max_speed_b(KBatch bt, const double* __restrict__ u, double* smax) {
+  const int b = blockIdx.x;
+  const int64_t c0 = bt.coff[b], c1 = bt.coff[b + 1];
+  double m = 0.0;
+  for (int64_t e = c0 + threadIdx.x; e < c1; e += BLOCK) {
+    double w[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) w[c] = u[c * bt.ncell + e];
+    m = fmax(m, spectral_radius<FLUX, 1, NV>(bt.ph, w, 0));
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  __shared__ double red[BLOCK / 64];
+  if (__lane_id() == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 1; w < BLOCK / 64; ++w) m = fmax(m, red[w]);
+    smax[b] = m;
+  }
+}
+
+__global__ void k_dt_b(KBatch bt, const double* smax, double cfl, double* dt) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < bt.nprob) dt[b] = cfl * bt.dx[b] / smax[b];
+}
+
+#define ACAT_CHECK_LAUNCH()                  \
+  do {                                       \
+    hipError_t e_ = hipGetLastError();       \
+    if (e_ != hipSuccess) return e_;         \
+  } while (0)
+
+template <int FLUX, int NV, int p>
+hipError_t launch_flux_b(const KBatch& bt, const KBStep& st, hipStream_t s) {
+  if (p > bt.Pmax) return hipSuccess;
+  static const char* names[5] = {"", "flux_b_p1", "flux_b_p2", "flux_b_p3", "flux_b_p4"};
+  auto kern = k_flux_b<FLUX, NV, p>;
+  const int grid = persistent_grid(kern, bt.nif, 0);
+  {
+    ProfScope ps(names[p], s);
+    kern<<<grid, BLOCK, 0, s>>>(bt, st);
+  }
+  ACAT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+template <int FLUX, int NV>
+hipError_t step_b_impl(const KBatch& bt, const KBStep& st, hipStream_t s) {
+  const int cblocks = (int)((bt.nif + BLOCK - 1) / BLOCK);
+  {
+    ProfScope ps("classify_b", s);
+    k_classify_b<FLUX, NV><<<cblocks, BLOCK, 0, s>>>(bt, st);
+  }
+  ACAT_CHECK_LAUNCH();
+  k_scan_hist<<<bt.Pmax, BLOCK, 0, s>>>(st.hist, cblocks, st.offs, st.counts);
+  ACAT_CHECK_LAUNCH();
+  k_scatter<PMAX><<<cblocks, BLOCK, 0, s>>>(st.ord, 1, bt.nif, cblocks, st.offs, st.counts, st.list);
+  ACAT_CHECK_LAUNCH();
+  hipError_t e;
+  if ((e = launch_flux_b<FLUX, NV, 1>(bt, st, s)) != hipSuccess) return e;
+  if ((e = launch_flux_b<FLUX, NV, 2>(bt, st, s)) != hipSuccess) return e;
+  if ((e = launch_flux_b<FLUX, NV, 3>(bt, st, s)) != hipSuccess) return e;
+  if ((e = launch_flux_b<FLUX, NV, 4>(bt, st, s)) != hipSuccess) return e;
+  {
+    ProfScope ps("update_b", s);
+    k_update_b<FLUX, NV><<<(unsigned)((bt.ncell + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(bt, st);
+  }
+  ACAT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+template <int FLUX, int NV>
+hipError_t cfl_b_impl(const KBatch& bt, const double* u, double cfl, double* smax, double* dt, hipStream_t s) {
+  {
+    ProfScope ps("max_speed_b", s);
+    k_max_speed_b<FLUX, NV><<<bt.nprob, BLOCK, 0, s>>>(bt, u, smax);
+  }
+  ACAT_CHECK_LAUNCH();
+  k_dt_b<<<(bt.nprob + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(bt, smax, cfl, dt);
+  ACAT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_step_batched(const KBatch& bt, const KBStep& st, hipStream_t s) {
+  if (bt.flux == EUL) return step_b_impl<EUL, 3>(bt, st, s);
+  if (bt.flux == BURG) return step_b_impl<BURG, 1>(bt, st, s);
+  return step_b_impl<ADV, 1>(bt, st, s);
+}
+
+hipError_t launch_cfl_batched(const KBatch& bt, const double* u, double cfl, double* smax, double* dt,
+                              hipStream_t s) {
+  if (bt.flux == EUL) return cfl_b_impl<EUL, 3>(bt, u, cfl, smax, dt, s);
+  if (bt.flux == BURG) return cfl_b_impl<BURG, 1>(bt, u, cfl, smax, dt, s);
+  return cfl_b_impl<ADV, 1>(bt, u, cfl, smax, dt, s);
+}
+
+}  // namespace acat

@@ -66,4 +66,36 @@ hipError_t launch_max_speed(const KProb& pb, const double* u, double* smax, hipS
 hipError_t launch_cfl_dt(const KProb& pb, const double* smax, double cfl, double t_final, double* t_dev,
                          double* dt_dev, hipStream_t stream);
 
+struct KBatch {
+  int nvar, flux, nprob, Pmax;
+  Phys ph;
+  double eps, theta;
+  int64_t ncell, nif;       // total cells and interfaces
+  const int64_t* coff;      // [nprob + 1] first cell of each problem
+  const int64_t* ioffs;     // [nprob + 1] first interface of each problem
+  const int32_t* N;         // [nprob] cells
+  const int32_t* P;         // [nprob] largest half-width
+  const int32_t* bc;        // [nprob] boundary
+  const double* dx;         // [nprob]
+};
+
+struct KBStep {
+  const double* u;
+  double* uout;
+  const double* dt;         // [nprob]
+  int8_t* ord;
+  double* psi;
+  double* al;
+  double* F;                // [nvar][nif]
+  int32_t* hist;
+  int32_t* offs;
+  int32_t* counts;
+  int32_t* list;
+  uint32_t* status;
+};
+
+hipError_t launch_step_batched(const KBatch& bt, const KBStep& st, hipStream_t stream);
+hipError_t launch_cfl_batched(const KBatch& bt, const double* u, double cfl, double* smax, double* dt,
+                              hipStream_t stream);
+
 }  // namespace acat

@@ -1,0 +1,209 @@
+// Device helpers shared by the step kernels (single problem and batched):
+// smoothness indicators, order selection, limiter, per-class work lists.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "acat_internal.hpp"
+#include "coeffs.hpp"
+
+namespace acat {
+namespace {
+
+constexpr CoeffTables TB = make_tables();
+constexpr int NXCD = 8;   // MI355X: 8 accelerator complex dies, each with its own L2
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ double superbee(double r) { return fmax(0.0, fmax(fmin(2.0 * r, 1.0), fmin(r, 2.0))); }
+
+// psi^p of one component; v holds offsets -G+1 .. G (index j + G - 1).
+template <int G, int p>
+__device__ __forceinline__ double psi_comp(const double (&v)[2 * G], double eps) {
+  double IL = 0.0, IR = 0.0;
+#pragma unroll
+  for (int j = -p + 1; j <= -1; ++j) {
+    const double d = v[j + G] - v[j + G - 1];
+    IL += d * d;
+  }
+#pragma unroll
+  for (int j = 1; j <= p - 1; ++j) {
+    const double d = v[j + G] - v[j + G - 1];
+    IR += d * d;
+  }
+  IL += eps;
+  IR += eps;
+  const double I = IL * IR / (IL + IR);
+  double s = 0.0;
+#pragma unroll
+  for (int j = -p + 1; j <= p; ++j) s += TB.TAU[p][j + p - 1] * v[j + G - 1];
+  double tau = TB.FACT2PM1[p] * s;
+  tau = tau * tau;
+  return I / (I + tau);
+}
+
+// p_s = max{p in 2..P : min_c psi^{c,p} >= theta}, else 1 (evaluated from P down)
+template <int NV, int G, int p>
+struct Select {
+  __device__ static __forceinline__ int run(const double (&v)[NV][2 * G], double eps, double theta) {
+    double psi = 1.0;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) psi = fmin(psi, psi_comp<G, p>(v[c], eps));
+    if (psi >= theta) return p;
+    return Select<NV, G, p - 1>::run(v, eps, theta);
+  }
+};
+template <int NV, int G>
+struct Select<NV, G, 1> {
+  __device__ static __forceinline__ int run(const double (&)[NV][2 * G], double, double) { return 1; }
+};
+
+// psi^1 = min_c min(phi(r+), phi(r-)); a component with u_{i+1} = u_i gives 1
+template <int NV, int G>
+__device__ __forceinline__ double limiter(const double (&v)[NV][2 * G]) {
+  double psi = 1e300;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    const double dl = v[c][G] - v[c][G - 1];
+    double l = 1.0;
+    if (dl != 0.0) {
+      const double rm = (v[c][G - 1] - v[c][G - 2]) / dl;
+      const double rp = (v[c][G + 1] - v[c][G]) / dl;
+      l = fmin(superbee(rp), superbee(rm));
+    }
+    psi = fmin(psi, l);
+  }
+  return psi;
+}
+
+// Balanced slice of one class list: the n items of class c (spatial order)
+// are cut into gridDim.x contiguous slices, and the slices of the blocks on
+// XCD x (blockIdx % 8) are adjacent, so neighbouring items share that XCD's L2.
+struct Slice {
+  const int32_t* items;
+  int64_t lo, hi;
+  __device__ Slice(const int32_t* counts, const int32_t* list, int c) {
+    int64_t base = 0;
+    for (int k = 0; k < c; ++k) base += counts[k];
+    const int64_t n = counts[c];
+    const int nb = gridDim.x / NXCD;
+    const int r = (blockIdx.x % NXCD) * nb + blockIdx.x / NXCD;
+    lo = n * r / gridDim.x;
+    hi = n * (r + 1) / gridDim.x;
+    items = list + base;
+  }
+};
+
+// Per-block class histogram (LDS atomics), written without global atomics.
+__device__ __forceinline__ void block_hist(int* sh, bool valid, int cls, int32_t* out) {
+  if (threadIdx.x < MAX_CLASSES) sh[threadIdx.x] = 0;
+  __syncthreads();
+  if (valid) atomicAdd(&sh[cls], 1);
+  __syncthreads();
+  if (threadIdx.x < MAX_CLASSES) out[(int64_t)blockIdx.x * MAX_CLASSES + threadIdx.x] = sh[threadIdx.x];
+}
+
+// offs[c][t] = items of class c in tiles < t, counts[c] = total; one block per class.
+__global__ __launch_bounds__(BLOCK) void k_scan_hist(const int32_t* hist, int ntiles, int32_t* offs,
+                                                     int32_t* counts) {
+  __shared__ int part[BLOCK];
+  const int c = blockIdx.x;
+  const int per = (ntiles + BLOCK - 1) / BLOCK;
+  const int t0 = threadIdx.x * per;
+  int acc = 0;
+  for (int t = t0; t < t0 + per && t < ntiles; ++t) acc += hist[(int64_t)t * MAX_CLASSES + c];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int k = 0; k < BLOCK; ++k) {
+      const int v = part[k];
+      part[k] = run;
+      run += v;
+    }
+    counts[c] = run;
+    offs[(int64_t)c * (ntiles + 1) + ntiles] = run;
+  }
+  __syncthreads();
+  int run = part[threadIdx.x];
+  for (int t = t0; t < t0 + per && t < ntiles; ++t) {
+    offs[(int64_t)c * (ntiles + 1) + t] = run;
+    run += hist[(int64_t)t * MAX_CLASSES + c];
+  }
+}
+
+// list[base_c + offs[c][tile] + rank] = item, for the item of every thread
+// (rank among the tile's items of the same class, in thread order).  One
+// block per tile of the classification; no atomics, deterministic.
+template <int NCLS>
+__global__ __launch_bounds__(BLOCK) void k_scatter(const int8_t* map, int map_bias, int64_t nitems, int ntiles,
+                                                   const int32_t* offs, const int32_t* counts, int32_t* list) {
+  __shared__ int wc[NCLS][BLOCK / 64];
+  const int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int c = e < nitems ? map[e] - map_bias : -1;
+  const int lane = __lane_id(), wid = threadIdx.x >> 6;
+  unsigned long long mine = 0ull;
+#pragma unroll
+  for (int k = 0; k < NCLS; ++k) {
+    const unsigned long long m = __ballot(c == k);
+    if (c == k) mine = m;
+    if (lane == 0) wc[k][wid] = __popcll(m);
+  }
+  __syncthreads();
+  if (c >= 0 && c < NCLS) {
+    int64_t pos = 0;
+    for (int k = 0; k < c; ++k) pos += counts[k];
+    pos += offs[(int64_t)c * (ntiles + 1) + blockIdx.x];
+    for (int w = 0; w < wid; ++w) pos += wc[c][w];
+    pos += __popcll(mine & ((1ull << lane) - 1ull));
+    list[pos] = (int32_t)e;
+  }
+}
+
+
+// p_s with a run-time largest half-width P <= p (batched problems): same
+// decisions as Select with P fixed, on a window of half-width G >= P.
+template <int NV, int G, int p>
+struct SelectRT {
+  __device__ static __forceinline__ int run(const double (&v)[NV][2 * G], int P, double eps, double theta) {
+    if (p <= P) {
+      double psi = 1.0;
+#pragma unroll
+      for (int c = 0; c < NV; ++c) psi = fmin(psi, psi_comp<G, p>(v[c], eps));
+      if (psi >= theta) return p;
+    }
+    return SelectRT<NV, G, p - 1>::run(v, P, eps, theta);
+  }
+};
+template <int NV, int G>
+struct SelectRT<NV, G, 1> {
+  __device__ static __forceinline__ int run(const double (&)[NV][2 * G], int, double, double) { return 1; }
+};
+
+// ------------------------------------------------------------ host side
+int num_cus() {
+  static int n = 0;
+  if (!n) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+      n = 256;
+  }
+  return n;
+}
+
+// Persistent grid of a tile-walking kernel: enough blocks to fill every CU
+// at the kernel's occupancy (cap > 0 overrides), never more than the tiles,
+// a multiple of the XCD count.
+template <typename K>
+int persistent_grid(K kernel, int64_t nitems, int cap) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, BLOCK, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  int64_t b = cap > 0 ? cap : (int64_t)per_cu * num_cus();
+  const int64_t ntiles = (nitems + BLOCK - 1) / BLOCK;
+  if (b > ntiles) b = ntiles;
+  b = (b + NXCD - 1) / NXCD * NXCD;
+  return (int)(b < NXCD ? NXCD : b);
+}
+
+}  // namespace
+}  // namespace acat

@@ -10,7 +10,7 @@ from __future__ import annotations
 
 import torch
 
-from . import (Decisions, Problem, cfl_dt, max_wave_speed, step, step_replay, workspace)
+from . import (Batch, Decisions, Problem, cfl_dt, max_wave_speed, step, step_replay, workspace)
 
 
 class Solver:
@@ -71,6 +71,61 @@ class Solver:
         if nsteps % 2:
             raise ValueError("capture an even number of steps (ping-pong buffers)")
         self.step()   # warm-up outside capture (kernels loaded)
+        self.step()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        start = self.cur
+        with torch.cuda.graph(g):
+            for _ in range(nsteps):
+                self.step()
+        self.cur = start
+        self.nsteps -= nsteps
+        self.graph, self.graph_steps = g, nsteps
+        return g
+
+    def replay(self, times: int = 1):
+        for _ in range(times):
+            self.graph.replay()
+            self.nsteps += self.graph_steps
+        return self.u
+
+
+class BatchSolver:
+    """Fixed-step time loop of a Batch: per step, per-problem CFL time steps
+    and one batched step; `capture(k)` records k steps into one HIP graph."""
+
+    def __init__(self, batch: Batch, u0, cfl: float, device="cuda"):
+        self.batch = batch
+        self.cfl = float(cfl)
+        u0 = torch.as_tensor(u0, dtype=torch.float64, device=device).contiguous()
+        if tuple(u0.shape) != batch.shape:
+            raise ValueError(f"initial state {tuple(u0.shape)} != {batch.shape}")
+        self.buf = [u0.clone(), torch.empty_like(u0)]
+        self.cur = 0
+        self.dt = torch.zeros(batch.nprob, dtype=torch.float64, device=device)
+        self.nsteps = 0
+        self.graph = None
+        self.graph_steps = 0
+
+    @property
+    def u(self) -> torch.Tensor:
+        return self.buf[self.cur]
+
+    def step(self):
+        self.batch.cfl_dt(self.u, self.cfl, self.dt)
+        self.batch.step(self.u, self.dt, out=self.buf[1 - self.cur])
+        self.cur ^= 1
+        self.nsteps += 1
+
+    def run(self, nsteps: int):
+        for _ in range(nsteps):
+            self.step()
+        return self.u
+
+    def capture(self, nsteps: int = 2):
+        if nsteps % 2:
+            raise ValueError("capture an even number of steps (ping-pong buffers)")
+        self.step()
         self.step()
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()

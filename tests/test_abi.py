@@ -101,3 +101,32 @@ def test_workspace_grows_with_problem(lib):
     assert large > small > 0
     w2 = acat.workspace_bytes(_prob(dim=2, nvar=4, nx=64, ny=32, dy=0.1, P=3))
     assert w2 > 9 * 4 * 64 * 32
+
+
+def _batch_struct(n, P, bc, dx, flux=2, nvar=3):
+    import paper_2007_01416_amd as acat
+    n = np.ascontiguousarray(n, np.int64); P = np.ascontiguousarray(P, np.int32)
+    bc = np.ascontiguousarray(bc, np.int32); dx = np.ascontiguousarray(dx, np.float64)
+    b = acat._Batch(nvar, flux, 1.4, 1.0, 1e-12, 0.5, len(n), n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                    P.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), bc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                    dx.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return b, (n, P, bc, dx)
+
+
+@pytest.mark.parametrize("n,P,bc,dx,code", [
+    ([64, 32], [2, 3], [0, 1], [0.1, 0.1], 0),
+    ([64, 4], [2, 1], [0, 1], [0.1, 0.1], -2),      # too few cells
+    ([64, 32], [2, 5], [0, 1], [0.1, 0.1], -2),     # P out of range
+    ([64, 32], [2, 3], [0, 7], [0.1, 0.1], -2),     # bad boundary
+    ([64, 32], [2, 3], [0, 1], [0.1, 0.0], -2),     # dx <= 0
+])
+def test_batch_validation(lib, n, P, bc, dx, code):
+    b, keep = _batch_struct(n, P, bc, dx)
+    nb = ctypes.c_size_t(0)
+    assert lib.acat_batch_workspace_size(ctypes.byref(b), ctypes.byref(nb)) == code
+    if code == 0:
+        assert nb.value > 0
+        # a step needs its state and time-step pointers, and a large enough workspace
+        ws = ctypes.create_string_buffer(nb.value)
+        assert lib.acat_step_batched(ctypes.byref(b), None, None, None, ws, nb.value, None) == -1
+        assert lib.acat_step_batched(ctypes.byref(b), ws, ws, ws, ws, 16, None) == -6

@@ -1,0 +1,109 @@
+"""Batched step (many independent 1D problems, one launch per order class):
+bitwise equal to per-problem steps and to the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def T(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def concat(states):
+    return np.concatenate(states, axis=1)
+
+
+def make_batch(acat, probs):
+    return acat.Batch([p["u"].shape[1] for p in probs], [p["P"] for p in probs], [p["bc"] for p in probs],
+                      [p["dx"] for p in probs], flux=probs[0]["flux"], nvar=probs[0]["nvar"])
+
+
+def test_batched_c4_equals_per_instance_steps(acat):
+    """256 Euler problems, N log-uniform in [512, 16384], P in {2,3,4}."""
+    import torch
+    w = workloads.batch_1d()
+    probs = w["problems"]
+    batch = make_batch(acat, probs)
+    bs = acat.BatchSolver(batch, concat([p["u"] for p in probs]), w["cfl"])
+    singles = []
+    for p in probs:
+        pg = acat.Problem(dim=1, nvar=3, nx=p["u"].shape[1], flux="euler", P=p["P"], bc=p["bc"], dx=p["dx"])
+        singles.append(acat.Solver(pg, p["u"], w["cfl"]))
+    for n in range(3):
+        bs.step()
+        for s in singles:
+            s.step()
+        torch.cuda.synchronize()
+        got = bs.u.cpu().numpy()
+        parts = batch.split(got)
+        dts = bs.dt.cpu().numpy()
+        for b, s in enumerate(singles):
+            assert float(s.dt.item()) == dts[b], f"dt problem {b} step {n}"
+            assert np.array_equal(parts[b], s.u.cpu().numpy()), f"state problem {b} step {n}"
+    say(f"[batched C4] {batch.nprob} problems, {batch.ncell} cells: 3 steps bitwise equal to per-problem steps")
+
+
+@pytest.mark.parametrize("flux", ["euler", "burgers"])
+def test_batched_lockstep_oracle(acat, flux):
+    rng = np.random.default_rng(3)
+    probs = []
+    for b in range(12):
+        n = int(rng.integers(16, 300))
+        P = int(rng.integers(1, 5))
+        bc = "periodic" if b % 3 == 0 else "transmissive"
+        if flux == "euler":
+            p = workloads.euler_1d(n=n, P=P, stream=(b,))
+        else:
+            x = np.arange(n) / n
+            p = dict(u=(np.sin(2 * np.pi * x + b) + (x > 0.5))[None].copy(), dx=1.0 / n, flux="burgers", P=P,
+                     nvar=1)
+        p["bc"] = bc
+        p["P"] = P
+        probs.append(p)
+    batch = make_batch(acat, probs)
+    us = [p["u"].copy() for p in probs]
+    u = T(concat(us))
+    import torch
+    dt = torch.zeros(batch.nprob, dtype=torch.float64, device="cuda")
+    fid = oracle.FLUX_EULER if flux == "euler" else oracle.FLUX_BURGERS
+    for step in range(8):
+        batch.cfl_dt(u, 0.6, dt)
+        u = batch.step(u, dt)
+        dts = dt.cpu().numpy()
+        parts = batch.split(u.cpu().numpy())
+        for b, p in enumerate(probs):
+            po = oracle.Problem(dim=1, nvar=p["nvar"], nx=us[b].shape[1], flux=fid, P=p["P"],
+                                bc=oracle.BC_PERIODIC if p["bc"] == "periodic" else oracle.BC_TRANSMISSIVE,
+                                dx=p["dx"])
+            assert dts[b] == oracle.dt_cfl(po, us[b], 0.6)
+            us[b] = oracle.step1d(po, us[b], dts[b])["u"]
+            assert np.array_equal(parts[b], us[b]), f"problem {b} step {step}"
+
+
+def test_batched_graph_replay_matches_eager(acat):
+    import torch
+    w = workloads.batch_1d(nprob=32, nmin=64, nmax=2048)
+    probs = w["problems"]
+    batch = make_batch(acat, probs)
+    u0 = concat([p["u"] for p in probs])
+    a = acat.BatchSolver(batch, u0, 0.5)
+    a.capture(2)
+    b = acat.BatchSolver(batch, u0, 0.5)
+    b.run(2)
+    for rep in range(3):
+        a.replay(1)
+        b.run(2)
+        torch.cuda.synchronize()
+        assert np.array_equal(a.u.cpu().numpy(), b.u.cpu().numpy()), f"replay {rep}"
