@@ -67,6 +67,47 @@ def cpu_baseline(w, nsteps_sample=1):
                       f"state ({el:.1f} s)"}
 
 
+def bench_batched(acat, workloads, steps_batched=500, steps_single=10):
+    """256 independent 1D Euler problems: batched graph-replayed steps vs the
+    same problems advanced one acat_step per problem."""
+    import numpy as np
+    import torch
+    w = workloads.batch_1d()
+    probs = w["problems"]
+    batch = acat.Batch([p["u"].shape[1] for p in probs], [p["P"] for p in probs], [p["bc"] for p in probs],
+                       [p["dx"] for p in probs], flux="euler", nvar=3)
+    u0 = np.concatenate([p["u"] for p in probs], axis=1)
+    bs = acat.BatchSolver(batch, u0, w["cfl"])
+    bs.capture(2)
+    bs.replay(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bs.replay(steps_batched // 2)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    singles = []
+    for p in probs:
+        pg = acat.Problem(dim=1, nvar=3, nx=p["u"].shape[1], flux="euler", P=p["P"], bc=p["bc"], dx=p["dx"])
+        singles.append(acat.Solver(pg, p["u"], w["cfl"]))
+    for s in singles:
+        s.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps_single):
+        for s in singles:
+            s.step()
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    cells = batch.ncell
+    vb = cells * steps_batched / tb
+    vs = cells * steps_single / ts
+    return {"workload": f"{batch.nprob} independent 1D Euler problems, N log-uniform in [512,16384] "
+                        f"(total {cells} cells), P in {{2,3,4}}, transmissive, per-problem CFL 0.5",
+            "value": vb, "unit": "cell-updates/s", "steps": steps_batched, "ms_per_step": 1e3 * tb / steps_batched,
+            "per_instance_value": vs, "per_instance_steps": steps_single,
+            "per_instance_ms_per_step": 1e3 * ts / steps_single, "speedup_vs_per_instance": vb / vs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +115,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched and adjoint workloads")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         sys.exit("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus must be 1)")
@@ -151,6 +193,8 @@ def main():
         "kernels": {k: {"launches": v["launches"], "avg_us": round(v["avg_us"], 2)} for k, v in kernels.items()},
         "device_status": flags,
     }
+    if not args.no_extra:
+        out["batched"] = bench_batched(acat, workloads)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

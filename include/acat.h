@@ -116,6 +116,30 @@ acat_status acat_step_replay(const acat_problem* prob, const double* u_in, doubl
                              const double* dt_dev, void* workspace, size_t workspace_bytes,
                              const acat_decisions* dec, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Adjoint (reverse mode) of one step with frozen decisions.  With
+ * u_out = S(u_in) the map of acat_step_replay for the same `dec` and time
+ * step, ubar_in = (dS/du_in)^T ubar_out: the conservative update's
+ * transpose gives the interface flux adjoints Fbar = lambda (ubar_{i+1} -
+ * ubar_i), and each interface (1D) or corner (2D) recomputes its Taylor
+ * recursion (Sec. 2.2; Sec. 4) and runs it backwards, with the analytic
+ * flux Jacobians and the transposed centred-difference and time-
+ * extrapolation weights; the FL-CAT2 blend (Sec. 3.1) is differentiated at
+ * fixed psi1 and alpha.  Contributions are summed per cell in a fixed order
+ * (deterministic; no atomics).
+ *   - dec: the decisions of the forward step (all used pointers set); u_in:
+ *     the forward step's input state; dt / dt_dev as in acat_step.
+ *   - ubar_out, ubar_in: state-shaped adjoints; ubar_in may equal ubar_out
+ *     (in place) but may not partially overlap it or overlap u_in.
+ *   - 1D: every flux and boundary; 2D: periodic only (else
+ *     ACAT_ERR_UNSUPPORTED).  Recorded orders outside 1..P are taken as 1
+ *     and set ACAT_DEV_BAD_ORDER.
+ * --------------------------------------------------------------------- */
+acat_status acat_adjoint_workspace_size(const acat_problem* prob, size_t* bytes /* host */);
+acat_status acat_step_adjoint(const acat_problem* prob, const double* u_in, double dt, const double* dt_dev,
+                              const acat_decisions* dec, const double* ubar_out, double* ubar_in,
+                              void* workspace, size_t workspace_bytes, void* stream);
+
 /* smax_dev[d] = max over cells of the spectral radius of the flux Jacobian
  * in direction d (d < dim): |u| (Burgers), |a| (advection), |v|+c (Euler). */
 acat_status acat_max_wave_speed(const acat_problem* prob, const double* u, double* smax_dev, void* stream);

@@ -207,6 +207,29 @@ def jvp(prob: Problem, u, du, dt: float, maps, nthreads: int = 0):
     return out, dout
 
 
+def vjp_dense(prob: Problem, u, ubar, dt: float, maps, nthreads: int = 0):
+    """Adjoint of the frozen replay step by its definition, ubar_in = J^T ubar
+    with J the Jacobian of the replay step assembled column by column from
+    jvp: entry j of ubar_in is <ubar, J e_j>.  Small problems only."""
+    u = _state(prob, u)
+    ubar = _state(prob, ubar)
+    e = np.zeros(u.size)
+    out = np.empty(u.size)
+    for j in range(u.size):
+        e[j] = 1.0
+        _, col = jvp(prob, u, e.reshape(u.shape), dt, maps, nthreads)
+        out[j] = float(np.dot(col.ravel(), ubar.ravel()))
+        e[j] = 0.0
+    return out.reshape(u.shape)
+
+
+def maps_of(prob: Problem, r: dict):
+    """The frozen decisions of a step result, in the form jvp / step2d take."""
+    if prob.dim == 1:
+        return (r["order"], r["psi1"], r["alpha"])
+    return tuple(r[k] for k in ("ordx", "ordy", "psix", "psiy", "alx", "aly"))
+
+
 def update_cells(prob: Problem, u, dt: float, cells, nthreads: int = 0):
     """Updated state at the given cells ([n,2] of (i1, i2)); returns (vals [n,nvar], orders [n,4])."""
     u = _state(prob, u)

@@ -53,6 +53,9 @@ _SIGS = {
                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p],
     "acat_step_replay": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p],
+    "acat_adjoint_workspace_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "acat_step_adjoint": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "acat_max_wave_speed": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "acat_cfl_dt": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                     ctypes.c_void_p, ctypes.c_void_p],
@@ -212,6 +215,32 @@ def step_replay(prob: Problem, u: torch.Tensor, dt, dec: Decisions, out: torch.T
     return out
 
 
+def adjoint_workspace_bytes(prob: Problem) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load().acat_adjoint_workspace_size(ctypes.byref(prob.c()), ctypes.byref(n)),
+           "acat_adjoint_workspace_size")
+    return n.value
+
+
+def adjoint_workspace(prob: Problem, device="cuda") -> torch.Tensor:
+    return torch.empty(adjoint_workspace_bytes(prob), dtype=torch.uint8, device=device)
+
+
+def step_adjoint(prob: Problem, u: torch.Tensor, dt, dec: Decisions, ubar_out: torch.Tensor,
+                 ubar_in: torch.Tensor = None, ws: torch.Tensor = None, stream=None) -> torch.Tensor:
+    """ubar_in = (d step_replay(u) / du)^T ubar_out for the decisions `dec`."""
+    _check_state(prob, u, "u")
+    _check_state(prob, ubar_out, "ubar_out")
+    ubar_in = torch.empty_like(u) if ubar_in is None else ubar_in
+    _check_state(prob, ubar_in, "ubar_in")
+    ws = adjoint_workspace(prob, u.device) if ws is None else ws
+    dtv, dtp = (float(dt), None) if not torch.is_tensor(dt) else (0.0, _ptr(dt))
+    _check(load().acat_step_adjoint(ctypes.byref(prob.c()), _ptr(u), dtv, dtp, ctypes.byref(dec.c()),
+                                    _ptr(ubar_out), _ptr(ubar_in), _ptr(ws), ws.numel(), _stream(stream)),
+           "acat_step_adjoint")
+    return ubar_in
+
+
 def max_wave_speed(prob: Problem, u: torch.Tensor, smax: torch.Tensor = None, stream=None) -> torch.Tensor:
     _check_state(prob, u, "u")
     smax = torch.empty(2, dtype=torch.float64, device=u.device) if smax is None else smax
@@ -318,4 +347,4 @@ def profile_read(max_kernels: int = 64) -> dict:
     return out
 
 
-from .runner import BatchSolver, Solver  # noqa: E402  (time loops and graph capture)
+from .runner import ACATRun, AdjointRun, BatchSolver, Solver  # noqa: E402  (time loops and graph capture)

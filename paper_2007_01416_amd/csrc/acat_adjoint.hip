@@ -1,0 +1,677 @@
+// Adjoint of one ACAT step with frozen decisions (orders, psi^1, Rusanov
+// speed, time step): ubar_in = ubar_out + sum over interfaces of
+// (dF/du)^T Fbar, with Fbar_k = lambda (ubar_{i+1} - ubar_i) for the
+// interface between cells i and i+1 (in 2D likewise for G along y).
+//
+// Per interface (1D) or corner (2D) the kernels recompute the CAT recursion
+// of the forward step (Sec. 2.2; Sec. 4 corner recursion) in registers, one
+// lane per stencil node, keeping the Taylor history U^1..U^{2q-1} of the
+// node, then run it backwards: flux Jacobian-transpose products at the
+// predicted states, and for the spatial derivative of each level the
+// transposed row/column sums through LDS.  Each lane writes the
+// contribution to its node into a per-item buffer; a gather kernel adds, for
+// every cell, the contributions of all items whose stencil covers it in a
+// fixed order (deterministic, no atomics).
+#include <hip/hip_runtime.h>
+
+#include "acat_internal.hpp"
+#include "coeffs.hpp"
+#include "step_common.hpp"
+
+namespace acat {
+namespace {
+
+// ======================================================================= 1D
+// contribution buffer: C[c][k * 2P + a], a = node index of interface k
+template <int FLUX, int NV, int p>
+__global__ __launch_bounds__(BLOCK) void k_adj1d(KProb pb, KStep st, const double* __restrict__ ubo,
+                                                 double* __restrict__ C, int LMAX) {
+  constexpr int L = 2 * p;
+  constexpr int GPB = BLOCK / L;
+  constexpr int SL = L + 1;
+  constexpr int NS = GPB * SL + SL;
+  __shared__ double xs[2][NV][NS];
+
+  const int tid = threadIdx.x;
+  const int g = tid / L;
+  const int a = tid - g * L;
+  const int slot = g * SL + a;
+  const bool inblk = g < GPB;
+  const double lam = step_dt(st) / pb.dx;
+  const int64_t nx = pb.nx, nI = pb.nIx;
+  const int nx32 = (int)nx;
+  const int64_t cstride = nI * LMAX;
+
+  double g1[L], g1T[L];
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    g1[l] = TB.G1[p][a][l];
+    g1T[l] = TB.G1[p][l][a];
+  }
+  const double eta = TB.ETA[p][a];
+
+  int buf = 0;
+  const Slice sl(st.counts, st.list, p - 1);
+  for (int64_t base = sl.lo; base < sl.hi; base += GPB) {
+    const bool valid = inblk && base + g < sl.hi;
+    const int32_t k = valid ? sl.items[base + g] : 0;
+    const int i = k + (int)pb.ioff;
+    const int node = bc_index32(i + (a - p + 1), nx32, pb.bc);
+    double u[NV], Fb[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) u[c] = valid ? st.u[c * nx + node] : 1.0;
+    // Fbar = lambda (ubar_{i+1} - ubar_i); a transmissive boundary interface
+    // updates only the cell inside the grid
+    const bool hasR = valid && (pb.bc == PERIODIC || i + 1 < nx32);
+    const bool hasL = valid && i >= 0;
+    const int cr = bc_index32(i + 1, nx32, pb.bc), cl = bc_index32(i, nx32, pb.bc);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      const double ur = hasR ? ubo[c * nx + cr] : 0.0;
+      const double ul = hasL ? ubo[c * nx + cl] : 0.0;
+      Fb[c] = lam * (ur - ul);
+    }
+    double psi = 1.0, al = 0.0;
+    if constexpr (p == 1) {
+      if (valid) {
+        psi = st.psix[k];
+        al = st.alx[k];
+      }
+    }
+    // ---- forward recomputation, keeping U^l at this node
+    double fh0[NV], cur[NV];
+    flux1d<FLUX, NV>(pb.ph, u, fh0);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) cur[c] = fh0[c];
+    double U[L][NV];
+#pragma unroll
+    for (int kk = 2; kk <= 2 * p - 1; ++kk) {   // Fh^{2p-1} is not needed backwards
+#pragma unroll
+      for (int c = 0; c < NV; ++c) xs[buf][c][slot] = cur[c];
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int l = 0; l < L; ++l) sacc = fma(g1[l], xs[buf][c][g * SL + l], sacc);
+        U[kk - 1][c] = -lam * sacc;
+      }
+      buf ^= 1;
+      double nxt[NV];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) nxt[c] = 0.0;
+#pragma unroll
+      for (int ri = 0; ri < L; ++ri) {
+        const int r = ri - p + 1;
+        double ph[NV];
+        if (r == 0) {
+#pragma unroll
+          for (int c = 0; c < NV; ++c) ph[c] = fh0[c];
+        } else {
+          double w[NV];
+#pragma unroll
+          for (int c = 0; c < NV; ++c) {
+            double sacc = u[c];
+#pragma unroll
+            for (int l = 1; l <= kk - 1; ++l) sacc = fma(TB.TAYLOR[r + PMAX - 1][l], U[l][c], sacc);
+            w[c] = sacc;
+          }
+          flux1d<FLUX, NV>(pb.ph, w, ph);
+        }
+#pragma unroll
+        for (int c = 0; c < NV; ++c) nxt[c] = fma(TB.GT[p][kk - 1][ri], ph[c], nxt[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < NV; ++c) cur[c] = nxt[c];
+    }
+    // U^{2p-1}
+    if (2 * p >= 2) {
+#pragma unroll
+      for (int c = 0; c < NV; ++c) xs[buf][c][slot] = cur[c];
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int l = 0; l < L; ++l) sacc = fma(g1[l], xs[buf][c][g * SL + l], sacc);
+        U[2 * p - 1][c] = -lam * sacc;
+      }
+      buf ^= 1;
+    }
+    // ---- reverse sweep
+    // F = sum_j eta_j S_j, S_j = sum_k Fh^{k-1}_j / k!  =>  Sbar_j = eta_j psi Fbar
+    double sb[NV], ub[NV], f0b[NV], fhb[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      sb[c] = eta * psi * Fb[c];
+      ub[c] = 0.0;
+      f0b[c] = 0.0;
+      fhb[c] = TB.INVFACT[2 * p] * sb[c];   // Fhbar^{2p-1}
+    }
+    double Ub[L][NV];
+#pragma unroll
+    for (int l = 0; l < L; ++l)
+#pragma unroll
+      for (int c = 0; c < NV; ++c) Ub[l][c] = 0.0;
+#pragma unroll
+    for (int kk = 2 * p; kk >= 2; --kk) {
+      // Fh^{kk-1} = sum_r GT_r phi_r
+#pragma unroll
+      for (int ri = 0; ri < L; ++ri) {
+        const int r = ri - p + 1;
+        double phb[NV];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) phb[c] = TB.GT[p][kk - 1][ri] * fhb[c];
+        if (r == 0) {
+#pragma unroll
+          for (int c = 0; c < NV; ++c) f0b[c] += phb[c];
+        } else {
+          double w[NV], wb[NV];
+#pragma unroll
+          for (int c = 0; c < NV; ++c) {
+            double sacc = u[c];
+#pragma unroll
+            for (int l = 1; l <= kk - 1; ++l) sacc = fma(TB.TAYLOR[r + PMAX - 1][l], U[l][c], sacc);
+            w[c] = sacc;
+            wb[c] = 0.0;
+          }
+          flux1d_vjp<FLUX, NV>(pb.ph, w, phb, wb);
+#pragma unroll
+          for (int c = 0; c < NV; ++c) {
+            ub[c] += wb[c];
+#pragma unroll
+            for (int l = 1; l <= kk - 1; ++l) Ub[l][c] += TB.TAYLOR[r + PMAX - 1][l] * wb[c];
+          }
+        }
+      }
+      // U^{kk-1}_a = -lam sum_l g1[a][l] Fh^{kk-2}_l  =>  Fhbar^{kk-2}_a += -lam sum_j g1[j][a] Ubar_j
+#pragma unroll
+      for (int c = 0; c < NV; ++c) xs[buf][c][slot] = Ub[kk - 1][c];
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int j = 0; j < L; ++j) sacc += g1T[j] * xs[buf][c][g * SL + j];
+        fhb[c] = TB.INVFACT[kk - 1] * sb[c] - lam * sacc;   // Fhbar^{kk-2}
+      }
+      buf ^= 1;
+    }
+    // Fh^0 = f(u) also enters every r = 0 term
+#pragma unroll
+    for (int c = 0; c < NV; ++c) f0b[c] += fhb[c];
+    flux1d_vjp<FLUX, NV>(pb.ph, u, f0b, ub);
+    if constexpr (p == 1) {
+      // Rusanov part of the FL-CAT2 blend: (1 - psi) [(f_i + f_{i+1})/2 - alpha/2 (u_{i+1} - u_i)]
+      double lb[NV], zero[NV];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        lb[c] = 0.5 * (1.0 - psi) * Fb[c];
+        zero[c] = 0.0;
+      }
+      flux1d_vjp<FLUX, NV>(pb.ph, u, lb, zero);
+#pragma unroll
+      for (int c = 0; c < NV; ++c) ub[c] += zero[c] + (a == 0 ? al : -al) * lb[c];
+    }
+    if (valid) {
+#pragma unroll
+      for (int c = 0; c < NV; ++c) C[c * cstride + (int64_t)k * LMAX + a] = ub[c];
+    }
+  }
+}
+
+// ubar_in[m] = ubar_out[m] + the contributions of every interface with a
+// stencil node at cell m (through the boundary map), interfaces in
+// increasing order, nodes in increasing order.  Periodic: interfaces
+// i = m - j, j in [-P+1, P] (node j of interface i is cell m exactly when
+// i + j = m, as nx >= 2P).  Transmissive: the same window, extended to the
+// first (last) interface for the P cells next to the left (right) edge,
+// whose clamped nodes reach them.
+template <int NV>
+__global__ __launch_bounds__(BLOCK) void k_gather1d(KProb pb, KStep st, const double* __restrict__ ubo,
+                                                    const double* __restrict__ C, int LMAX, double* ubi) {
+  const int m = blockIdx.x * BLOCK + threadIdx.x;
+  const int nx = (int)pb.nx, P = pb.P, ioff = (int)pb.ioff, nI = (int)pb.nIx;
+  if (m >= nx) return;
+  const int64_t cstride = (int64_t)nI * LMAX;
+  const bool per = pb.bc == PERIODIC;
+  double acc[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) acc[c] = ubo[c * pb.nx + m];
+  const int ilo = (!per && m < P) ? ioff : m - P;
+  const int ihi = (!per && m >= nx - P) ? nx - 1 : m + P - 1;
+  for (int i0 = ilo; i0 <= ihi; ++i0) {
+    const int i = per ? (i0 < 0 ? i0 + nx : (i0 >= nx ? i0 - nx : i0)) : i0;
+    const int k = i - ioff;
+    const int q = st.cls[k] + 1;
+    for (int a = 0; a < 2 * q; ++a) {
+      const int j = a - q + 1;
+      const int node = per ? i0 + j : bc_index32(i0 + j, nx, pb.bc);
+      if (node != m) continue;
+#pragma unroll
+      for (int c = 0; c < NV; ++c) acc[c] += C[c * cstride + (int64_t)k * LMAX + a];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NV; ++c) ubi[c * pb.nx + m] = acc[c];
+}
+
+// ======================================================================= 2D
+// One corner recursion forward (keeping U), then backwards.  sfb/sgb: the
+// adjoints of this node's series SF / SG; ub accumulates the adjoint of u,
+// f0b/g0b those of f(u), g(u).
+template <int FLUX, int NV, int Q1, int Q2, int QT>
+__device__ __forceinline__ void corner_adjoint(const Phys& ph, double lamx, double lamy, const double (&u)[NV],
+                                               const double (&f0)[NV], const double (&g0)[NV],
+                                               const double (&g1x)[2 * Q1], const double (&g1y)[2 * Q2],
+                                               const double (&g1xT)[2 * Q1], const double (&g1yT)[2 * Q2],
+                                               double2* xsb0, double2* xsb1, int stride, int& buf, int slot,
+                                               int gbase, int a1, int a2, const double (&sfb)[NV],
+                                               const double (&sgb)[NV], double (&ub)[NV], double (&f0b)[NV],
+                                               double (&g0b)[NV]) {
+  constexpr int N1 = 2 * Q1, N2 = 2 * Q2, T = 2 * QT;
+  double fc[NV], gc[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    fc[c] = f0[c];
+    gc[c] = g0[c];
+  }
+  double U[T][NV];
+  // forward: U^1 .. U^{T-1}
+#pragma unroll
+  for (int kk = 2; kk <= T; ++kk) {
+    double2* xsw = buf ? xsb1 : xsb0;
+    Xch<NV>::put(xsw, stride, slot, fc, gc);
+    __syncthreads();
+    const double* xr = reinterpret_cast<const double*>(xsw);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      double sx = 0.0, sy = 0.0;
+#pragma unroll
+      for (int l = 0; l < N1; ++l) sx = fma(g1x[l], Xch<NV>::get(xr, stride, gbase + a2 * N1 + l, c, false), sx);
+#pragma unroll
+      for (int l = 0; l < N2; ++l) sy = fma(g1y[l], Xch<NV>::get(xr, stride, gbase + l * N1 + a1, c, true), sy);
+      U[kk - 1][c] = -lamx * sx - lamy * sy;
+    }
+    buf ^= 1;
+    if (kk == T) break;
+    double nf[NV], ng[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      nf[c] = 0.0;
+      ng[c] = 0.0;
+    }
+#pragma unroll
+    for (int ri = 0; ri < T; ++ri) {
+      const int r = ri - QT + 1;
+      double pf[NV], pg[NV];
+      if (r == 0) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+          pf[c] = f0[c];
+          pg[c] = g0[c];
+        }
+      } else {
+        double w[NV];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+          double sacc = u[c];
+#pragma unroll
+          for (int l = 1; l <= kk - 1; ++l) sacc = fma(TB.TAYLOR[r + PMAX - 1][l], U[l][c], sacc);
+          w[c] = sacc;
+        }
+        flux2d<FLUX, NV>(ph, w, pf, pg);
+      }
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        nf[c] = fma(TB.GT[QT][kk - 1][ri], pf[c], nf[c]);
+        ng[c] = fma(TB.GT[QT][kk - 1][ri], pg[c], ng[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      fc[c] = nf[c];
+      gc[c] = ng[c];
+    }
+  }
+  // backward
+  double fhb[NV], ghb[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    fhb[c] = TB.INVFACT[T] * sfb[c];
+    ghb[c] = TB.INVFACT[T] * sgb[c];
+  }
+  double Ub[T][NV];
+#pragma unroll
+  for (int l = 0; l < T; ++l)
+#pragma unroll
+    for (int c = 0; c < NV; ++c) Ub[l][c] = 0.0;
+#pragma unroll
+  for (int kk = T; kk >= 2; --kk) {
+#pragma unroll
+    for (int ri = 0; ri < T; ++ri) {
+      const int r = ri - QT + 1;
+      double pfb[NV], pgb[NV];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        pfb[c] = TB.GT[QT][kk - 1][ri] * fhb[c];
+        pgb[c] = TB.GT[QT][kk - 1][ri] * ghb[c];
+      }
+      if (r == 0) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+          f0b[c] += pfb[c];
+          g0b[c] += pgb[c];
+        }
+      } else {
+        double w[NV], wb[NV];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+          double sacc = u[c];
+#pragma unroll
+          for (int l = 1; l <= kk - 1; ++l) sacc = fma(TB.TAYLOR[r + PMAX - 1][l], U[l][c], sacc);
+          w[c] = sacc;
+          wb[c] = 0.0;
+        }
+        flux2d_vjp<FLUX, NV>(ph, w, pfb, pgb, wb);
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+          ub[c] += wb[c];
+#pragma unroll
+          for (int l = 1; l <= kk - 1; ++l) Ub[l][c] += TB.TAYLOR[r + PMAX - 1][l] * wb[c];
+        }
+      }
+    }
+    // U^{kk-1} = -lamx sum_l g1x[a1][l] Fh_(l,a2) - lamy sum_l g1y[a2][l] Gh_(a1,l)
+    //  => Fhbar_(a1,a2) += -lamx sum_j g1x[j][a1] Ubar_(j,a2); Ghbar likewise along the column
+    double2* xsw = buf ? xsb1 : xsb0;
+    Xch<NV>::put(xsw, stride, slot, Ub[kk - 1], Ub[kk - 1]);
+    __syncthreads();
+    const double* xr = reinterpret_cast<const double*>(xsw);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      double sx = 0.0, sy = 0.0;
+#pragma unroll
+      for (int j = 0; j < N1; ++j) sx += g1xT[j] * Xch<NV>::get(xr, stride, gbase + a2 * N1 + j, c, false);
+#pragma unroll
+      for (int j = 0; j < N2; ++j) sy += g1yT[j] * Xch<NV>::get(xr, stride, gbase + j * N1 + a1, c, true);
+      fhb[c] = TB.INVFACT[kk - 1] * sfb[c] - lamx * sx;
+      ghb[c] = TB.INVFACT[kk - 1] * sgb[c] - lamy * sy;
+    }
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    f0b[c] += fhb[c];
+    g0b[c] += ghb[c];
+  }
+}
+
+// contribution buffer: C[c][e * LMAX + nd], nd = a2 * 2Q1 + a1 node of corner e
+template <int FLUX, int NV, int Q1, int Q2>
+__global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const double* __restrict__ ubo,
+                                                 double* __restrict__ C, int LMAX) {
+  constexpr int N1 = 2 * Q1, N2 = 2 * Q2, L = N1 * N2, CPB = BLOCK / L;
+  constexpr int NP = Xch<NV>::NP;
+  constexpr int STRIDE = BLOCK + L;
+  __shared__ double2 xs[2][NP * STRIDE];
+
+  const int tid = threadIdx.x;
+  const int g = tid / L;
+  const int nd = tid - g * L;
+  const int a1 = nd % N1, a2 = nd / N1;
+  const bool inblk = g < CPB;
+  const int cls = (Q1 - 1) * pb.P + (Q2 - 1);
+  const double dt = step_dt(st);
+  const double lamx = dt / pb.dx, lamy = dt / pb.dy;
+  const int64_t nx = pb.nx, ny = pb.ny, plane = pb.nx * pb.ny;
+  const int nx32 = (int)pb.nx, ny32 = (int)pb.ny, ioff = (int)pb.ioff;
+  const uint32_t n1u = (uint32_t)pb.n1;
+  const int64_t cstride = pb.n1 * pb.n2 * LMAX;
+
+  double g1x[N1], g1y[N2], g1xT[N1], g1yT[N2];
+#pragma unroll
+  for (int l = 0; l < N1; ++l) {
+    g1x[l] = TB.G1[Q1][a1][l];
+    g1xT[l] = TB.G1[Q1][l][a1];
+  }
+#pragma unroll
+  for (int l = 0; l < N2; ++l) {
+    g1y[l] = TB.G1[Q2][a2][l];
+    g1yT[l] = TB.G1[Q2][l][a2];
+  }
+  const bool on_row = a2 == Q2 - 1, on_col = a1 == Q1 - 1;
+
+  int buf = 0;
+  const Slice sl(st.counts, st.list, cls);
+  for (int64_t base = sl.lo; base < sl.hi; base += CPB) {
+    const bool valid = inblk && base + g < sl.hi;
+    const int32_t e = valid ? sl.items[base + g] : 0;
+    const uint32_t eq = (uint32_t)e / n1u;
+    const int i2 = (int)eq + ioff, i1 = (int)((uint32_t)e - eq * n1u) + ioff;
+    const int x = bc_index32(i1 + (a1 - Q1 + 1), nx32, pb.bc);
+    const int y = bc_index32(i2 + (a2 - Q2 + 1), ny32, pb.bc);
+    double u[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) u[c] = valid ? st.u[c * plane + (int64_t)y * nx + x] : 1.0;
+    // Fbar = lamx (ubar_{i+e1} - ubar_i), Gbar = lamy (ubar_{i+e2} - ubar_i)
+    double Fb[NV], Gb[NV];
+    {
+      const int x0 = bc_index32(i1, nx32, pb.bc), y0 = bc_index32(i2, ny32, pb.bc);
+      const int xr = bc_index32(i1 + 1, nx32, pb.bc), yr = bc_index32(i2 + 1, ny32, pb.bc);
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        const double u0 = valid ? ubo[c * plane + (int64_t)y0 * nx + x0] : 0.0;
+        const double ux = valid ? ubo[c * plane + (int64_t)y0 * nx + xr] : 0.0;
+        const double uy = valid ? ubo[c * plane + (int64_t)yr * nx + x0] : 0.0;
+        Fb[c] = lamx * (ux - u0);
+        Gb[c] = lamy * (uy - u0);
+      }
+    }
+    double psix = 1.0, alx = 0.0, psiy = 1.0, aly = 0.0;
+    if (valid) {
+      if (Q1 == 1) {
+        const int64_t ex = (int64_t)i2 * pb.nIx + (i1 - ioff);
+        psix = st.psix[ex];
+        alx = st.alx[ex];
+      }
+      if (Q2 == 1) {
+        const int64_t ey = (int64_t)(i2 - ioff) * nx + i1;
+        psiy = st.psiy[ey];
+        aly = st.aly[ey];
+      }
+    }
+    double f0[NV], g0[NV];
+    flux2d<FLUX, NV>(pb.ph, u, f0, g0);
+    double sfb[NV], sgb[NV], zero[NV], ub[NV], f0b[NV], g0b[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      sfb[c] = on_row ? TB.ETA[Q1][a1] * psix * Fb[c] : 0.0;
+      sgb[c] = on_col ? TB.ETA[Q2][a2] * psiy * Gb[c] : 0.0;
+      zero[c] = 0.0;
+      ub[c] = 0.0;
+      f0b[c] = 0.0;
+      g0b[c] = 0.0;
+    }
+    const int slot = g * L + nd;
+    if constexpr (Q1 == Q2) {
+      corner_adjoint<FLUX, NV, Q1, Q2, Q1>(pb.ph, lamx, lamy, u, f0, g0, g1x, g1y, g1xT, g1yT, xs[0], xs[1],
+                                           STRIDE, buf, slot, g * L, a1, a2, sfb, sgb, ub, f0b, g0b);
+    } else {
+      corner_adjoint<FLUX, NV, Q1, Q2, Q1>(pb.ph, lamx, lamy, u, f0, g0, g1x, g1y, g1xT, g1yT, xs[0], xs[1],
+                                           STRIDE, buf, slot, g * L, a1, a2, sfb, zero, ub, f0b, g0b);
+      corner_adjoint<FLUX, NV, Q1, Q2, Q2>(pb.ph, lamx, lamy, u, f0, g0, g1x, g1y, g1xT, g1yT, xs[0], xs[1],
+                                           STRIDE, buf, slot, g * L, a1, a2, zero, sgb, ub, f0b, g0b);
+    }
+    // Rusanov parts of the FL-CAT2 blends, on the two nodes each one reads
+    if (Q1 == 1 && on_row && (a1 == Q1 - 1 || a1 == Q1)) {
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        const double lb = 0.5 * (1.0 - psix) * Fb[c];
+        f0b[c] += lb;
+        ub[c] += (a1 == Q1 - 1 ? alx : -alx) * lb;
+      }
+    }
+    if (Q2 == 1 && on_col && (a2 == Q2 - 1 || a2 == Q2)) {
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        const double lb = 0.5 * (1.0 - psiy) * Gb[c];
+        g0b[c] += lb;
+        ub[c] += (a2 == Q2 - 1 ? aly : -aly) * lb;
+      }
+    }
+    flux2d_vjp<FLUX, NV>(pb.ph, u, f0b, g0b, ub);
+    if (valid) {
+#pragma unroll
+      for (int c = 0; c < NV; ++c) C[c * cstride + (int64_t)e * LMAX + nd] = ub[c];
+    }
+  }
+}
+
+// periodic 2D gather: cell m collects node (j1, j2) of corner m - j for every
+// j in [-P+1, P]^2 inside that corner's rectangle (j2 outer, j1 inner).
+template <int NV>
+__global__ __launch_bounds__(BLOCK) void k_gather2d(KProb pb, KStep st, const double* __restrict__ ubo,
+                                                    const double* __restrict__ C, int LMAX, double* ubi) {
+  const int64_t m = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int nx = (int)pb.nx, ny = (int)pb.ny, P = pb.P;
+  if (m >= (int64_t)nx * ny) return;
+  const int m1 = (int)(m % nx), m2 = (int)(m / nx);
+  const int64_t plane = (int64_t)nx * ny;
+  const int64_t cstride = pb.n1 * pb.n2 * LMAX;
+  double acc[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) acc[c] = ubo[c * plane + m];
+  for (int j2 = -P + 1; j2 <= P; ++j2) {
+    const int k2 = bc_index32(m2 - j2, ny, PERIODIC);
+    for (int j1 = -P + 1; j1 <= P; ++j1) {
+      const int k1 = bc_index32(m1 - j1, nx, PERIODIC);
+      const int64_t e = (int64_t)k2 * nx + k1;
+      const int cl = st.cls[e];
+      const int q1 = cl / P + 1, q2 = cl % P + 1;
+      if (j1 < -q1 + 1 || j1 > q1 || j2 < -q2 + 1 || j2 > q2) continue;
+      const int nd = (j2 + q2 - 1) * (2 * q1) + (j1 + q1 - 1);
+#pragma unroll
+      for (int c = 0; c < NV; ++c) acc[c] += C[c * cstride + e * LMAX + nd];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NV; ++c) ubi[c * plane + m] = acc[c];
+}
+
+#define ACAT_CHECK_LAUNCH()                  \
+  do {                                       \
+    hipError_t e_ = hipGetLastError();       \
+    if (e_ != hipSuccess) return e_;         \
+  } while (0)
+
+template <int FLUX, int NV, int P, int p>
+hipError_t launch_adj1d(const KProb& pb, const KStep& st, const double* ubo, double* C, hipStream_t s) {
+  if constexpr (p <= P) {
+    auto kern = k_adj1d<FLUX, NV, p>;
+    const int grid = persistent_grid(kern, pb.nIx, 0);
+    {
+      ProfScope ps("adjoint1d", s);
+      kern<<<grid, BLOCK, 0, s>>>(pb, st, ubo, C, 2 * P);
+    }
+    ACAT_CHECK_LAUNCH();
+  }
+  return hipSuccess;
+}
+
+template <int FLUX, int NV, int P>
+hipError_t adj1d_impl(const KProb& pb, const KStep& st, const double* ubo, double* ubi, double* C, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_adj1d<FLUX, NV, P, 1>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj1d<FLUX, NV, P, 2>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj1d<FLUX, NV, P, 3>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj1d<FLUX, NV, P, 4>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  {
+    ProfScope ps("gather1d", s);
+    k_gather1d<NV><<<(unsigned)((pb.nx + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st, ubo, C, 2 * P, ubi);
+  }
+  ACAT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+template <int FLUX, int NV, int P, int Q1, int Q2>
+hipError_t launch_adj2d(const KProb& pb, const KStep& st, const double* ubo, double* C, hipStream_t s) {
+  if constexpr (Q1 <= P && Q2 <= P) {
+    auto kern = k_adj2d<FLUX, NV, Q1, Q2>;
+    const int grid = persistent_grid(kern, pb.n1 * pb.n2, 0);
+    {
+      ProfScope ps("adjoint2d", s);
+      kern<<<grid, BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P);
+    }
+    ACAT_CHECK_LAUNCH();
+  }
+  return hipSuccess;
+}
+
+template <int FLUX, int NV, int P>
+hipError_t adj2d_impl(const KProb& pb, const KStep& st, const double* ubo, double* ubi, double* C, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_adj2d<FLUX, NV, P, 1, 1>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj2d<FLUX, NV, P, 1, 2>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj2d<FLUX, NV, P, 2, 1>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj2d<FLUX, NV, P, 2, 2>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj2d<FLUX, NV, P, 1, 3>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj2d<FLUX, NV, P, 3, 1>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj2d<FLUX, NV, P, 2, 3>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj2d<FLUX, NV, P, 3, 2>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj2d<FLUX, NV, P, 3, 3>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  {
+    ProfScope ps("gather2d", s);
+    k_gather2d<NV><<<(unsigned)((pb.nx * pb.ny + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P,
+                                                                                       ubi);
+  }
+  ACAT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(const KProb& pb, const KStep& st, const double* ubo, double* ubi, double* C,
+                          hipStream_t s) {
+  if (pb.dim == 1) {
+    if (pb.flux == EUL) {
+      switch (pb.P) {
+        case 1: return adj1d_impl<EUL, 3, 1>(pb, st, ubo, ubi, C, s);
+        case 2: return adj1d_impl<EUL, 3, 2>(pb, st, ubo, ubi, C, s);
+        case 3: return adj1d_impl<EUL, 3, 3>(pb, st, ubo, ubi, C, s);
+        case 4: return adj1d_impl<EUL, 3, 4>(pb, st, ubo, ubi, C, s);
+      }
+    } else if (pb.flux == BURG) {
+      switch (pb.P) {
+        case 1: return adj1d_impl<BURG, 1, 1>(pb, st, ubo, ubi, C, s);
+        case 2: return adj1d_impl<BURG, 1, 2>(pb, st, ubo, ubi, C, s);
+        case 3: return adj1d_impl<BURG, 1, 3>(pb, st, ubo, ubi, C, s);
+        case 4: return adj1d_impl<BURG, 1, 4>(pb, st, ubo, ubi, C, s);
+      }
+    } else {
+      switch (pb.P) {
+        case 1: return adj1d_impl<ADV, 1, 1>(pb, st, ubo, ubi, C, s);
+        case 2: return adj1d_impl<ADV, 1, 2>(pb, st, ubo, ubi, C, s);
+        case 3: return adj1d_impl<ADV, 1, 3>(pb, st, ubo, ubi, C, s);
+        case 4: return adj1d_impl<ADV, 1, 4>(pb, st, ubo, ubi, C, s);
+      }
+    }
+  } else {
+    if (pb.flux == EUL) {
+      switch (pb.P) {
+        case 1: return adj2d_impl<EUL, 4, 1>(pb, st, ubo, ubi, C, s);
+        case 2: return adj2d_impl<EUL, 4, 2>(pb, st, ubo, ubi, C, s);
+        case 3: return adj2d_impl<EUL, 4, 3>(pb, st, ubo, ubi, C, s);
+      }
+    } else {
+      switch (pb.P) {
+        case 1: return adj2d_impl<ADV, 1, 1>(pb, st, ubo, ubi, C, s);
+        case 2: return adj2d_impl<ADV, 1, 2>(pb, st, ubo, ubi, C, s);
+        case 3: return adj2d_impl<ADV, 1, 3>(pb, st, ubo, ubi, C, s);
+      }
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace acat

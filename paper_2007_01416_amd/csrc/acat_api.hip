@@ -72,7 +72,7 @@ KProb make_kprob(const acat_problem* p) {
 //   psix, psiy    double
 //   alx, aly      double
 //   Fx, Gy        double interface fluxes
-//   cls           int8 order class of every 2D corner
+//   cls           int8 order class of every item (1D interface, 2D corner)
 //   hist          int32[tiles][MAX_CLASSES]
 //   offs          int32[MAX_CLASSES][tiles + 1]
 //   list          int32[items]
@@ -97,7 +97,7 @@ Layout layout(const KProb& k) {
   L.aly = o;   o += align_up(sizeof(double) * ny_if);
   L.Fx = o;    o += align_up(sizeof(double) * k.nvar * nx_if);
   L.Gy = o;    o += align_up(sizeof(double) * k.nvar * ny_if);
-  L.cls = o;   o += align_up(k.dim == 2 ? (size_t)L.nItems : 0);
+  L.cls = o;   o += align_up((size_t)L.nItems);
   L.hist = o;  o += align_up(sizeof(int32_t) * MAX_CLASSES * (size_t)cblocks);
   L.offs = o;  o += align_up(sizeof(int32_t) * MAX_CLASSES * (size_t)(cblocks + 1));
   L.list = o;  o += align_up(sizeof(int32_t) * (size_t)L.nItems);
@@ -166,6 +166,37 @@ acat_status do_step(const acat_problem* prob, const double* u_in, double* u_out,
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = k.dim == 1 ? launch_step_1d(k, st, 0, s) : launch_step_2d(k, st, 0, s);
   return e == hipSuccess ? ACAT_OK : ACAT_ERR_DEVICE;
+}
+
+// Adjoint workspace: header, class map, tile histograms, prefix, item lists
+// and the per-item contribution buffer C[nvar][items][LMAX].
+struct ALayout {
+  size_t hdr, cls, hist, offs, list, C, total;
+  int64_t nItems;
+  int lmax;
+};
+
+ALayout alayout(const KProb& k) {
+  ALayout L{};
+  L.nItems = k.dim == 2 ? k.n1 * k.n2 : k.nIx;
+  L.lmax = k.dim == 2 ? 4 * k.P * k.P : 2 * k.P;
+  const int64_t cblocks = (L.nItems + BLOCK - 1) / BLOCK;
+  size_t o = 0;
+  L.hdr = o;   o += align_up(sizeof(int32_t) * MAX_CLASSES + sizeof(uint32_t) * 4);
+  L.cls = o;   o += align_up((size_t)L.nItems);
+  L.hist = o;  o += align_up(sizeof(int32_t) * MAX_CLASSES * (size_t)cblocks);
+  L.offs = o;  o += align_up(sizeof(int32_t) * MAX_CLASSES * (size_t)(cblocks + 1));
+  L.list = o;  o += align_up(sizeof(int32_t) * (size_t)L.nItems);
+  L.C = o;     o += align_up(sizeof(double) * (size_t)k.nvar * (size_t)L.nItems * (size_t)L.lmax);
+  L.total = o;
+  return L;
+}
+
+acat_status check_adjoint(const acat_problem* prob) {
+  acat_status rc = check_problem(prob);
+  if (rc != ACAT_OK) return rc;
+  if (prob->dim == 2 && prob->bc != ACAT_BC_PERIODIC) return ACAT_ERR_UNSUPPORTED;
+  return ACAT_OK;
 }
 
 // ------------------------------------------------------------------ batch
@@ -276,6 +307,54 @@ acat_status acat_step_replay(const acat_problem* prob, const double* u_in, doubl
                              const double* dt_dev, void* workspace, size_t workspace_bytes,
                              const acat_decisions* dec, void* stream) {
   return do_step(prob, u_in, u_out, dt, dt_dev, workspace, workspace_bytes, dec, true, stream);
+}
+
+acat_status acat_adjoint_workspace_size(const acat_problem* prob, size_t* bytes) {
+  acat_status rc = check_adjoint(prob);
+  if (rc != ACAT_OK) return rc;
+  if (!bytes) return ACAT_ERR_NULL;
+  *bytes = alayout(make_kprob(prob)).total;
+  return ACAT_OK;
+}
+
+acat_status acat_step_adjoint(const acat_problem* prob, const double* u_in, double dt, const double* dt_dev,
+                              const acat_decisions* dec, const double* ubar_out, double* ubar_in, void* workspace,
+                              size_t workspace_bytes, void* stream) {
+  acat_status rc = check_adjoint(prob);
+  if (rc != ACAT_OK) return rc;
+  if (!u_in || !ubar_out || !ubar_in || !dec) return ACAT_ERR_NULL;
+  if (!dec->order_x || !dec->psi1_x || !dec->alpha_x) return ACAT_ERR_NULL;
+  if (prob->dim == 2 && (!dec->order_y || !dec->psi1_y || !dec->alpha_y)) return ACAT_ERR_NULL;
+  if (!dt_dev && !(dt >= 0.0)) return ACAT_ERR_ARG;
+  const KProb k = make_kprob(prob);
+  const size_t state_bytes = sizeof(double) * (size_t)k.nvar * k.nx * k.ny;
+  if (overlaps(u_in, ubar_in, state_bytes)) return ACAT_ERR_ALIAS;
+  if (ubar_in != ubar_out && overlaps(ubar_in, ubar_out, state_bytes)) return ACAT_ERR_ALIAS;
+  const ALayout L = alayout(k);
+  if (!workspace || workspace_bytes < L.total) return ACAT_ERR_WORKSPACE;
+  char* w = static_cast<char*>(workspace);
+  KStep st{};
+  st.u = u_in;
+  st.dt = dt;
+  st.dt_dev = dt_dev;
+  st.ordx = dec->order_x;
+  st.psix = dec->psi1_x;
+  st.alx = dec->alpha_x;
+  st.ordy = dec->order_y;
+  st.psiy = dec->psi1_y;
+  st.aly = dec->alpha_y;
+  st.counts = reinterpret_cast<int32_t*>(w + L.hdr);
+  st.cls = reinterpret_cast<int8_t*>(w + L.cls);
+  st.hist = reinterpret_cast<int32_t*>(w + L.hist);
+  st.offs = reinterpret_cast<int32_t*>(w + L.offs);
+  st.list = reinterpret_cast<int32_t*>(w + L.list);
+  st.status = status_ptr();
+  if (!st.status) return ACAT_ERR_DEVICE;
+  st.replay = 1;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_lists(k, st, s);
+  if (e == hipSuccess) e = launch_adjoint(k, st, ubar_out, ubar_in, reinterpret_cast<double*>(w + L.C), s);
+  return e == hipSuccess ? ACAT_OK : ACAT_ERR_DEVICE;
 }
 
 acat_status acat_max_wave_speed(const acat_problem* prob, const double* u, double* smax_dev, void* stream) {

@@ -38,7 +38,7 @@ struct KStep {
   double* aly;
   double* Fx;             // x-interface fluxes [nvar][ny][nIx] (1D: [nvar][nI])
   double* Gy;             // y-interface fluxes [nvar][nIy][nx]
-  int8_t* cls;            // 2D: order class (q1-1)*P + (q2-1) of every corner [n2][n1]
+  int8_t* cls;            // order class of every item: 1D p-1 per interface; 2D (q1-1)*P + (q2-1) per corner [n2][n1]
   int32_t* hist;          // per-tile class histograms of the classification kernel [tiles][MAX_CLASSES]
   int32_t* offs;          // per-class exclusive prefix of hist over tiles [MAX_CLASSES][tiles + 1]
   int32_t* counts;        // [MAX_CLASSES] items per order class
@@ -63,6 +63,12 @@ struct ProfScope {
 hipError_t launch_step_1d(const KProb& pb, const KStep& st, int grid_blocks, hipStream_t stream);
 hipError_t launch_step_2d(const KProb& pb, const KStep& st, int grid_blocks, hipStream_t stream);
 hipError_t launch_max_speed(const KProb& pb, const double* u, double* smax, hipStream_t stream);
+// classification (replay: recorded orders) and per-class item lists only
+hipError_t launch_lists(const KProb& pb, const KStep& st, hipStream_t stream);
+// adjoint of one step with the decisions and lists in st: ubi = ubo + (dF/du)^T Fbar;
+// C is the per-item contribution buffer [nvar][items][LMAX] (LMAX = 2P in 1D, 4P^2 in 2D)
+hipError_t launch_adjoint(const KProb& pb, const KStep& st, const double* ubo, double* ubi, double* C,
+                          hipStream_t stream);
 hipError_t launch_cfl_dt(const KProb& pb, const double* smax, double cfl, double t_final, double* t_dev,
                          double* dt_dev, hipStream_t stream);
 

@@ -75,6 +75,7 @@ __global__ __launch_bounds__(BLOCK) void k_classify1d(KProb pb, KStep st) {
       st.alx[k] = al;
     }
   }
+  if (valid) st.cls[k] = (int8_t)(ps - 1);
   __shared__ int sh[MAX_CLASSES];
   block_hist(sh, valid, ps - 1, st.hist);
 }
@@ -316,36 +317,6 @@ __global__ __launch_bounds__(BLOCK) void k_classify2d(KProb pb, KStep st) {
   __shared__ int sh[MAX_CLASSES];
   block_hist(sh, valid, cls, st.hist);
 }
-
-// LDS exchange of the time-derivative fluxes of a 2D corner: per node, the
-// NV components of Fh and of Gh stored as double2 pairs in component-major
-// planes (consecutive lanes write consecutive 16-byte words).
-//   NV = 4: planes (F0,F1) (F2,F3) (G0,G1) (G2,G3);   NV = 1: plane (F0,G0)
-template <int NV>
-struct Xch {
-  static constexpr int NP = NV == 1 ? 1 : NV;
-  static __device__ __forceinline__ void put(double2* plane0, int stride, int slot, const double (&f)[NV],
-                                             const double (&g)[NV]) {
-    if constexpr (NV == 1) {
-      plane0[slot] = make_double2(f[0], g[0]);
-    } else {
-#pragma unroll
-      for (int c = 0; c < NV; c += 2) {
-        plane0[(c / 2) * stride + slot] = make_double2(f[c], f[c + 1]);
-        plane0[(NV / 2 + c / 2) * stride + slot] = make_double2(g[c], g[c + 1]);
-      }
-    }
-  }
-  // component c of Fh (G = false) or Gh (G = true) at a slot
-  static __device__ __forceinline__ double get(const double* planes, int stride, int slot, int c, bool G) {
-    if constexpr (NV == 1) {
-      return planes[2 * slot + (G ? 1 : 0)];
-    } else {
-      const int pl = (G ? NV / 2 : 0) + c / 2;
-      return planes[2 * (pl * stride + slot) + (c & 1)];
-    }
-  }
-};
 
 // One recursion over the rectangle J_Q1 x J_Q2 with time nodes J_QT
 // (Taylor order 2 QT).  Each lane is one node (a1, a2) and accumulates the
@@ -647,8 +618,10 @@ hipError_t launch_class1d(const KProb& pb, const KStep& st, int cap, hipStream_t
   return hipSuccess;
 }
 
+// classification (or, in replay, the recorded orders) -> class map, then the
+// per-class item lists
 template <int FLUX, int NV, int P>
-hipError_t step1d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s) {
+hipError_t lists1d_impl(const KProb& pb, const KStep& st, hipStream_t s) {
   const int64_t nI = pb.nIx;
   const int cblocks = (int)((nI + BLOCK - 1) / BLOCK);
   {
@@ -658,9 +631,15 @@ hipError_t step1d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s)
   ACAT_CHECK_LAUNCH();
   k_scan_hist<<<P, BLOCK, 0, s>>>(st.hist, cblocks, st.offs, st.counts);
   ACAT_CHECK_LAUNCH();
-  k_scatter<P><<<cblocks, BLOCK, 0, s>>>(st.ordx, 1, nI, cblocks, st.offs, st.counts, st.list);
+  k_scatter<P><<<cblocks, BLOCK, 0, s>>>(st.cls, 0, nI, cblocks, st.offs, st.counts, st.list);
   ACAT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+template <int FLUX, int NV, int P>
+hipError_t step1d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s) {
   hipError_t e;
+  if ((e = lists1d_impl<FLUX, NV, P>(pb, st, s)) != hipSuccess) return e;
   if ((e = launch_class1d<FLUX, NV, P, 1>(pb, st, cap, s)) != hipSuccess) return e;
   if ((e = launch_class1d<FLUX, NV, P, 2>(pb, st, cap, s)) != hipSuccess) return e;
   if ((e = launch_class1d<FLUX, NV, P, 3>(pb, st, cap, s)) != hipSuccess) return e;
@@ -692,7 +671,7 @@ hipError_t launch_class2d(const KProb& pb, const KStep& st, int cap, hipStream_t
 }
 
 template <int FLUX, int NV, int P>
-hipError_t step2d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s) {
+hipError_t lists2d_impl(const KProb& pb, const KStep& st, hipStream_t s) {
   const int64_t nc = pb.n1 * pb.n2;
   const int cblocks = (int)((nc + BLOCK - 1) / BLOCK);
   {
@@ -704,7 +683,13 @@ hipError_t step2d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s)
   ACAT_CHECK_LAUNCH();
   k_scatter<P * P><<<cblocks, BLOCK, 0, s>>>(st.cls, 0, nc, cblocks, st.offs, st.counts, st.list);
   ACAT_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+template <int FLUX, int NV, int P>
+hipError_t step2d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s) {
   hipError_t e;
+  if ((e = lists2d_impl<FLUX, NV, P>(pb, st, s)) != hipSuccess) return e;
   if ((e = launch_class2d<FLUX, NV, P, 1, 1>(pb, st, cap, s)) != hipSuccess) return e;
   if ((e = launch_class2d<FLUX, NV, P, 1, 2>(pb, st, cap, s)) != hipSuccess) return e;
   if ((e = launch_class2d<FLUX, NV, P, 2, 1>(pb, st, cap, s)) != hipSuccess) return e;
@@ -764,6 +749,46 @@ hipError_t launch_step_2d(const KProb& pb, const KStep& st, int grid_blocks, hip
       case 1: return step2d_impl<ADV, 1, 1>(pb, st, cap, s);
       case 2: return step2d_impl<ADV, 1, 2>(pb, st, cap, s);
       case 3: return step2d_impl<ADV, 1, 3>(pb, st, cap, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_lists(const KProb& pb, const KStep& st, hipStream_t s) {
+  if (pb.dim == 1) {
+    if (pb.flux == EUL) {
+      switch (pb.P) {
+        case 1: return lists1d_impl<EUL, 3, 1>(pb, st, s);
+        case 2: return lists1d_impl<EUL, 3, 2>(pb, st, s);
+        case 3: return lists1d_impl<EUL, 3, 3>(pb, st, s);
+        case 4: return lists1d_impl<EUL, 3, 4>(pb, st, s);
+      }
+    } else if (pb.flux == BURG) {
+      switch (pb.P) {
+        case 1: return lists1d_impl<BURG, 1, 1>(pb, st, s);
+        case 2: return lists1d_impl<BURG, 1, 2>(pb, st, s);
+        case 3: return lists1d_impl<BURG, 1, 3>(pb, st, s);
+        case 4: return lists1d_impl<BURG, 1, 4>(pb, st, s);
+      }
+    } else {
+      switch (pb.P) {
+        case 1: return lists1d_impl<ADV, 1, 1>(pb, st, s);
+        case 2: return lists1d_impl<ADV, 1, 2>(pb, st, s);
+        case 3: return lists1d_impl<ADV, 1, 3>(pb, st, s);
+        case 4: return lists1d_impl<ADV, 1, 4>(pb, st, s);
+      }
+    }
+  } else if (pb.flux == EUL) {
+    switch (pb.P) {
+      case 1: return lists2d_impl<EUL, 4, 1>(pb, st, s);
+      case 2: return lists2d_impl<EUL, 4, 2>(pb, st, s);
+      case 3: return lists2d_impl<EUL, 4, 3>(pb, st, s);
+    }
+  } else if (pb.flux == ADV) {
+    switch (pb.P) {
+      case 1: return lists2d_impl<ADV, 1, 1>(pb, st, s);
+      case 2: return lists2d_impl<ADV, 1, 2>(pb, st, s);
+      case 3: return lists2d_impl<ADV, 1, 3>(pb, st, s);
     }
   }
   return hipErrorInvalidValue;

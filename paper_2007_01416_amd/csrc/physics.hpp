@@ -78,6 +78,71 @@ __device__ __forceinline__ void flux2d(const Phys& ph, const double (&u)[NV], do
   }
 }
 
+// Jacobian-transpose products (adjoint of flux1d): ub += f'(u)^T fb
+template <int FLUX, int NV>
+__device__ __forceinline__ void flux1d_vjp(const Phys& ph, const double (&u)[NV], const double (&fb)[NV],
+                                           double (&ub)[NV]) {
+  if constexpr (FLUX == ADV) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) ub[c] += ph.ax * fb[c];
+  } else if constexpr (FLUX == BURG) {
+    ub[0] += u[0] * fb[0];
+  } else {
+    // f = (m, m v + p, v (E + p)), v = m / rho, p = (gamma-1)(E - m v / 2)
+    const double rho = u[0], m = u[1], E = u[2];
+    const double v = m / rho;
+    const double p = ph.gm1 * (E - 0.5 * (m * v));
+    double mb = fb[0] + fb[1] * v, vb = fb[1] * m + fb[2] * (E + p);
+    const double epb = fb[2] * v;
+    double Eb = epb;
+    const double pb = fb[1] + epb;
+    Eb += ph.gm1 * pb;
+    const double q = ph.gm1 * pb;
+    mb -= 0.5 * q * v;
+    vb -= 0.5 * q * m;
+    mb += vb / rho;
+    ub[0] += -vb * v / rho;
+    ub[1] += mb;
+    ub[2] += Eb;
+  }
+}
+
+// adjoint of flux2d: ub += f'(u)^T fb + g'(u)^T gb
+template <int FLUX, int NV>
+__device__ __forceinline__ void flux2d_vjp(const Phys& ph, const double (&u)[NV], const double (&fb)[NV],
+                                           const double (&gb)[NV], double (&ub)[NV]) {
+  if constexpr (FLUX == ADV) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) ub[c] += ph.ax * fb[c] + ph.ay * gb[c];
+  } else {
+    const double rho = u[0], m = u[1], n = u[2], E = u[3];
+    const double ir = 1.0 / rho;
+    const double v = m * ir, w = n * ir;
+    const double p = ph.gm1 * (E - 0.5 * (m * v + n * w));
+    const double ep = E + p;
+    // f = (m, m v + p, n v, v ep), g = (n, m w, n w + p, w ep)
+    double mb = fb[0] + fb[1] * v + gb[1] * w;
+    double nb = gb[0] + fb[2] * v + gb[2] * w;
+    double vb = fb[1] * m + fb[2] * n + fb[3] * ep;
+    double wb = gb[1] * m + gb[2] * n + gb[3] * ep;
+    const double epb = fb[3] * v + gb[3] * w;
+    const double pb = fb[1] + gb[2] + epb;
+    double Eb = epb + ph.gm1 * pb;
+    const double q = ph.gm1 * pb;
+    mb -= 0.5 * q * v;
+    vb -= 0.5 * q * m;
+    nb -= 0.5 * q * w;
+    wb -= 0.5 * q * n;
+    mb += vb * ir;
+    nb += wb * ir;
+    const double irb = vb * m + wb * n;
+    ub[0] += -irb * ir * ir;
+    ub[1] += mb;
+    ub[2] += nb;
+    ub[3] += Eb;
+  }
+}
+
 // spectral radius of the flux Jacobian in direction d (0: x, 1: y)
 template <int FLUX, int DIM, int NV>
 __device__ __forceinline__ double spectral_radius(const Phys& ph, const double (&u)[NV], int d) {

@@ -206,4 +206,35 @@ int persistent_grid(K kernel, int64_t nitems, int cap) {
 }
 
 }  // namespace
+
+// LDS exchange of the time-derivative fluxes of a 2D corner: per node, the
+// NV components of Fh and of Gh stored as double2 pairs in component-major
+// planes (consecutive lanes write consecutive 16-byte words).
+//   NV = 4: planes (F0,F1) (F2,F3) (G0,G1) (G2,G3);   NV = 1: plane (F0,G0)
+template <int NV>
+struct Xch {
+  static constexpr int NP = NV == 1 ? 1 : NV;
+  static __device__ __forceinline__ void put(double2* plane0, int stride, int slot, const double (&f)[NV],
+                                             const double (&g)[NV]) {
+    if constexpr (NV == 1) {
+      plane0[slot] = make_double2(f[0], g[0]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < NV; c += 2) {
+        plane0[(c / 2) * stride + slot] = make_double2(f[c], f[c + 1]);
+        plane0[(NV / 2 + c / 2) * stride + slot] = make_double2(g[c], g[c + 1]);
+      }
+    }
+  }
+  // component c of Fh (G = false) or Gh (G = true) at a slot
+  static __device__ __forceinline__ double get(const double* planes, int stride, int slot, int c, bool G) {
+    if constexpr (NV == 1) {
+      return planes[2 * slot + (G ? 1 : 0)];
+    } else {
+      const int pl = (G ? NV / 2 : 0) + c / 2;
+      return planes[2 * (pl * stride + slot) + (c & 1)];
+    }
+  }
+};
+
 }  // namespace acat

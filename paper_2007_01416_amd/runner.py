@@ -5,12 +5,21 @@ Each step is: acat_max_wave_speed -> acat_cfl_dt (dt and t stay on the
 device) -> acat_step.  Nothing synchronises with the host, so a block of
 steps can be captured once into a HIP graph (torch.cuda.CUDAGraph drives
 hipStreamBeginCapture on its capture stream) and replayed.
+
+AdjointRun / ACATRun: gradients of a function of the final state of an
+n-step run with respect to the initial state, through acat_step_adjoint,
+with the decisions of every step (orders, psi^1, alpha) and its time step
+frozen at the forward run's values.  The forward keeps a state checkpoint
+every k steps; the backward recomputes each k-step segment from its
+checkpoint (recording decisions and time steps) and runs the adjoint steps
+of the segment in reverse.
 """
 from __future__ import annotations
 
 import torch
 
-from . import (Batch, Decisions, Problem, cfl_dt, max_wave_speed, step, step_replay, workspace)
+from . import (Batch, Decisions, Problem, adjoint_workspace, cfl_dt, max_wave_speed, step, step_adjoint,
+               step_replay, workspace)
 
 
 class Solver:
@@ -143,3 +152,119 @@ class BatchSolver:
             self.graph.replay()
             self.nsteps += self.graph_steps
         return self.u
+
+
+def _order_hash(dec: Decisions) -> torch.Tensor:
+    """Device checksum of a step's order maps (position-weighted sum)."""
+    h = None
+    for t in (dec.order_x, dec.order_y):
+        if t is None:
+            continue
+        v = t.reshape(-1).to(torch.int64)
+        w = torch.arange(1, v.numel() + 1, device=v.device, dtype=torch.int64) % 8191 + 1
+        s = (v * w).sum()
+        h = s if h is None else h * 1000003 + s
+    return h
+
+
+class AdjointRun:
+    """n CFL steps of one problem with a reverse pass.
+
+    forward(u0) -> u_n keeps u every `checkpoint_every` steps (and, with
+    record_all, the decisions of every step for replay()).  backward(ubar_n)
+    -> ubar_0 = (d u_n / d u0)^T ubar_n with the decisions and time steps of
+    the forward run frozen; segments are recomputed from their checkpoints.
+    With verify, the order maps of the recomputation are checked against
+    checksums taken in the forward pass.
+    """
+
+    def __init__(self, prob: Problem, cfl: float, nsteps: int, checkpoint_every: int = 20,
+                 record_all: bool = False, verify: bool = True, device="cuda"):
+        if nsteps < 1 or checkpoint_every < 1:
+            raise ValueError("nsteps and checkpoint_every must be >= 1")
+        self.prob, self.cfl, self.nsteps, self.k = prob, float(cfl), int(nsteps), int(checkpoint_every)
+        self.device = device
+        self.ws = workspace(prob, device)
+        self.aws = adjoint_workspace(prob, device)
+        self.smax = torch.zeros(2, dtype=torch.float64, device=device)
+        self.dts = torch.zeros(self.nsteps, dtype=torch.float64, device=device)
+        self.seg_dec = [Decisions(prob, device) for _ in range(min(self.k, self.nsteps))]
+        self.seg_u = [torch.empty(prob.shape, dtype=torch.float64, device=device)
+                      for _ in range(min(self.k, self.nsteps))]
+        self.record_all = record_all
+        self.all_dec = [Decisions(prob, device) for _ in range(self.nsteps)] if record_all else None
+        self.verify = verify
+        self.hashes = torch.zeros(self.nsteps, dtype=torch.int64, device=device) if verify else None
+        self.tmp = torch.empty(prob.shape, dtype=torch.float64, device=device)
+        self.checkpoints = []
+
+    def _step(self, u, out, n, dec):
+        max_wave_speed(self.prob, u, self.smax)
+        cfl_dt(self.prob, self.smax, self.cfl, self.dts[n:n + 1])
+        step(self.prob, u, self.dts[n:n + 1], out=out, ws=self.ws, dec=dec)
+
+    def forward(self, u0: torch.Tensor) -> torch.Tensor:
+        u = torch.as_tensor(u0, dtype=torch.float64, device=self.device).contiguous().clone()
+        nxt = torch.empty_like(u)
+        self.checkpoints = []
+        for n in range(self.nsteps):
+            if n % self.k == 0:
+                self.checkpoints.append(u.clone())
+            dec = self.all_dec[n] if self.record_all else (self.seg_dec[0] if self.verify else None)
+            self._step(u, nxt, n, dec)
+            if self.verify:
+                self.hashes[n] = _order_hash(dec)
+            u, nxt = nxt, u
+        return u
+
+    def replay(self, u0: torch.Tensor) -> torch.Tensor:
+        """The frozen forward map (decisions and time steps of the last
+        forward run); needs record_all."""
+        if not self.record_all:
+            raise RuntimeError("replay needs record_all=True")
+        u = torch.as_tensor(u0, dtype=torch.float64, device=self.device).contiguous().clone()
+        nxt = torch.empty_like(u)
+        for n in range(self.nsteps):
+            step_replay(self.prob, u, self.dts[n:n + 1], self.all_dec[n], out=nxt, ws=self.ws)
+            u, nxt = nxt, u
+        return u
+
+    def backward(self, ubar: torch.Tensor) -> torch.Tensor:
+        if not self.checkpoints:
+            raise RuntimeError("backward before forward")
+        ub = torch.as_tensor(ubar, dtype=torch.float64, device=self.device).contiguous().clone()
+        dts = torch.zeros(self.nsteps, dtype=torch.float64, device=self.device)
+        hashes = torch.zeros_like(self.hashes) if self.verify else None
+        for s in reversed(range(len(self.checkpoints))):
+            n0 = s * self.k
+            m = min(self.k, self.nsteps - n0)
+            u = self.seg_u[0]
+            u.copy_(self.checkpoints[s])
+            for j in range(m):
+                out = self.seg_u[j + 1] if j + 1 < m else self.tmp   # the segment's last state is not needed
+                max_wave_speed(self.prob, self.seg_u[j], self.smax)
+                cfl_dt(self.prob, self.smax, self.cfl, dts[n0 + j:n0 + j + 1])
+                step(self.prob, self.seg_u[j], dts[n0 + j:n0 + j + 1], out=out, ws=self.ws, dec=self.seg_dec[j])
+                if self.verify:
+                    hashes[n0 + j] = _order_hash(self.seg_dec[j])
+            for j in reversed(range(m)):
+                step_adjoint(self.prob, self.seg_u[j], dts[n0 + j:n0 + j + 1], self.seg_dec[j], ub, ubar_in=ub,
+                             ws=self.aws)
+        if self.verify:
+            if not torch.equal(hashes, self.hashes) or not torch.equal(dts, self.dts):
+                raise RuntimeError("recomputed decisions differ from the forward run")
+        return ub
+
+
+class ACATRun(torch.autograd.Function):
+    """u_n = ACATRun.apply(u0, run): the n-step forward of an AdjointRun, with
+    its checkpointed adjoint as the backward."""
+
+    @staticmethod
+    def forward(ctx, u0, run: AdjointRun):
+        ctx.run = run
+        return run.forward(u0.detach())
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        return ctx.run.backward(grad_out.contiguous()), None

@@ -130,3 +130,39 @@ def test_batch_validation(lib, n, P, bc, dx, code):
         ws = ctypes.create_string_buffer(nb.value)
         assert lib.acat_step_batched(ctypes.byref(b), None, None, None, ws, nb.value, None) == -1
         assert lib.acat_step_batched(ctypes.byref(b), ws, ws, ws, ws, 16, None) == -6
+
+
+def test_adjoint_argument_errors_before_launch(lib):
+    import paper_2007_01416_amd as acat
+    p = _prob()
+    pc = p.c()
+    n = ctypes.c_size_t(0)
+    assert lib.acat_adjoint_workspace_size(ctypes.byref(pc), ctypes.byref(n)) == 0
+    # the contribution buffer dominates: nvar * interfaces * 2P doubles
+    assert n.value >= 8 * 3 * 64 * 4
+    # 2D transmissive has no adjoint kernel
+    p2 = _prob(dim=2, nvar=4, ny=32, dy=0.1, bc="transmissive")
+    assert lib.acat_adjoint_workspace_size(ctypes.byref(p2.c()), ctypes.byref(n)) == -4
+    assert lib.acat_adjoint_workspace_size(ctypes.byref(_prob(P=5).c()), ctypes.byref(n)) == -2
+    ub = (ctypes.c_double * (3 * 64))()
+    ub2 = (ctypes.c_double * (3 * 64))()
+    u = (ctypes.c_double * (3 * 64))()
+    a, b, c = (ctypes.cast(x, ctypes.c_void_p) for x in (u, ub, ub2))
+    o = (ctypes.c_int8 * 64)()
+    d = (ctypes.c_double * 64)()
+    dec = acat._Decisions(ctypes.cast(o, ctypes.c_void_p), ctypes.cast(d, ctypes.c_void_p),
+                          ctypes.cast(d, ctypes.c_void_p), None, None, None)
+    ws = ctypes.create_string_buffer(16)
+    adj = lib.acat_step_adjoint
+    assert adj(ctypes.byref(pc), a, 0.1, None, None, b, c, ws, 16, None) == -1            # no decisions
+    nodec = acat._Decisions(None, None, None, None, None, None)
+    assert adj(ctypes.byref(pc), a, 0.1, None, ctypes.byref(nodec), b, c, ws, 16, None) == -1
+    assert adj(ctypes.byref(pc), a, 0.1, None, ctypes.byref(dec), None, c, ws, 16, None) == -1
+    assert adj(ctypes.byref(pc), a, -1.0, None, ctypes.byref(dec), b, c, ws, 16, None) == -2
+    assert adj(ctypes.byref(pc), a, 0.1, None, ctypes.byref(dec), b, a, ws, 16, None) == -3   # ubar_in over u
+    half = ctypes.c_void_p(ctypes.addressof(ub) + 8 * 10)
+    assert adj(ctypes.byref(pc), a, 0.1, None, ctypes.byref(dec), b, half, ws, 16, None) == -3
+    assert adj(ctypes.byref(pc), a, 0.1, None, ctypes.byref(dec), b, c, ws, 16, None) == -6   # workspace
+    # 2D needs the y decisions too
+    p2 = _prob(dim=2, nvar=4, nx=16, ny=16, dy=0.1)
+    assert adj(ctypes.byref(p2.c()), a, 0.1, None, ctypes.byref(dec), b, c, ws, 16, None) == -1

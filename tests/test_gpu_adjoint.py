@@ -1,0 +1,242 @@
+"""GPU adjoint (acat_step_adjoint, AdjointRun / ACATRun) against the oracle.
+
+Per step, element by element: the kernel's ubar_in = J^T ubar_out against
+the oracle's dense adjoint (J assembled column by column from the oracle's
+dual-number JVP of the frozen replay step), with the decisions taken from
+the oracle's own step.  Bound: max |gpu - oracle| <= 1e-11 max |oracle|
+(the two sum the same products in different orders; the Jacobian entries
+are O(1) and the sums have at most a few hundred terms).
+
+At the adjoint workload's size (2D Euler 512^2, P = 2): the inner product
+<J^T w, v> against the oracle's <w, J v> (<= 1e-10 relative), and central
+finite differences of the GPU replay step (<= 1e-6 relative).  Over many
+steps: the checkpointed ACATRun gradient against the oracle's tangent run
+and against finite differences of the frozen replay run.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from gpu_helpers import both_problems, from_workload
+
+pytestmark = pytest.mark.gpu
+
+TOL_DENSE = 1e-11
+TOL_JVP = 1e-10
+TOL_FD = 1e-6
+
+
+def gpu_decisions(acat, pg, po, r):
+    dec = acat.Decisions(pg)
+    names = ("order", "psi1", "alpha") if po.dim == 1 else ("ordx", "psix", "alx", "ordy", "psiy", "aly")
+    dst = (dec.order_x, dec.psi1_x, dec.alpha_x) if po.dim == 1 else \
+        (dec.order_x, dec.psi1_x, dec.alpha_x, dec.order_y, dec.psi1_y, dec.alpha_y)
+    for n, t in zip(names, dst):
+        t.copy_(torch.from_numpy(np.ascontiguousarray(r[n])))
+    return dec
+
+
+def smooth_2d(n, jump=True, amp=0.2):
+    """Smooth periodic Euler state on [0,1]^2 with an x-band of higher
+    density: at n = 24 and P = 3 every order class (q1, q2) occurs."""
+    x = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    rho = 1 + amp * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)
+    v = 0.3 + 0.1 * np.sin(2 * np.pi * Y)
+    w = -0.2 + 0.1 * np.cos(2 * np.pi * X)
+    p = 1 + 0.1 * np.sin(2 * np.pi * (X + Y))
+    if jump:
+        rho = rho + 0.5 * ((X > 0.4) & (X < 0.7))
+    E = p / 0.4 + 0.5 * rho * (v * v + w * w)
+    return np.stack([rho, rho * v, rho * w, E])
+
+
+def dense_case(acat, po, pg, u, dt, seed=0):
+    r = oracle.step1d(po, u, dt) if po.dim == 1 else oracle.step2d(po, u, dt)
+    maps = oracle.maps_of(po, r)
+    ub = np.random.default_rng(seed).standard_normal(u.shape)
+    want = oracle.vjp_dense(po, u, ub, dt, maps)
+    dec = gpu_decisions(acat, pg, po, r)
+    ug = torch.from_numpy(np.ascontiguousarray(u)).cuda()
+    got = acat.step_adjoint(pg, ug, dt, dec, torch.from_numpy(ub).cuda()).cpu().numpy()
+    return got, want, r
+
+
+def orders_seen(po, r):
+    if po.dim == 1:
+        return set(np.unique(r["order"]).tolist())
+    return set(zip(r["ordx"].ravel().tolist(), r["ordy"].ravel().tolist()))
+
+
+@pytest.mark.parametrize("P", [2, 3, 4])
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+def test_adjoint_1d_euler_matches_dense_oracle(acat, P, bc):
+    w = workloads.euler_1d(n=32, P=P)
+    po, pg = from_workload(w, bc=bc)
+    dt = oracle.dt_cfl(po, w["u"], 0.5)
+    got, want, r = dense_case(acat, po, pg, w["u"], dt, seed=P)
+    assert orders_seen(po, r) >= {1, P}
+    err = np.abs(got - want).max()
+    print(f"1D euler P={P} {bc}: max err {err:.3e} (scale {np.abs(want).max():.3e})", flush=True)
+    assert err <= TOL_DENSE * np.abs(want).max()
+
+
+@pytest.mark.parametrize("flux,P,bc", [("burgers", 3, "transmissive"), ("burgers", 4, "periodic"),
+                                       ("advection", 2, "periodic"), ("advection", 3, "transmissive")])
+def test_adjoint_1d_scalar_matches_dense_oracle(acat, flux, P, bc):
+    n = 32
+    rng = np.random.default_rng(P)
+    x = (np.arange(n) + 0.5) / n
+    u = (np.sin(2 * np.pi * x) + 0.5 * (x > 0.5) + 0.01 * rng.standard_normal(n))[None, :]
+    po, pg = both_problems(1, 1, n, flux, P, bc, 1.0 / n, ax=0.7)
+    dt = oracle.dt_cfl(po, u, 0.5)
+    got, want, _ = dense_case(acat, po, pg, u, dt, seed=P + 10)
+    assert np.abs(got - want).max() <= TOL_DENSE * np.abs(want).max()
+
+
+@pytest.mark.parametrize("P", [2, 3])
+def test_adjoint_2d_euler_matches_dense_oracle(acat, P):
+    n = 24
+    u = smooth_2d(n)
+    po, pg = both_problems(2, 4, n, "euler", P, "periodic", 1.0 / n, ny=n, dy=1.0 / n)
+    dt = oracle.dt_cfl(po, u, 0.4)
+    got, want, r = dense_case(acat, po, pg, u, dt, seed=20 + P)
+    if P == 3:
+        assert len(orders_seen(po, r)) == 9      # every corner class (q1, q2)
+    err = np.abs(got - want).max()
+    print(f"2D euler P={P}: max err {err:.3e} (scale {np.abs(want).max():.3e})", flush=True)
+    assert err <= TOL_DENSE * np.abs(want).max()
+
+
+def test_adjoint_2d_advection_matches_dense_oracle(acat):
+    n = 16
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal((1, n, n))
+    po, pg = both_problems(2, 1, n, "advection", 3, "periodic", 0.1, ny=n, dy=0.12, ax=0.8, ay=-0.5)
+    dt = oracle.dt_cfl(po, u, 0.4)
+    got, want, _ = dense_case(acat, po, pg, u, dt, seed=7)
+    assert np.abs(got - want).max() <= TOL_DENSE * np.abs(want).max()
+
+
+def test_adjoint_in_place_device_dt_and_zero_dt(acat):
+    n = 24
+    u = smooth_2d(n)
+    po, pg = both_problems(2, 4, n, "euler", 3, "periodic", 1.0 / n, ny=n, dy=1.0 / n)
+    dt = oracle.dt_cfl(po, u, 0.4)
+    r = oracle.step2d(po, u, dt)
+    dec = gpu_decisions(acat, pg, po, r)
+    ug = torch.from_numpy(u).cuda()
+    ub = torch.from_numpy(np.random.default_rng(1).standard_normal(u.shape)).cuda()
+    ref = acat.step_adjoint(pg, ug, dt, dec, ub)
+    dt_dev = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    inplace = ub.clone()
+    acat.step_adjoint(pg, ug, dt_dev, dec, inplace, ubar_in=inplace)
+    assert torch.equal(inplace, ref)
+    # dt = 0: the step is the identity, and so is its adjoint
+    assert torch.equal(acat.step_adjoint(pg, ug, 0.0, dec, ub), ub)
+    # deterministic: a second call gives the same bits
+    assert torch.equal(acat.step_adjoint(pg, ug, dt, dec, ub), ref)
+    assert acat.device_status() == 0
+
+
+def test_adjoint_1d_bad_recorded_order_is_flagged(acat):
+    w = workloads.euler_1d(n=32, P=3)
+    po, pg = from_workload(w)
+    dt = oracle.dt_cfl(po, w["u"], 0.5)
+    r = oracle.step1d(po, w["u"], dt)
+    dec = gpu_decisions(acat, pg, po, r)
+    dec.order_x[5] = 7                       # outside 1..P: taken as 1, flagged
+    ug = torch.from_numpy(w["u"]).cuda()
+    out = acat.step_adjoint(pg, ug, dt, dec, torch.ones_like(ug))
+    assert torch.isfinite(out).all()
+    assert acat.device_status() & 4
+
+
+# ---------------------------------------------------------------- C5 scale
+@pytest.fixture(scope="module")
+def c5():
+    return workloads.adjoint_2d()
+
+
+def test_adjoint_step_c5_inner_product_and_fd(acat, c5):
+    w = c5
+    po, pg = from_workload(w)
+    u = w["u"]
+    dt = oracle.dt_cfl(po, u, w["cfl"])
+    r = oracle.step2d(po, u, dt, nthreads=16)
+    maps = oracle.maps_of(po, r)
+    dec = gpu_decisions(acat, pg, po, r)
+    rng = np.random.default_rng(11)
+    wb = rng.standard_normal(u.shape)
+    ug = torch.from_numpy(u).cuda()
+    adj = acat.step_adjoint(pg, ug, dt, dec, torch.from_numpy(wb).cuda()).cpu().numpy()
+    for k in range(2):
+        v = w["directions"](k)
+        lhs = float(np.vdot(adj, v))
+        rhs = float(np.vdot(wb, oracle.jvp(po, u, v, dt, maps, nthreads=16)[1]))
+        assert abs(lhs - rhs) <= TOL_JVP * abs(rhs), (k, lhs, rhs)
+        h = 1e-6
+        vg = torch.from_numpy(v).cuda()
+        up = acat.step_replay(pg, ug + h * vg, dt, dec).cpu().numpy()
+        um = acat.step_replay(pg, ug - h * vg, dt, dec).cpu().numpy()
+        fd = float(np.vdot(wb, (up - um) / (2 * h)))
+        assert abs(fd - lhs) <= TOL_FD * abs(lhs), (k, fd, lhs)
+
+
+def misfit_grad(w, u_T, rho_star):
+    """dL/du_T of L = 1/2 dx dy sum (rho_T - rho*_T)^2."""
+    g = torch.zeros_like(u_T)
+    g[0] = w["dx"] * w["dy"] * (u_T[0] - rho_star)
+    return g
+
+
+@pytest.mark.parametrize("n,nsteps,k", [(64, 12, 5), (64, 10, 10)])
+def test_checkpointed_run_matches_oracle_tangent(acat, n, nsteps, k):
+    """Gradient of a misfit after nsteps through ACATRun (checkpoint every k)
+    against the oracle's tangent run along two directions."""
+    w = workloads.adjoint_2d(n=n)
+    po, pg = from_workload(w)
+    uT_o, _, _, hist = oracle.run(po, w["u"], w["cfl"], nsteps=nsteps, nthreads=16, record=True)
+    star = oracle.run(po, w["target_u0"], w["cfl"], nsteps=nsteps, nthreads=16)[0][0]
+    run = acat.AdjointRun(pg, w["cfl"], nsteps, checkpoint_every=k)
+    u0 = torch.from_numpy(w["u"]).cuda().requires_grad_(True)
+    uT = acat.ACATRun.apply(u0, run)
+    assert torch.equal(uT.detach().cpu(), torch.from_numpy(uT_o))     # forward: bitwise
+    loss = 0.5 * w["dx"] * w["dy"] * ((uT[0] - torch.from_numpy(star).cuda()) ** 2).sum()
+    loss.backward()
+    grad = u0.grad.cpu().numpy()
+    gT = misfit_grad(w, torch.from_numpy(uT_o), torch.from_numpy(star)).numpy()
+    for j in range(2):
+        v = w["directions"](j)
+        dv = v.copy()
+        for hstep in hist:
+            dv = oracle.jvp(po, hstep["u"], dv, hstep["dt"], oracle.maps_of(po, hstep), nthreads=16)[1]
+        rhs = float(np.vdot(gT, dv))
+        lhs = float(np.vdot(grad, v))
+        assert abs(lhs - rhs) <= TOL_JVP * abs(rhs), (j, lhs, rhs)
+
+
+def test_checkpointed_run_matches_fd_of_replay(acat):
+    """ACATRun gradient against central differences of the frozen replay run
+    (decisions and time steps of the forward run), 4 directions."""
+    w = workloads.adjoint_2d(n=128)
+    po, pg = from_workload(w)
+    nsteps = 20
+    star = torch.from_numpy(oracle.run(po, w["target_u0"], w["cfl"], nsteps=nsteps, nthreads=16)[0][0]).cuda()
+    run = acat.AdjointRun(pg, w["cfl"], nsteps, checkpoint_every=5, record_all=True)
+    u0 = torch.from_numpy(w["u"]).cuda()
+    uT = run.forward(u0)
+    gT = misfit_grad(w, uT, star)
+    grad = run.backward(gT)
+
+    def loss(u):
+        return 0.5 * w["dx"] * w["dy"] * float(((u[0] - star) ** 2).sum())
+
+    for j in range(4):
+        v = torch.from_numpy(w["directions"](j)).cuda()
+        ad = float((grad * v).sum())
+        best = min(abs((loss(run.replay(u0 + h * v)) - loss(run.replay(u0 - h * v))) / (2 * h) - ad)
+                   for h in (1e-4, 1e-5, 1e-6))
+        assert best <= TOL_FD * abs(ad), (j, best, ad)

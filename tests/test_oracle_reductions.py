@@ -111,3 +111,39 @@ def test_jvp_matches_central_difference_1d(P):
     um = oracle.step1d(pb, u - h * d, dt, order=maps[0], psi1=maps[1], alpha=maps[2])["u"]
     fd = (up - um) / (2 * h)
     assert np.abs(fd - jv).max() < 1e-7 * np.abs(jv).max()
+
+
+@pytest.mark.parametrize("P", [2, 3, 4])
+def test_vjp_of_periodic_advection_is_reversed_advection(P):
+    """Linear advection, periodic, every interface frozen at order P: the
+    step is u -> A u with A circulant and centred, so A^T is the same step
+    with the speed reversed (mirror symmetry of the order-2P Lax-Wendroff
+    stencil).  Pins the transpose the dense oracle adjoint assembles."""
+    n = 24
+    rng = np.random.default_rng(P)
+    pb = prob1d(n, ADV, P, dx=0.1, ax=1.3)
+    pr = prob1d(n, ADV, P, dx=0.1, ax=-1.3)
+    u = rng.standard_normal((1, n))
+    ub = rng.standard_normal((1, n))
+    dt = 0.6 * 0.1 / 1.3
+    maps = (np.full(n, P, np.int8), np.full(n, -1.0), np.full(n, -1.0))
+    got = oracle.vjp_dense(pb, u, ub, dt, maps)
+    want = oracle.step1d(pr, ub, dt, order=maps[0], psi1=maps[1], alpha=maps[2])["u"]
+    assert np.abs(got - want).max() < 1e-13
+
+
+def test_vjp_dense_inner_product_euler_2d():
+    """<J^T w, v> = <w, J v> for the dense oracle adjoint of a frozen 2D
+    Euler step with mixed orders."""
+    import workloads
+    rng = np.random.default_rng(5)
+    w = workloads.euler_2d(n=12, P=2)
+    pb = oracle.Problem(dim=2, nvar=4, nx=12, ny=12, flux=EUL, P=2, bc=0, dx=w["dx"], dy=w["dy"])
+    u = w["u"]
+    dt = oracle.dt_cfl(pb, u, 0.4)
+    maps = oracle.maps_of(pb, oracle.step2d(pb, u, dt))
+    wb = rng.standard_normal(u.shape)
+    v = rng.standard_normal(u.shape)
+    lhs = np.vdot(oracle.vjp_dense(pb, u, wb, dt, maps), v)
+    rhs = np.vdot(wb, oracle.jvp(pb, u, v, dt, maps)[1])
+    assert abs(lhs - rhs) < 1e-11 * abs(rhs)
