@@ -108,6 +108,102 @@ def bench_batched(acat, workloads, steps_batched=500, steps_single=10):
             "per_instance_ms_per_step": 1e3 * ts / steps_single, "speedup_vs_per_instance": vb / vs}
 
 
+def bench_adjoint(acat, workloads, F, fd_dirs=32, fd_h=(1e-4, 1e-5, 1e-6, 1e-7, 1e-8)):
+    """2D Euler 512^2 P=2: gradient of the final-density misfit after 200
+    steps w.r.t. the initial state (checkpoint every 20, recomputation),
+    timed against the plain 200-step forward; central differences of the
+    frozen replay run on seeded smooth directions with an h sweep."""
+    import numpy as np
+    import torch
+    w = workloads.adjoint_2d()
+    n = w["u"].shape[-1]
+    nsteps, k, cfl = w["nsteps"], w["checkpoint_every"], w["cfl"]
+    pg = acat.Problem(dim=2, nvar=4, nx=n, ny=n, flux="euler", P=w["P"], bc="periodic", dx=w["dx"], dy=w["dy"],
+                      gamma=w["gamma"])
+    u0 = torch.from_numpy(w["u"]).cuda()
+    star = acat.AdjointRun(pg, cfl, nsteps, k, verify=False).forward(torch.from_numpy(w["target_u0"]).cuda())[0]
+    area = w["dx"] * w["dy"]
+
+    def grad_T(uT):
+        g = torch.zeros_like(uT)
+        g[0] = area * (uT[0] - star)
+        return g
+
+    def loss(u):
+        return 0.5 * area * float(((u[0] - star) ** 2).sum())
+
+    # plain forward: the same steps with no checkpoints or recording
+    plain = acat.Solver(pg, w["u"], cfl)
+    plain.run(4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain.run(nsteps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    # checkpointed forward + backward
+    run = acat.AdjointRun(pg, cfl, nsteps, k, verify=False)
+    run.backward(grad_T(run.forward(u0)))         # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    uT = run.forward(u0)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    gT = grad_T(uT)
+    run.class_log = torch.zeros((nsteps, 16), dtype=torch.int32, device="cuda")
+    acat.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grad = run.backward(gT)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    prof = acat.profile_read()
+    acat.profile(False)
+    hist = run.class_log.cpu().numpy().astype(np.int64).sum(0)
+    P = w["P"]
+    kern = {}
+    for q1 in range(1, P + 1):
+        for q2 in range(1, P + 1):
+            name = f"adjoint2d_q{q1}{q2}"
+            if name in prof:
+                c, ms = prof[name]
+                kern[name] = dict(launches=c, ms=ms, flops=int(hist[(q1 - 1) * P + (q2 - 1)]) *
+                                  F.adjoint_corner_flops_2d(q1, q2))
+    dom = max(kern, key=lambda x: kern[x]["ms"])
+    achieved = kern[dom]["flops"] / (kern[dom]["ms"] * 1e-3) / 1e12
+    # verified run (recomputed order maps and time steps checked) recording every step for the replay map
+    vrun = acat.AdjointRun(pg, cfl, nsteps, k, record_all=True, verify=True)
+    uT2 = vrun.forward(u0)
+    grad2 = vrun.backward(grad_T(uT2))
+    deterministic = bool(torch.equal(grad, grad2))
+    t0 = time.perf_counter()
+    errs, per_h = [], {h: [] for h in fd_h}
+    for j in range(fd_dirs):
+        if j % 8 == 0:
+            print(f"[bench] adjoint finite differences: direction {j}/{fd_dirs}", file=sys.stderr, flush=True)
+        v = torch.from_numpy(w["directions"](j)).cuda()
+        ad = float((grad2 * v).sum())
+        rel = []
+        for h in fd_h:
+            fd = (loss(vrun.replay(u0 + h * v)) - loss(vrun.replay(u0 - h * v))) / (2 * h)
+            r = abs(fd - ad) / abs(ad)
+            per_h[h].append(r)
+            rel.append(r)
+        errs.append(min(rel))
+    t_fd = time.perf_counter() - t0
+    return {"workload": f"2D Euler {n}x{n} P={P} periodic, {nsteps} steps, CFL {cfl}, loss 1/2 dx dy sum "
+                        f"(rho_T - rho*_T)^2, gradient w.r.t. all of u0, checkpoint every {k}",
+            "forward_plain_ms": 1e3 * t_plain, "forward_checkpointed_ms": 1e3 * t_fwd, "backward_ms": 1e3 * t_bwd,
+            "adjoint_over_forward": t_bwd / t_plain,
+            "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                         "avg_launch_us": 1e3 * kern[dom]["ms"] / kern[dom]["launches"]},
+            "adjoint_kernels_ms": {x: round(v["ms"], 3) for x, v in kern.items()},
+            "loss": loss(uT), "grad_deterministic": deterministic,
+            "fd_check": {"directions": fd_dirs, "h": list(fd_h), "max_rel_err_best_h": max(errs),
+                         "median_rel_err_by_h": {f"{h:.0e}": float(np.median(per_h[h])) for h in fd_h},
+                         "seconds": t_fd}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +212,7 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and adjoint workloads")
+    ap.add_argument("--fd-dirs", type=int, default=32, help="finite-difference directions of the adjoint check")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         sys.exit("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus must be 1)")
@@ -194,8 +291,12 @@ def main():
         "device_status": flags,
     }
     if not args.no_extra:
+        print("[bench] batched 1D workload", file=sys.stderr, flush=True)
         out["batched"] = bench_batched(acat, workloads)
+        print("[bench] adjoint workload", file=sys.stderr, flush=True)
+        out["adjoint"] = bench_adjoint(acat, workloads, F, fd_dirs=args.fd_dirs)
     if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
 

@@ -568,10 +568,11 @@ __global__ __launch_bounds__(BLOCK) void k_gather2d(KProb pb, KStep st, const do
 template <int FLUX, int NV, int P, int p>
 hipError_t launch_adj1d(const KProb& pb, const KStep& st, const double* ubo, double* C, hipStream_t s) {
   if constexpr (p <= P) {
+    static const char* names[5] = {"", "adjoint1d_p1", "adjoint1d_p2", "adjoint1d_p3", "adjoint1d_p4"};
     auto kern = k_adj1d<FLUX, NV, p>;
     const int grid = persistent_grid(kern, pb.nIx, 0);
     {
-      ProfScope ps("adjoint1d", s);
+      ProfScope ps(names[p], s);
       kern<<<grid, BLOCK, 0, s>>>(pb, st, ubo, C, 2 * P);
     }
     ACAT_CHECK_LAUNCH();
@@ -597,10 +598,14 @@ hipError_t adj1d_impl(const KProb& pb, const KStep& st, const double* ubo, doubl
 template <int FLUX, int NV, int P, int Q1, int Q2>
 hipError_t launch_adj2d(const KProb& pb, const KStep& st, const double* ubo, double* C, hipStream_t s) {
   if constexpr (Q1 <= P && Q2 <= P) {
+    static const char* names[4][4] = {{"", "", "", ""},
+                                      {"", "adjoint2d_q11", "adjoint2d_q12", "adjoint2d_q13"},
+                                      {"", "adjoint2d_q21", "adjoint2d_q22", "adjoint2d_q23"},
+                                      {"", "adjoint2d_q31", "adjoint2d_q32", "adjoint2d_q33"}};
     auto kern = k_adj2d<FLUX, NV, Q1, Q2>;
     const int grid = persistent_grid(kern, pb.n1 * pb.n2, 0);
     {
-      ProfScope ps("adjoint2d", s);
+      ProfScope ps(names[Q1][Q2], s);
       kern<<<grid, BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P);
     }
     ACAT_CHECK_LAUNCH();

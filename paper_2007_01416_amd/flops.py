@@ -16,12 +16,25 @@ Flux evaluations (distinct operations, shared subexpressions once):
   1D Euler f: v = m/rho, m v, 1/2, E -, (gamma-1) x, m v + p, E + p, v (E+p) = 8
   Burgers f = (u u)/2                                          = 2
   advection f = a u                                            = 1 per variable
+
+Adjoint (reverse mode) of one 2D corner, adjoint_corner_flops_2d: the
+forward recursion up to U^{T-1} (its values are the linearisation points),
+then the reverse sweep: per level and node, the time-derivative weights
+applied to the incoming adjoint, the Jacobian-transpose products at the
+T-1 predicted states, the adjoint of the Taylor predictions, and the
+transposed centred differences; the last level only on the row and column
+the fluxes read; finally the Jacobian-transpose products at the node
+state.  Predictions the reverse sweep recomputes instead of storing are not
+counted.
+  2D Euler f'(u)^T fb + g'(u)^T gb (analytic, primitive variables once) = 58
+  2D advection                                                          = 3
 """
 from __future__ import annotations
 
 C_FG_EULER2D = 16
 C_F_EULER2D = 13
 C_F = {("euler", 1): 8, ("burgers", 1): 2, ("advection", 1): 1}
+V_FG_EULER2D = 58
 
 
 def _pass_2d(n1, n2, qt, do_f, do_g, s, cfg, cf):
@@ -98,3 +111,45 @@ def classify_flops(P: int, s: int, dim: int) -> int:
 
 def update_flops(s: int, dim: int) -> int:
     return s * (3 if dim == 1 else 6)
+
+
+def _adj_pass_2d(n1, n2, qt, do_f, do_g, s, cfg, vfg):
+    """Reverse of one corner recursion (forward part up to U^{T-1} included)."""
+    T = 2 * qt
+    R = n1 * n2
+    u_cost = s * (2 * n1 + 2 * n2 + 3)
+    ut_cost = s * (2 * n1 + 2 * n2 + 4)          # transposed differences, scalings, series term
+    nlast = (n1 if do_f else 0) + (n2 if do_g else 0) - (1 if (do_f and do_g) else 0)
+    total = 0
+    # forward: U^1 .. U^{T-1}, Fh/Gh up to level T-2
+    for kk in range(2, T + 1):
+        total += R * u_cost
+        if kk < T:
+            total += R * (T - 1) * (2 * s * (kk - 1) + cfg)
+            total += R * 2 * (2 * s * T)
+    # reverse
+    for kk in range(T, 1, -1):
+        nodes = nlast if kk == T else R
+        w = 2 * s * (kk - 1) if kk == T else 0   # the forward computed the lower levels' predictions
+        per_r = 2 * s + w + vfg + s + 2 * s * (kk - 1)   # scale, prediction, vjp, ub, Ub
+        total += nodes * ((T - 1) * per_r + 4 * s)
+        total += (nlast if kk == T else R) * ut_cost
+    return total
+
+
+def adjoint_corner_flops_2d(q1: int, q2: int, s: int = 4, cfg: int = C_FG_EULER2D,
+                            vfg: int = V_FG_EULER2D) -> int:
+    """Algorithmic flops of the adjoint of one 2D corner of class (q1, q2)."""
+    n1, n2 = 2 * q1, 2 * q2
+    total = n1 * n2 * (cfg + vfg + 4 * s)        # f, g at the nodes; final transpose products; f0b/g0b sums
+    if q1 == q2:
+        total += _adj_pass_2d(n1, n2, q1, True, True, s, cfg, vfg)
+    else:
+        total += _adj_pass_2d(n1, n2, q1, True, False, s, cfg, vfg)
+        total += _adj_pass_2d(n1, n2, q2, False, True, s, cfg, vfg)
+    total += 2 * 3 * s                           # flux adjoints from the update transpose
+    if q1 == 1:
+        total += 2 * 4 * s
+    if q2 == 1:
+        total += 2 * 4 * s
+    return total

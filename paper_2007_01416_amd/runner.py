@@ -197,6 +197,7 @@ class AdjointRun:
         self.hashes = torch.zeros(self.nsteps, dtype=torch.int64, device=device) if verify else None
         self.tmp = torch.empty(prob.shape, dtype=torch.float64, device=device)
         self.checkpoints = []
+        self.class_log = None   # optional int32 [nsteps, 16]: per-class item counts of each adjoint step
 
     def _step(self, u, out, n, dec):
         max_wave_speed(self.prob, u, self.smax)
@@ -250,6 +251,8 @@ class AdjointRun:
             for j in reversed(range(m)):
                 step_adjoint(self.prob, self.seg_u[j], dts[n0 + j:n0 + j + 1], self.seg_dec[j], ub, ubar_in=ub,
                              ws=self.aws)
+                if self.class_log is not None:
+                    self.class_log[n0 + j].copy_(self.aws[:64].view(torch.int32))
         if self.verify:
             if not torch.equal(hashes, self.hashes) or not torch.equal(dts, self.dts):
                 raise RuntimeError("recomputed decisions differ from the forward run")
