@@ -213,6 +213,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and adjoint workloads")
     ap.add_argument("--fd-dirs", type=int, default=32, help="finite-difference directions of the adjoint check")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (reference dispatch for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         sys.exit("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus must be 1)")
@@ -232,6 +234,12 @@ def main():
     s = acat.Solver(prob, w["u"], w["cfl"])
     for _ in range(args.warmup):
         s.step()
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     counts = s.ws[:64].view(torch.int32)          # per-class item counts of the last step
     hist = torch.zeros((args.steps, 16), dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
