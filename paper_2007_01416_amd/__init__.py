@@ -278,7 +278,8 @@ class _Batch(ctypes.Structure):
                 ("eps", ctypes.c_double), ("theta", ctypes.c_double),
                 ("nprob", ctypes.c_int32),
                 ("n", ctypes.POINTER(ctypes.c_int64)), ("P", ctypes.POINTER(ctypes.c_int32)),
-                ("bc", ctypes.POINTER(ctypes.c_int32)), ("dx", ctypes.POINTER(ctypes.c_double))]
+                ("bc", ctypes.POINTER(ctypes.c_int32)), ("dx", ctypes.POINTER(ctypes.c_double)),
+                ("launch", ctypes.POINTER(ctypes.c_int32))]
 
 
 class Batch:
@@ -301,7 +302,9 @@ class Batch:
                          self.n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                          self.P.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                          self.bc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                         self.dx.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                         self.dx.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None)
+        self._launch = None
+        self.launch_table = {}
         nb = ctypes.c_size_t(0)
         _check(load().acat_batch_workspace_size(ctypes.byref(self._c), ctypes.byref(nb)), "acat_batch_workspace_size")
         self.ws = torch.empty(nb.value, dtype=torch.uint8, device=device)
@@ -311,6 +314,29 @@ class Batch:
     @property
     def shape(self):
         return (self.nvar, self.ncell)
+
+    @property
+    def orders(self):
+        return sorted(set(range(1, int(self.P.max()) + 1)))
+
+    def set_launch(self, table=None):
+        """Launch shapes of the per-order flux kernels: {p: (waves_per_block,
+        blocks_per_cu)} (missing p and None: the defaults 4 waves, occupancy
+        limit).  Results do not depend on it."""
+        import numpy as np
+        if table is None:
+            self._launch = None
+            self._c.launch = None
+        else:
+            arr = np.zeros(8, dtype=np.int32)
+            for p, (wv, pc) in table.items():
+                arr[2 * (p - 1)] = wv
+                arr[2 * (p - 1) + 1] = pc
+            self._launch = arr
+            self._c.launch = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        self.launch_table = dict(table) if table else {}
+        nb = ctypes.c_size_t(0)
+        _check(load().acat_batch_workspace_size(ctypes.byref(self._c), ctypes.byref(nb)), "acat_batch launch table")
 
     def split(self, u):
         """Per-problem views of a batched state."""

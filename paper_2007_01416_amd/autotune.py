@@ -1,0 +1,75 @@
+"""Autotuner of the batched step's launch shapes.
+
+For each order class p of a batch, the flux kernel's shape is a number of
+waves per block (1, 2 or 4: 64, 128 or 256 threads, i.e. 32p ... 128/p
+interfaces per block round) and a number of persistent blocks per CU (the
+occupancy limit, or fewer).  The classes are independent launches, so each
+is tuned on its own: every candidate shape runs the whole batched step on
+a fixed state a few times with the library's kernel timer on, and the
+class's own kernel time decides.  Shapes never change results (tested bit
+for bit), only time.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import profile, profile_read
+
+WAVES = (1, 2, 4)
+PER_CU = (0, 1, 2, 4, 8)
+
+
+def _time_classes(batch, u, dt, out, reps):
+    profile(True)
+    for _ in range(reps):
+        batch.step(u, dt, out=out)
+    rec = profile_read()
+    profile(False)
+    return {p: rec[f"flux_b_p{p}"][1] / reps for p in batch.orders if f"flux_b_p{p}" in rec}
+
+
+def tune(batch, u: torch.Tensor, dt: torch.Tensor, reps: int = 5, waves=WAVES, per_cu=PER_CU,
+         cache: str | None = None, verbose: bool = False) -> dict:
+    """Choose and set the fastest shape per order class; returns
+    {p: (waves, blocks_per_cu, ms)}.  With `cache` (a JSON file) a table
+    stored for the same batch signature is reused."""
+    key = signature(batch)
+    if cache and os.path.exists(cache):
+        stored = json.load(open(cache))
+        if key in stored:
+            table = {int(p): tuple(v[:2]) for p, v in stored[key].items()}
+            batch.set_launch(table)
+            return {int(p): tuple(v) for p, v in stored[key].items()}
+    out = torch.empty_like(u)
+    batch.set_launch(None)
+    batch.step(u, dt, out=out)               # warm-up (modules loaded)
+    best = {}
+    for wv in waves:
+        for pc in per_cu:
+            batch.set_launch({p: (wv, pc) for p in batch.orders})
+            times = _time_classes(batch, u, dt, out, reps)
+            for p, ms in times.items():
+                if verbose:
+                    print(f"[tune] p={p} waves={wv} per_cu={pc}: {ms * 1e3:.1f} us", flush=True)
+                if p not in best or ms < best[p][2]:
+                    best[p] = (wv, pc, ms)
+    batch.set_launch({p: (v[0], v[1]) for p, v in best.items()})
+    if cache:
+        stored = json.load(open(cache)) if os.path.exists(cache) else {}
+        stored[key] = {str(p): list(v) for p, v in best.items()}
+        with open(cache, "w") as f:
+            json.dump(stored, f, indent=1)
+    return best
+
+
+def signature(batch) -> str:
+    """Batch identity for the cache: device, flux, sizes and orders."""
+    import hashlib
+    h = hashlib.sha256()
+    for a in (batch.n, batch.P, batch.bc):
+        h.update(a.tobytes())
+    dev = torch.cuda.get_device_name() if torch.cuda.is_available() else "cpu"
+    return f"{dev}|nvar{batch.nvar}|{h.hexdigest()[:16]}"

@@ -208,6 +208,12 @@ acat_status check_batch(const acat_batch* bt) {
   if (bt->flux == ACAT_FLUX_EULER && (bt->nvar != 3 || !(bt->gamma > 1.0))) return ACAT_ERR_ARG;
   if (bt->flux != ACAT_FLUX_EULER && bt->nvar != 1) return bt->nvar < 1 ? ACAT_ERR_ARG : ACAT_ERR_UNSUPPORTED;
   if (!(bt->eps >= 0.0) || !(bt->theta > 0.0 && bt->theta <= 1.0)) return ACAT_ERR_ARG;
+  if (bt->launch) {
+    for (int p = 0; p < PMAX; ++p) {
+      const int w = bt->launch[2 * p], c = bt->launch[2 * p + 1];
+      if (!(w == 0 || w == 1 || w == 2 || w == 4) || c < 0 || c > 32) return ACAT_ERR_ARG;
+    }
+  }
   int64_t cells = 0, ifs = 0;
   for (int b = 0; b < bt->nprob; ++b) {
     const int P = bt->P[b];
@@ -279,6 +285,12 @@ KBatch make_kbatch(const acat_batch* bt, const BLayout& L, char* w) {
   k.P = reinterpret_cast<const int32_t*>(w + L.P);
   k.bc = reinterpret_cast<const int32_t*>(w + L.bc);
   k.dx = reinterpret_cast<const double*>(w + L.dx);
+  for (int p = 1; p <= PMAX; ++p) {
+    k.waves[p] = bt->launch && bt->launch[2 * (p - 1)] > 0 ? bt->launch[2 * (p - 1)] : 4;
+    k.per_cu[p] = bt->launch ? bt->launch[2 * (p - 1) + 1] : 0;
+  }
+  k.waves[0] = 4;
+  k.per_cu[0] = 0;
   return k;
 }
 

@@ -69,11 +69,12 @@ __global__ __launch_bounds__(BLOCK) void k_classify_b(KBatch bt, KBStep st) {
   block_hist(sh, valid, ps - 1, st.hist);
 }
 
-// Interfaces of order p of every problem (same arithmetic as k_flux1d).
-template <int FLUX, int NV, int p>
-__global__ __launch_bounds__(BLOCK) void k_flux_b(KBatch bt, KBStep st) {
+// Interfaces of order p of every problem (same arithmetic as k_flux1d), BS
+// threads per block: BS / 2p interfaces per round.
+template <int FLUX, int NV, int p, int BS>
+__global__ __launch_bounds__(BS) void k_flux_b(KBatch bt, KBStep st) {
   constexpr int L = 2 * p;
-  constexpr int GPB = BLOCK / L;
+  constexpr int GPB = BS / L;
   constexpr int SL = L + 1;
   constexpr int NS = GPB * SL + SL;
   __shared__ double xs[2][NV][NS];
@@ -251,18 +252,28 @@ __global__ void k_dt_b(KBatch bt, const double* smax, double cfl, double* dt) {
     if (e_ != hipSuccess) return e_;         \
   } while (0)
 
-template <int FLUX, int NV, int p>
-hipError_t launch_flux_b(const KBatch& bt, const KBStep& st, hipStream_t s) {
-  if (p > bt.Pmax) return hipSuccess;
+template <int FLUX, int NV, int p, int BS>
+hipError_t launch_flux_b_bs(const KBatch& bt, const KBStep& st, hipStream_t s) {
   static const char* names[5] = {"", "flux_b_p1", "flux_b_p2", "flux_b_p3", "flux_b_p4"};
-  auto kern = k_flux_b<FLUX, NV, p>;
-  const int grid = persistent_grid(kern, bt.nif, 0);
+  auto kern = k_flux_b<FLUX, NV, p, BS>;
+  const int grid = persistent_grid(kern, bt.nif, 0, BS, bt.per_cu[p]);
   {
     ProfScope ps(names[p], s);
-    kern<<<grid, BLOCK, 0, s>>>(bt, st);
+    kern<<<grid, BS, 0, s>>>(bt, st);
   }
   ACAT_CHECK_LAUNCH();
   return hipSuccess;
+}
+
+// launch shape of class p from the batch's tuning table (waves per block)
+template <int FLUX, int NV, int p>
+hipError_t launch_flux_b(const KBatch& bt, const KBStep& st, hipStream_t s) {
+  if (p > bt.Pmax) return hipSuccess;
+  switch (bt.waves[p]) {
+    case 1: return launch_flux_b_bs<FLUX, NV, p, 64>(bt, st, s);
+    case 2: return launch_flux_b_bs<FLUX, NV, p, 128>(bt, st, s);
+    default: return launch_flux_b_bs<FLUX, NV, p, 256>(bt, st, s);
+  }
 }
 
 template <int FLUX, int NV>

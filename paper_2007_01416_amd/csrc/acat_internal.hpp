@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "coeffs.hpp"
 #include "physics.hpp"
 
 namespace acat {
@@ -83,6 +84,8 @@ struct KBatch {
   const int32_t* P;         // [nprob] largest half-width
   const int32_t* bc;        // [nprob] boundary
   const double* dx;         // [nprob]
+  int waves[PMAX + 1];      // per order class p: waves per block of the flux kernel (1, 2 or 4)
+  int per_cu[PMAX + 1];     // per order class p: persistent blocks per CU (0: occupancy limit)
 };
 
 struct KBStep {

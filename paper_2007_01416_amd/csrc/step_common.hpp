@@ -191,15 +191,17 @@ int num_cus() {
   return n;
 }
 
-// Persistent grid of a tile-walking kernel: enough blocks to fill every CU
-// at the kernel's occupancy (cap > 0 overrides), never more than the tiles,
-// a multiple of the XCD count.
+// Persistent grid of a tile-walking kernel of `bs` threads per block:
+// enough blocks to fill every CU at the kernel's occupancy (or `per_cu`
+// blocks per CU when that is > 0; cap > 0 overrides both), never more than
+// the tiles, a multiple of the XCD count.
 template <typename K>
-int persistent_grid(K kernel, int64_t nitems, int cap) {
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, BLOCK, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+int persistent_grid(K kernel, int64_t nitems, int cap, int bs = BLOCK, int per_cu = 0) {
+  if (per_cu <= 0 &&
+      (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, bs, 0) != hipSuccess || per_cu < 1))
+    per_cu = 1;
   int64_t b = cap > 0 ? cap : (int64_t)per_cu * num_cus();
-  const int64_t ntiles = (nitems + BLOCK - 1) / BLOCK;
+  const int64_t ntiles = (nitems + bs - 1) / bs;
   if (b > ntiles) b = ntiles;
   b = (b + NXCD - 1) / NXCD * NXCD;
   return (int)(b < NXCD ? NXCD : b);

@@ -132,6 +132,21 @@ def test_batch_validation(lib, n, P, bc, dx, code):
         assert lib.acat_step_batched(ctypes.byref(b), ws, ws, ws, ws, 16, None) == -6
 
 
+@pytest.mark.parametrize("table,code", [
+    ([0] * 8, 0), ([1, 0, 2, 4, 4, 32, 0, 1], 0),
+    ([3, 0, 0, 0, 0, 0, 0, 0], -2),                 # 3 waves per block
+    ([0, 0, 0, 0, 0, 0, 8, 0], -2),                 # 8 waves per block
+    ([0, 33, 0, 0, 0, 0, 0, 0], -2),                # too many blocks per CU
+    ([0, 0, 0, -1, 0, 0, 0, 0], -2),
+])
+def test_batch_launch_table_validation(lib, table, code):
+    b, keep = _batch_struct([64, 32], [2, 3], [0, 1], [0.1, 0.1])
+    t = np.ascontiguousarray(table, np.int32)
+    b.launch = t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    nb = ctypes.c_size_t(0)
+    assert lib.acat_batch_workspace_size(ctypes.byref(b), ctypes.byref(nb)) == code
+
+
 def test_adjoint_argument_errors_before_launch(lib):
     import paper_2007_01416_amd as acat
     p = _prob()

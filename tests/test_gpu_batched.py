@@ -107,3 +107,28 @@ def test_batched_graph_replay_matches_eager(acat):
         b.run(2)
         torch.cuda.synchronize()
         assert np.array_equal(a.u.cpu().numpy(), b.u.cpu().numpy()), f"replay {rep}"
+
+
+def test_batched_launch_shapes_and_autotuner_keep_results(acat, tmp_path):
+    """Every launch shape of the per-order flux kernels gives the same bits;
+    the autotuner picks one per order and caches it."""
+    import torch
+    from paper_2007_01416_amd import autotune
+    w = workloads.batch_1d(nprob=32, nmin=256, nmax=2048)
+    probs = w["problems"]
+    batch = make_batch(acat, probs)
+    u = T(concat([p["u"] for p in probs]))
+    dt = torch.empty(batch.nprob, dtype=torch.float64, device="cuda")
+    batch.cfl_dt(u, w["cfl"], dt)
+    ref = batch.step(u, dt)
+    for wv in (1, 2, 4):
+        for pc in (0, 1, 3):
+            batch.set_launch({p: (wv, pc) for p in batch.orders})
+            assert torch.equal(batch.step(u, dt), ref), (wv, pc)
+    cache = str(tmp_path / "tune.json")
+    best = autotune.tune(batch, u, dt, reps=2, cache=cache)
+    assert set(best) == set(batch.orders)
+    assert torch.equal(batch.step(u, dt), ref)
+    again = autotune.tune(batch, u, dt, cache=cache)           # from the cache
+    assert {p: v[:2] for p, v in again.items()} == {p: tuple(v[:2]) for p, v in best.items()}
+    say(f"[autotune] {best}")
