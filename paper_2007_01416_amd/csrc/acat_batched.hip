@@ -111,20 +111,32 @@ __global__ __launch_bounds__(BS) void k_flux_b(KBatch bt, KBStep st) {
       cur[c] = fh0[c];
       S[c] = fma(TB.INVFACT[1], fh0[c], 0.0);
     }
-    double U[L][NV];
+    double W[L][NV];   // Taylor predictions at the time nodes r != 0, one term per level
+#pragma unroll
+    for (int ri = 0; ri < L; ++ri)
+#pragma unroll
+      for (int c = 0; c < NV; ++c) W[ri][c] = u[c];
 #pragma unroll
     for (int kk = 2; kk <= 2 * p; ++kk) {
 #pragma unroll
       for (int c = 0; c < NV; ++c) xs[buf][c][slot] = cur[c];
       __syncthreads();
+      double Uk[NV];
 #pragma unroll
       for (int c = 0; c < NV; ++c) {
         double sacc = 0.0;
 #pragma unroll
         for (int l = 0; l < L; ++l) sacc = fma(g1[l], xs[buf][c][g * SL + l], sacc);
-        U[kk - 1][c] = -lam * sacc;
+        Uk[c] = -lam * sacc;
       }
       buf ^= 1;
+#pragma unroll
+      for (int ri = 0; ri < L; ++ri) {
+        const int r = ri - p + 1;
+        if (r == 0) continue;
+#pragma unroll
+        for (int c = 0; c < NV; ++c) W[ri][c] = fma(TB.TAYLOR[r + PMAX - 1][kk - 1], Uk[c], W[ri][c]);
+      }
       double nxt[NV];
 #pragma unroll
       for (int c = 0; c < NV; ++c) nxt[c] = 0.0;
@@ -136,15 +148,7 @@ __global__ __launch_bounds__(BS) void k_flux_b(KBatch bt, KBStep st) {
 #pragma unroll
           for (int c = 0; c < NV; ++c) ph[c] = fh0[c];
         } else {
-          double w[NV];
-#pragma unroll
-          for (int c = 0; c < NV; ++c) {
-            double sacc = u[c];
-#pragma unroll
-            for (int l = 1; l <= kk - 1; ++l) sacc = fma(TB.TAYLOR[r + PMAX - 1][l], U[l][c], sacc);
-            w[c] = sacc;
-          }
-          flux1d<FLUX, NV>(bt.ph, w, ph);
+          flux1d<FLUX, NV>(bt.ph, W[ri], ph);
         }
 #pragma unroll
         for (int c = 0; c < NV; ++c) nxt[c] = fma(TB.GT[p][kk - 1][ri], ph[c], nxt[c]);

@@ -124,7 +124,13 @@ __global__ __launch_bounds__(BLOCK) void k_flux1d(KProb pb, KStep st) {
         cur[c] = fh0[c];
         S[c] = fma(TB.INVFACT[1], fh0[c], 0.0);
       }
-      double U[L][NV];   // U[l] = dt^l u~^(l) at this node, l = 1 .. 2p-1
+      // Taylor predictions W_r = u + sum_{l<kk} r^l/l! U^l, U^l = dt^l u~^(l), at the
+      // time nodes r != 0, one term added per level (same fma chain as summing from u)
+      double W[L][NV];
+#pragma unroll
+      for (int ri = 0; ri < L; ++ri)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) W[ri][c] = u[c];
 #pragma unroll
       for (int kk = 2; kk <= 2 * p; ++kk) {
         // share Fh^{kk-2} of every node of the stencil
@@ -132,14 +138,22 @@ __global__ __launch_bounds__(BLOCK) void k_flux1d(KProb pb, KStep st) {
         for (int c = 0; c < NV; ++c) xs[buf][c][slot] = cur[c];
         __syncthreads();
         // U^{kk-1} = -lambda * (spatial derivative of Fh^{kk-2} at this node)
+        double Uk[NV];
 #pragma unroll
         for (int c = 0; c < NV; ++c) {
           double sacc = 0.0;
 #pragma unroll
           for (int l = 0; l < L; ++l) sacc = fma(g1[l], xs[buf][c][g * SL + l], sacc);
-          U[kk - 1][c] = -lam * sacc;
+          Uk[c] = -lam * sacc;
         }
         buf ^= 1;
+#pragma unroll
+        for (int ri = 0; ri < L; ++ri) {
+          const int r = ri - p + 1;
+          if (r == 0) continue;
+#pragma unroll
+          for (int c = 0; c < NV; ++c) W[ri][c] = fma(TB.TAYLOR[r + PMAX - 1][kk - 1], Uk[c], W[ri][c]);
+        }
         // flux at the Taylor-predicted states of the time nodes r, and its
         // (kk-1)-th time derivative at r = 0
         double nxt[NV];
@@ -153,15 +167,7 @@ __global__ __launch_bounds__(BLOCK) void k_flux1d(KProb pb, KStep st) {
 #pragma unroll
             for (int c = 0; c < NV; ++c) ph[c] = fh0[c];
           } else {
-            double w[NV];
-#pragma unroll
-            for (int c = 0; c < NV; ++c) {
-              double sacc = u[c];
-#pragma unroll
-              for (int l = 1; l <= kk - 1; ++l) sacc = fma(TB.TAYLOR[r + PMAX - 1][l], U[l][c], sacc);
-              w[c] = sacc;
-            }
-            flux1d<FLUX, NV>(pb.ph, w, ph);
+            flux1d<FLUX, NV>(pb.ph, W[ri], ph);
           }
 #pragma unroll
           for (int c = 0; c < NV; ++c) nxt[c] = fma(TB.GT[p][kk - 1][ri], ph[c], nxt[c]);
@@ -339,7 +345,14 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, double lamx, double 
     if (DOF) SF[c] = fma(TB.INVFACT[1], f0[c], 0.0);
     if (DOG) SG[c] = fma(TB.INVFACT[1], g0[c], 0.0);
   }
-  double U[2 * QT][NV];
+  // Taylor predictions W_r = u + sum_{l<kk} r^l/l! U^l at the time nodes r != 0,
+  // extended by one term per level (the same chain of fused multiply-adds as
+  // summing from u each level)
+  double W[2 * QT][NV];
+#pragma unroll
+  for (int ri = 0; ri < 2 * QT; ++ri)
+#pragma unroll
+    for (int c = 0; c < NV; ++c) W[ri][c] = u[c];
 #pragma unroll
   for (int kk = 2; kk <= 2 * QT; ++kk) {
     double2* xsw = buf ? xsb1 : xsb0;
@@ -347,6 +360,7 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, double lamx, double 
     __syncthreads();
     const double* xr = reinterpret_cast<const double*>(xsw);
     // U^{kk-1} = -lamx d_x Fh^{kk-2} - lamy d_y Gh^{kk-2} at this node
+    double Uk[NV];
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
       double sx = 0.0, sy = 0.0;
@@ -354,9 +368,16 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, double lamx, double 
       for (int l = 0; l < N1; ++l) sx = fma(g1x[l], Xch<NV>::get(xr, stride, gbase + a2 * N1 + l, c, false), sx);
 #pragma unroll
       for (int l = 0; l < N2; ++l) sy = fma(g1y[l], Xch<NV>::get(xr, stride, gbase + l * N1 + a1, c, true), sy);
-      U[kk - 1][c] = -lamx * sx - lamy * sy;
+      Uk[c] = -lamx * sx - lamy * sy;
     }
     buf ^= 1;
+#pragma unroll
+    for (int ri = 0; ri < 2 * QT; ++ri) {
+      const int r = ri - QT + 1;
+      if (r == 0) continue;
+#pragma unroll
+      for (int c = 0; c < NV; ++c) W[ri][c] = fma(TB.TAYLOR[r + PMAX - 1][kk - 1], Uk[c], W[ri][c]);
+    }
     double nf[NV], ng[NV];
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
@@ -374,15 +395,7 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, double lamx, double 
           pg[c] = g0[c];
         }
       } else {
-        double w[NV];
-#pragma unroll
-        for (int c = 0; c < NV; ++c) {
-          double sacc = u[c];
-#pragma unroll
-          for (int l = 1; l <= kk - 1; ++l) sacc = fma(TB.TAYLOR[r + PMAX - 1][l], U[l][c], sacc);
-          w[c] = sacc;
-        }
-        flux2d<FLUX, NV>(ph, w, pf, pg);
+        flux2d<FLUX, NV>(ph, W[ri], pf, pg);
       }
 #pragma unroll
       for (int c = 0; c < NV; ++c) {

@@ -5,8 +5,12 @@ multiply-add counts 2.  The counts are those of the method's own steps for
 the order actually selected at each interface or corner (Sec. 2.2 recursion
 in 1D; Sec. 4 corner recursion on the rectangle J_q1 x J_q2, with the last
 recursion step restricted to the nodes the final fluxes read, i.e. row
-j2 = 0 for F and column j1 = 0 for G, as Sec. 4 allows).  They do not count
-work an implementation adds (idle lanes, recomputation, index arithmetic).
+j2 = 0 for F and column j1 = 0 for G, as Sec. 4 allows).  The Taylor
+predictions u + sum_{l<k} (r dt)^l/l! u~^(l) at the time nodes are counted
+in their incremental form, one term added per level (the same sums: each
+level extends the previous level's partial sum), not re-summed from u at
+every level.  They do not count work an implementation adds (idle lanes,
+recomputation, index arithmetic).
 
 Flux evaluations (distinct operations, shared subexpressions once):
   2D Euler f and g at one state: 1/rho, v, w, mx v, my w, their sum, 1/2,
@@ -44,7 +48,7 @@ def _pass_2d(n1, n2, qt, do_f, do_g, s, cfg, cf):
     u_cost = s * (2 * n1 + 2 * n2 + 3)           # x and y derivatives, two scalings, one subtraction
     total = 0
     for kk in range(2, T + 1):
-        w_cost = 2 * s * (kk - 1)                # Taylor prediction of one state
+        w_cost = 2 * s                           # one more term of the Taylor prediction of one state
         if kk < T:
             total += R * u_cost
             total += R * (T - 1) * (w_cost + cfg)
@@ -91,7 +95,7 @@ def interface_flops_1d(p: int, s: int, cf: int) -> int:
     total = n * cf
     for kk in range(2, T + 1):
         total += n * s * (2 * n + 1)             # spatial derivative and scaling
-        total += n * (T - 1) * (2 * s * (kk - 1) + cf)
+        total += n * (T - 1) * (2 * s + cf)      # one more prediction term, flux at the prediction
         total += n * s * 2 * T
     total += T * s * (2 * n + 2)
     if p == 1:
@@ -121,19 +125,21 @@ def _adj_pass_2d(n1, n2, qt, do_f, do_g, s, cfg, vfg):
     ut_cost = s * (2 * n1 + 2 * n2 + 4)          # transposed differences, scalings, series term
     nlast = (n1 if do_f else 0) + (n2 if do_g else 0) - (1 if (do_f and do_g) else 0)
     total = 0
-    # forward: U^1 .. U^{T-1}, Fh/Gh up to level T-2
+    # forward: U^1 .. U^{T-1}, Fh/Gh up to level T-2, predictions up to level T-1
     for kk in range(2, T + 1):
         total += R * u_cost
         if kk < T:
-            total += R * (T - 1) * (2 * s * (kk - 1) + cfg)
+            total += R * (T - 1) * (2 * s + cfg)
             total += R * 2 * (2 * s * T)
-    # reverse
+    # reverse; the incremental predictions W_r(k) = W_r(k-1) + r^{k-1}/(k-1)! U^{k-1}
+    # reverse into a running adjoint of W_r (s adds) and one term of U's adjoint (2s)
     for kk in range(T, 1, -1):
         nodes = nlast if kk == T else R
-        w = 2 * s * (kk - 1) if kk == T else 0   # the forward computed the lower levels' predictions
-        per_r = 2 * s + w + vfg + s + 2 * s * (kk - 1)   # scale, prediction, vjp, ub, Ub
+        w = 2 * s if kk == T else 0              # last prediction term (the forward stopped at T-1)
+        per_r = 2 * s + w + vfg + s + 2 * s      # scale, prediction, vjp, running adjoint, U term
         total += nodes * ((T - 1) * per_r + 4 * s)
         total += (nlast if kk == T else R) * ut_cost
+    total += R * (T - 1) * s                     # prediction adjoints into u
     return total
 
 
