@@ -109,6 +109,16 @@ acat_status acat_step(const acat_problem* prob, const double* u_in, double* u_ou
                       const double* dt_dev, void* workspace, size_t workspace_bytes,
                       const acat_decisions* dec, void* stream);
 
+/* One step with its own CFL time step: dt_dev[0] = the time step that
+ * acat_max_wave_speed + acat_cfl_dt(cfl, t_final, t_dev) would give for u_in
+ * (bit for bit), computed inside the step (the classification pass reduces
+ * the wave speeds; no atomics, no extra pass over u_in), then u_out = the
+ * step of u_in with it.  t_dev (nullable) is advanced as in acat_cfl_dt.
+ * dt_dev (device scalar) is required; cfl > 0. */
+acat_status acat_step_cfl(const acat_problem* prob, const double* u_in, double* u_out, double cfl, double t_final,
+                          double* t_dev, double* dt_dev, void* workspace, size_t workspace_bytes,
+                          const acat_decisions* dec, void* stream);
+
 /* The same step with the decisions frozen to `dec` (orders, psi1, alpha):
  * a smooth function of u_in, the forward map differentiated by
  * acat_step_adjoint. */

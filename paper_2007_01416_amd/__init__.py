@@ -53,6 +53,9 @@ _SIGS = {
                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p],
     "acat_step_replay": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p],
+    "acat_step_cfl": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                      ctypes.c_void_p],
     "acat_adjoint_workspace_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
     "acat_step_adjoint": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
@@ -200,6 +203,20 @@ def step(prob: Problem, u: torch.Tensor, dt, out: torch.Tensor = None, ws: torch
     dc = ctypes.byref(dec.c()) if dec is not None else None
     _check(load().acat_step(ctypes.byref(prob.c()), _ptr(u), _ptr(out), dtv, dtp, _ptr(ws), ws.numel(), dc,
                             _stream(stream)), "acat_step")
+    return out
+
+
+def step_cfl(prob: Problem, u: torch.Tensor, cfl: float, dt: torch.Tensor, t: torch.Tensor = None,
+             t_final: float = float("inf"), out: torch.Tensor = None, ws: torch.Tensor = None,
+             dec: Decisions = None, stream=None) -> torch.Tensor:
+    """One ACAT step with its CFL time step computed inside the step (written
+    to the 1-element cuda float64 tensor dt; t advanced when given)."""
+    _check_state(prob, u, "u")
+    out = torch.empty_like(u) if out is None else out
+    ws = workspace(prob, u.device) if ws is None else ws
+    dc = ctypes.byref(dec.c()) if dec is not None else None
+    _check(load().acat_step_cfl(ctypes.byref(prob.c()), _ptr(u), _ptr(out), float(cfl), float(t_final), _ptr(t),
+                                _ptr(dt), _ptr(ws), ws.numel(), dc, _stream(stream)), "acat_step_cfl")
     return out
 
 

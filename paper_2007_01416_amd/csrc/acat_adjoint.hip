@@ -22,7 +22,9 @@ namespace acat {
 namespace {
 
 // ======================================================================= 1D
-// contribution buffer: C[c][k * 2P + a], a = node index of interface k
+// contribution buffer, slot-major: C[c][slot][k] with slot = j + P - 1 for the
+// node at offset j in [-P+1, P] of interface k, so that a gather over one
+// offset reads consecutive interfaces
 template <int FLUX, int NV, int p>
 __global__ __launch_bounds__(BLOCK) void k_adj1d(KProb pb, KStep st, const double* __restrict__ ubo,
                                                  double* __restrict__ C, int LMAX) {
@@ -215,7 +217,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj1d(KProb pb, KStep st, const doubl
     }
     if (valid) {
 #pragma unroll
-      for (int c = 0; c < NV; ++c) C[c * cstride + (int64_t)k * LMAX + a] = ub[c];
+      for (int c = 0; c < NV; ++c) C[c * cstride + (int64_t)(a - p + pb.P) * nI + k] = ub[c];
     }
   }
 }
@@ -249,7 +251,7 @@ __global__ __launch_bounds__(BLOCK) void k_gather1d(KProb pb, KStep st, const do
       const int node = per ? i0 + j : bc_index32(i0 + j, nx, pb.bc);
       if (node != m) continue;
 #pragma unroll
-      for (int c = 0; c < NV; ++c) acc[c] += C[c * cstride + (int64_t)k * LMAX + a];
+      for (int c = 0; c < NV; ++c) acc[c] += C[c * cstride + (int64_t)(j + P - 1) * nI + k];
     }
   }
 #pragma unroll
@@ -407,7 +409,9 @@ __device__ __forceinline__ void corner_adjoint(const Phys& ph, double lamx, doub
   }
 }
 
-// contribution buffer: C[c][e * LMAX + nd], nd = a2 * 2Q1 + a1 node of corner e
+// contribution buffer, slot-major: C[c][slot][e], slot = (j2 + P - 1) 2P + (j1 + P - 1)
+// for the node at offset (j1, j2) of corner e (a gather over one offset reads
+// consecutive corners)
 template <int FLUX, int NV, int Q1, int Q2>
 __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const double* __restrict__ ubo,
                                                  double* __restrict__ C, int LMAX) {
@@ -427,7 +431,8 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
   const int64_t nx = pb.nx, ny = pb.ny, plane = pb.nx * pb.ny;
   const int nx32 = (int)pb.nx, ny32 = (int)pb.ny, ioff = (int)pb.ioff;
   const uint32_t n1u = (uint32_t)pb.n1;
-  const int64_t cstride = pb.n1 * pb.n2 * LMAX;
+  const int64_t nitems = pb.n1 * pb.n2;
+  const int64_t cstride = nitems * LMAX;
 
   double g1x[N1], g1y[N2], g1xT[N1], g1yT[N2];
 #pragma unroll
@@ -521,9 +526,10 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
       }
     }
     flux2d_vjp<FLUX, NV>(pb.ph, u, f0b, g0b, ub);
+    const int cslot = (a2 - Q2 + pb.P) * (2 * pb.P) + (a1 - Q1 + pb.P);
     if (valid) {
 #pragma unroll
-      for (int c = 0; c < NV; ++c) C[c * cstride + (int64_t)e * LMAX + nd] = ub[c];
+      for (int c = 0; c < NV; ++c) C[c * cstride + (int64_t)cslot * nitems + e] = ub[c];
     }
   }
 }
@@ -550,9 +556,9 @@ __global__ __launch_bounds__(BLOCK) void k_gather2d(KProb pb, KStep st, const do
       const int cl = st.cls[e];
       const int q1 = cl / P + 1, q2 = cl % P + 1;
       if (j1 < -q1 + 1 || j1 > q1 || j2 < -q2 + 1 || j2 > q2) continue;
-      const int nd = (j2 + q2 - 1) * (2 * q1) + (j1 + q1 - 1);
+      const int64_t slot = (int64_t)(j2 + P - 1) * (2 * P) + (j1 + P - 1);
 #pragma unroll
-      for (int c = 0; c < NV; ++c) acc[c] += C[c * cstride + e * LMAX + nd];
+      for (int c = 0; c < NV; ++c) acc[c] += C[c * cstride + slot * plane + e];
     }
   }
 #pragma unroll

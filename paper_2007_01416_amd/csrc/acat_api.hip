@@ -76,8 +76,9 @@ KProb make_kprob(const acat_problem* p) {
 //   hist          int32[tiles][MAX_CLASSES]
 //   offs          int32[MAX_CLASSES][tiles + 1]
 //   list          int32[items]
+//   part          double[tiles][dim] partial wave-speed maxima (acat_step_cfl)
 struct Layout {
-  size_t hdr, ordx, ordy, psix, psiy, alx, aly, Fx, Gy, cls, hist, offs, list, total;
+  size_t hdr, ordx, ordy, psix, psiy, alx, aly, Fx, Gy, cls, hist, offs, list, part, total;
   int64_t nItems;
 };
 
@@ -101,6 +102,7 @@ Layout layout(const KProb& k) {
   L.hist = o;  o += align_up(sizeof(int32_t) * MAX_CLASSES * (size_t)cblocks);
   L.offs = o;  o += align_up(sizeof(int32_t) * MAX_CLASSES * (size_t)(cblocks + 1));
   L.list = o;  o += align_up(sizeof(int32_t) * (size_t)L.nItems);
+  L.part = o;  o += align_up(sizeof(double) * 2 * (size_t)cblocks);
   L.total = o;
   return L;
 }
@@ -126,12 +128,24 @@ bool overlaps(const void* a, const void* b, size_t n) {
   return x < y + n && y < x + n;
 }
 
+struct CflArgs {
+  double cfl, t_final;
+  double* t_dev;
+  double* dt_out;
+};
+
 acat_status do_step(const acat_problem* prob, const double* u_in, double* u_out, double dt, const double* dt_dev,
-                    void* ws, size_t ws_bytes, const acat_decisions* dec, bool replay, void* stream) {
+                    void* ws, size_t ws_bytes, const acat_decisions* dec, bool replay, void* stream,
+                    const CflArgs* cfl = nullptr) {
   acat_status rc = check_problem(prob);
   if (rc != ACAT_OK) return rc;
   if (!u_in || !u_out) return ACAT_ERR_NULL;
-  if (!dt_dev && !(dt >= 0.0)) return ACAT_ERR_ARG;
+  if (cfl) {
+    if (!cfl->dt_out) return ACAT_ERR_NULL;
+    if (!(cfl->cfl > 0.0)) return ACAT_ERR_ARG;
+  } else if (!dt_dev && !(dt >= 0.0)) {
+    return ACAT_ERR_ARG;
+  }
   const KProb k = make_kprob(prob);
   const size_t state_bytes = sizeof(double) * (size_t)k.nvar * k.nx * k.ny;
   if (overlaps(u_in, u_out, state_bytes)) return ACAT_ERR_ALIAS;
@@ -163,6 +177,15 @@ acat_status do_step(const acat_problem* prob, const double* u_in, double* u_out,
   st.status = status_ptr();
   if (!st.status) return ACAT_ERR_DEVICE;
   st.replay = replay ? 1 : 0;
+  if (cfl) {
+    st.cfl_mode = 1;
+    st.cfl = cfl->cfl;
+    st.t_final = cfl->t_final;
+    st.t_dev = cfl->t_dev;
+    st.dt_out = cfl->dt_out;
+    st.dt_dev = cfl->dt_out;   // the flux and update kernels read the time step computed in the step
+    st.part = reinterpret_cast<double*>(w + L.part);
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = k.dim == 1 ? launch_step_1d(k, st, 0, s) : launch_step_2d(k, st, 0, s);
   return e == hipSuccess ? ACAT_OK : ACAT_ERR_DEVICE;
@@ -313,6 +336,13 @@ acat_status acat_step(const acat_problem* prob, const double* u_in, double* u_ou
                       const double* dt_dev, void* workspace, size_t workspace_bytes, const acat_decisions* dec,
                       void* stream) {
   return do_step(prob, u_in, u_out, dt, dt_dev, workspace, workspace_bytes, dec, false, stream);
+}
+
+acat_status acat_step_cfl(const acat_problem* prob, const double* u_in, double* u_out, double cfl, double t_final,
+                          double* t_dev, double* dt_dev, void* workspace, size_t workspace_bytes,
+                          const acat_decisions* dec, void* stream) {
+  CflArgs c{cfl, t_final, t_dev, dt_dev};
+  return do_step(prob, u_in, u_out, 0.0, nullptr, workspace, workspace_bytes, dec, false, stream, &c);
 }
 
 acat_status acat_step_replay(const acat_problem* prob, const double* u_in, double* u_out, double dt,

@@ -46,6 +46,14 @@ struct KStep {
   int32_t* list;          // item ids grouped by class, spatial order within a class [items]
   uint32_t* status;       // device status bits
   int replay;             // decisions given in ord/psi/al
+  // CFL mode: the classification also reduces the cells' spectral radii into
+  // per-block partial maxima `part`, from which one block computes the time
+  // step into dt_out (and advances t_dev) before the flux kernels read it
+  int cfl_mode;
+  double cfl, t_final;
+  double* t_dev;
+  double* dt_out;
+  double* part;           // [tiles][dim]
 };
 
 __device__ __forceinline__ double step_dt(const KStep& s) { return s.dt_dev ? *s.dt_dev : s.dt; }

@@ -42,6 +42,7 @@ __global__ __launch_bounds__(BLOCK) void k_classify1d(KProb pb, KStep st) {
   const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const bool valid = k < pb.nIx;
   int ps = 1;
+  double smax = 0.0;
   if (valid) {
     if (st.replay) {
       ps = st.ordx[k];
@@ -57,6 +58,12 @@ __global__ __launch_bounds__(BLOCK) void k_classify1d(KProb pb, KStep st) {
         const int64_t node = bc_index(i - G + 1 + a, pb.nx, pb.bc);
 #pragma unroll
         for (int c = 0; c < NV; ++c) v[c][a] = st.u[c * pb.nx + node];
+      }
+      if (st.cfl_mode) {   // the cell of node 0 (every cell is node 0 of one interface)
+        double uc[NV];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) uc[c] = v[c][G - 1];
+        smax = spectral_radius<FLUX, 1, NV>(pb.ph, uc, 0);
       }
       ps = Select<NV, G, P>::run(v, pb.eps, pb.theta);
       double psi1 = -1.0, al = -1.0;
@@ -78,6 +85,11 @@ __global__ __launch_bounds__(BLOCK) void k_classify1d(KProb pb, KStep st) {
   if (valid) st.cls[k] = (int8_t)(ps - 1);
   __shared__ int sh[MAX_CLASSES];
   block_hist(sh, valid, ps - 1, st.hist);
+  if (st.cfl_mode) {
+    double dummy = 0.0;
+    block_max2(smax, dummy);
+    if (threadIdx.x == 0) st.part[blockIdx.x] = smax;
+  }
 }
 
 // CAT2p flux of the interfaces of order p (p = 1: FL-CAT2 blend).
@@ -253,6 +265,7 @@ __global__ __launch_bounds__(BLOCK) void k_classify2d(KProb pb, KStep st) {
   const bool needF = i2 >= 0, needG = i1 >= 0;
   const bool valid = e < pb.n1 * pb.n2 && (needF || needG);
   int q1 = 1, q2 = 1;
+  double sx = 0.0, sy = 0.0;
   if (valid) {
     const int64_t r2 = bc_index(i2, ny, pb.bc);   // ghost rows read the clamped row
     const int64_t r1 = bc_index(i1, nx, pb.bc);
@@ -272,6 +285,13 @@ __global__ __launch_bounds__(BLOCK) void k_classify2d(KProb pb, KStep st) {
         const int64_t x = bc_index(i1 - G + 1 + a, nx, pb.bc);
 #pragma unroll
         for (int c = 0; c < NV; ++c) v[c][a] = st.u[(c * ny + r2) * nx + x];
+      }
+      if (st.cfl_mode) {   // the corner's own cell (every cell is the cell of one corner)
+        double uc[NV];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) uc[c] = v[c][G - 1];
+        sx = spectral_radius<FLUX, 2, NV>(pb.ph, uc, 0);
+        sy = spectral_radius<FLUX, 2, NV>(pb.ph, uc, 1);
       }
       q1 = Select<NV, G, P>::run(v, pb.eps, pb.theta);
       if (needF) {
@@ -322,6 +342,13 @@ __global__ __launch_bounds__(BLOCK) void k_classify2d(KProb pb, KStep st) {
   if (e < pb.n1 * pb.n2) st.cls[e] = valid ? (int8_t)cls : (int8_t)-1;
   __shared__ int sh[MAX_CLASSES];
   block_hist(sh, valid, cls, st.hist);
+  if (st.cfl_mode) {
+    block_max2(sx, sy);
+    if (threadIdx.x == 0) {
+      st.part[2 * blockIdx.x] = sx;
+      st.part[2 * blockIdx.x + 1] = sy;
+    }
+  }
 }
 
 // One recursion over the rectangle J_Q1 x J_Q2 with time nodes J_QT
@@ -597,9 +624,10 @@ __global__ __launch_bounds__(BLOCK) void k_max_speed(KProb pb, const double* __r
   }
 }
 
-__global__ void k_cfl_dt(int dim, double dx, double dy, const double* smax, double cfl, double t_final,
-                         double* t_dev, double* dt_dev) {
-  double dt = dim == 1 ? cfl * dx / smax[0] : 0.5 * cfl * fmin(dx / smax[0], dy / smax[1]);
+// CFL rule: 1D cfl dx / s; 2D (Sec. 5.5) cfl/2 min(dx/s_x, dy/s_y); clipped at t_final
+__device__ __forceinline__ void cfl_rule(int dim, double dx, double dy, double s0, double s1, double cfl,
+                                         double t_final, double* t_dev, double* dt_dev) {
+  double dt = dim == 1 ? cfl * dx / s0 : 0.5 * cfl * fmin(dx / s0, dy / s1);
   if (t_dev) {
     const double t = *t_dev;
     if (t >= t_final) dt = 0.0;
@@ -607,6 +635,22 @@ __global__ void k_cfl_dt(int dim, double dx, double dy, const double* smax, doub
     *t_dev = t + dt;
   }
   *dt_dev = dt;
+}
+
+__global__ void k_cfl_dt(int dim, double dx, double dy, const double* smax, double cfl, double t_final,
+                         double* t_dev, double* dt_dev) {
+  cfl_rule(dim, dx, dy, smax[0], dim == 2 ? smax[1] : 0.0, cfl, t_final, t_dev, dt_dev);
+}
+
+// time step from the classification's per-block partial maxima (one block)
+__global__ __launch_bounds__(BLOCK) void k_cfl_part(KProb pb, KStep st, int nparts) {
+  double m0 = 0.0, m1 = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += BLOCK) {
+    m0 = fmax(m0, st.part[pb.dim * i]);
+    if (pb.dim == 2) m1 = fmax(m1, st.part[2 * i + 1]);
+  }
+  block_max2(m0, m1);
+  if (threadIdx.x == 0) cfl_rule(pb.dim, pb.dx, pb.dy, m0, m1, st.cfl, st.t_final, st.t_dev, st.dt_out);
 }
 
 // ================================================================ launchers
@@ -642,9 +686,16 @@ hipError_t lists1d_impl(const KProb& pb, const KStep& st, hipStream_t s) {
     k_classify1d<FLUX, NV, P><<<cblocks, BLOCK, 0, s>>>(pb, st);
   }
   ACAT_CHECK_LAUNCH();
-  k_scan_hist<<<P, BLOCK, 0, s>>>(st.hist, cblocks, st.offs, st.counts);
+  if (st.cfl_mode) {
+    ProfScope ps("cfl_from_classify", s);
+    k_cfl_part<<<1, BLOCK, 0, s>>>(pb, st, cblocks);
+  }
   ACAT_CHECK_LAUNCH();
-  k_scatter<P><<<cblocks, BLOCK, 0, s>>>(st.cls, 0, nI, cblocks, st.offs, st.counts, st.list);
+  {
+    ProfScope ps("class_lists", s);
+    k_scan_hist<<<P, BLOCK, 0, s>>>(st.hist, cblocks, st.offs, st.counts);
+    k_scatter<P><<<cblocks, BLOCK, 0, s>>>(st.cls, 0, nI, cblocks, st.offs, st.counts, st.list);
+  }
   ACAT_CHECK_LAUNCH();
   return hipSuccess;
 }
@@ -692,9 +743,16 @@ hipError_t lists2d_impl(const KProb& pb, const KStep& st, hipStream_t s) {
     k_classify2d<FLUX, NV, P><<<cblocks, BLOCK, 0, s>>>(pb, st);
   }
   ACAT_CHECK_LAUNCH();
-  k_scan_hist<<<P * P, BLOCK, 0, s>>>(st.hist, cblocks, st.offs, st.counts);
+  if (st.cfl_mode) {
+    ProfScope ps("cfl_from_classify", s);
+    k_cfl_part<<<1, BLOCK, 0, s>>>(pb, st, cblocks);
+  }
   ACAT_CHECK_LAUNCH();
-  k_scatter<P * P><<<cblocks, BLOCK, 0, s>>>(st.cls, 0, nc, cblocks, st.offs, st.counts, st.list);
+  {
+    ProfScope ps("class_lists", s);
+    k_scan_hist<<<P * P, BLOCK, 0, s>>>(st.hist, cblocks, st.offs, st.counts);
+    k_scatter<P * P><<<cblocks, BLOCK, 0, s>>>(st.cls, 0, nc, cblocks, st.offs, st.counts, st.list);
+  }
   ACAT_CHECK_LAUNCH();
   return hipSuccess;
 }
@@ -814,7 +872,7 @@ hipError_t launch_max_speed(const KProb& pb, const double* u, double* smax, hipS
   ACAT_CHECK_LAUNCH();
   const int64_t n = pb.nx * (pb.dim == 2 ? pb.ny : 1);
   int64_t blocks = (n + BLOCK - 1) / BLOCK;
-  if (blocks > 4 * num_cus()) blocks = 4 * num_cus();
+  if (blocks > num_cus()) blocks = num_cus();   // one atomic per block: few blocks, many cells each
   const unsigned gb = (unsigned)blocks;
   if (pb.dim == 1) {
     if (pb.flux == EUL) k_max_speed<EUL, 1, 3><<<gb, BLOCK, 0, s>>>(pb, u, sm);

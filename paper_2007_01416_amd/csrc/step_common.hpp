@@ -94,6 +94,28 @@ struct Slice {
 };
 
 // Per-block class histogram (LDS atomics), written without global atomics.
+// Block maximum of (m0, m1) (non-negative values); the result is valid in thread 0.
+__device__ __forceinline__ void block_max2(double& m0, double& m1) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    m0 = fmax(m0, __shfl_xor(m0, off));
+    m1 = fmax(m1, __shfl_xor(m1, off));
+  }
+  __shared__ double red[2][BLOCK / 64];
+  if (__lane_id() == 0) {
+    red[0][threadIdx.x >> 6] = m0;
+    red[1][threadIdx.x >> 6] = m1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 1; w < BLOCK / 64; ++w) {
+      m0 = fmax(m0, red[0][w]);
+      m1 = fmax(m1, red[1][w]);
+    }
+  }
+}
+
 __device__ __forceinline__ void block_hist(int* sh, bool valid, int cls, int32_t* out) {
   if (threadIdx.x < MAX_CLASSES) sh[threadIdx.x] = 0;
   __syncthreads();

@@ -19,7 +19,7 @@ from __future__ import annotations
 import torch
 
 from . import (Batch, Decisions, Problem, adjoint_workspace, cfl_dt, max_wave_speed, step, step_adjoint,
-               step_replay, workspace)
+               step_cfl, step_replay, workspace)
 
 
 class Solver:
@@ -50,13 +50,13 @@ class Solver:
     def step(self, dec: Decisions = None, replay: bool = False):
         """One CFL step (dt from the current state, clipped at t_final)."""
         p = self.prob
-        max_wave_speed(p, self.u, self.smax)
-        cfl_dt(p, self.smax, self.cfl, self.dt, self.t, self.t_final)
         out = self.buf[1 - self.cur]
         if replay:
+            max_wave_speed(p, self.u, self.smax)
+            cfl_dt(p, self.smax, self.cfl, self.dt, self.t, self.t_final)
             step_replay(p, self.u, self.dt, dec, out=out, ws=self.ws)
         else:
-            step(p, self.u, self.dt, out=out, ws=self.ws, dec=dec)
+            step_cfl(p, self.u, self.cfl, self.dt, self.t, self.t_final, out=out, ws=self.ws, dec=dec)
         self.cur ^= 1
         self.nsteps += 1
 
@@ -200,9 +200,7 @@ class AdjointRun:
         self.class_log = None   # optional int32 [nsteps, 16]: per-class item counts of each adjoint step
 
     def _step(self, u, out, n, dec):
-        max_wave_speed(self.prob, u, self.smax)
-        cfl_dt(self.prob, self.smax, self.cfl, self.dts[n:n + 1])
-        step(self.prob, u, self.dts[n:n + 1], out=out, ws=self.ws, dec=dec)
+        step_cfl(self.prob, u, self.cfl, self.dts[n:n + 1], out=out, ws=self.ws, dec=dec)
 
     def forward(self, u0: torch.Tensor) -> torch.Tensor:
         u = torch.as_tensor(u0, dtype=torch.float64, device=self.device).contiguous().clone()
@@ -243,9 +241,8 @@ class AdjointRun:
             u.copy_(self.checkpoints[s])
             for j in range(m):
                 out = self.seg_u[j + 1] if j + 1 < m else self.tmp   # the segment's last state is not needed
-                max_wave_speed(self.prob, self.seg_u[j], self.smax)
-                cfl_dt(self.prob, self.smax, self.cfl, dts[n0 + j:n0 + j + 1])
-                step(self.prob, self.seg_u[j], dts[n0 + j:n0 + j + 1], out=out, ws=self.ws, dec=self.seg_dec[j])
+                step_cfl(self.prob, self.seg_u[j], self.cfl, dts[n0 + j:n0 + j + 1], out=out, ws=self.ws,
+                         dec=self.seg_dec[j])
                 if self.verify:
                     hashes[n0 + j] = _order_hash(self.seg_dec[j])
             for j in reversed(range(m)):

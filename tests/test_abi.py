@@ -181,3 +181,17 @@ def test_adjoint_argument_errors_before_launch(lib):
     # 2D needs the y decisions too
     p2 = _prob(dim=2, nvar=4, nx=16, ny=16, dy=0.1)
     assert adj(ctypes.byref(p2.c()), a, 0.1, None, ctypes.byref(dec), b, c, ws, 16, None) == -1
+
+
+def test_step_cfl_argument_errors_before_launch(lib):
+    p = _prob()
+    pc = p.c()
+    buf = (ctypes.c_double * (3 * 64))()
+    buf2 = (ctypes.c_double * (3 * 64))()
+    a, b = ctypes.cast(buf, ctypes.c_void_p), ctypes.cast(buf2, ctypes.c_void_p)
+    ws = ctypes.create_string_buffer(16)
+    f = lib.acat_step_cfl
+    assert f(ctypes.byref(pc), a, b, 0.5, 1.0, None, None, ws, 16, None, None) == -1     # dt_dev required
+    assert f(ctypes.byref(pc), a, b, 0.0, 1.0, None, b, ws, 16, None, None) == -2      # cfl > 0
+    assert f(ctypes.byref(pc), a, a, 0.5, 1.0, None, b, ws, 16, None, None) == -3      # aliasing
+    assert f(ctypes.byref(pc), a, b, 0.5, 1.0, None, b, ws, 16, None, None) == -6      # workspace

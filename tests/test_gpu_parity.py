@@ -276,3 +276,34 @@ def test_full_size_c3_sampled(acat):
         assert np.array_equal(g, vals)
         s.run(4)
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("case", ["1d-periodic", "1d-transmissive", "2d-periodic", "2d-transmissive"])
+def test_step_cfl_equals_separate_cfl_calls(acat, case):
+    """acat_step_cfl (wave speeds reduced inside the classification) gives the
+    same time step, clock and state, bit for bit, as acat_max_wave_speed +
+    acat_cfl_dt + acat_step; the clock is clipped at t_final."""
+    import torch
+    dim, bc = case.split("-")
+    if dim == "1d":
+        w = workloads.euler_1d(n=1000, P=4)
+        po, pg = from_workload(w, bc=bc)
+    else:
+        w = workloads.euler_2d(n=96, P=3)
+        po, pg = from_workload(w, bc=bc)
+    u = T(w["u"])
+    for t_final in (float("inf"), 1e-4):
+        dt_a = torch.zeros(1, dtype=torch.float64, device="cuda")
+        t_a = torch.zeros(1, dtype=torch.float64, device="cuda")
+        sm = acat.max_wave_speed(pg, u)
+        acat.cfl_dt(pg, sm, w["cfl"], dt_a, t_a, t_final)
+        ua = acat.step(pg, u, dt_a)
+        dt_b = torch.zeros(1, dtype=torch.float64, device="cuda")
+        t_b = torch.zeros(1, dtype=torch.float64, device="cuda")
+        ub = acat.step_cfl(pg, u, w["cfl"], dt_b, t_b, t_final)
+        assert torch.equal(dt_a, dt_b) and torch.equal(t_a, t_b), (case, t_final)
+        assert torch.equal(ua, ub), (case, t_final)
+        if t_final < 1.0:
+            assert float(t_b.item()) == t_final
+        else:
+            assert float(dt_b.item()) == oracle.dt_cfl(po, w["u"], w["cfl"])
