@@ -265,8 +265,7 @@ __global__ __launch_bounds__(BLOCK) void k_gather1d(KProb pb, KStep st, const do
 template <int FLUX, int NV, int Q1, int Q2, int QT>
 __device__ __forceinline__ void corner_adjoint(const Phys& ph, double lamx, double lamy, const double (&u)[NV],
                                                const double (&f0)[NV], const double (&g0)[NV],
-                                               const double (&g1x)[2 * Q1], const double (&g1y)[2 * Q2],
-                                               const double (&g1xT)[2 * Q1], const double (&g1yT)[2 * Q2],
+                                               const double* gx, const double* gy,
                                                double2* xsb0, double2* xsb1, int stride, int& buf, int slot,
                                                int gbase, int a1, int a2, const double (&sfb)[NV],
                                                const double (&sgb)[NV], double (&ub)[NV], double (&f0b)[NV],
@@ -290,9 +289,11 @@ __device__ __forceinline__ void corner_adjoint(const Phys& ph, double lamx, doub
     for (int c = 0; c < NV; ++c) {
       double sx = 0.0, sy = 0.0;
 #pragma unroll
-      for (int l = 0; l < N1; ++l) sx = fma(g1x[l], Xch<NV>::get(xr, stride, gbase + a2 * N1 + l, c, false), sx);
+      for (int l = 0; l < N1; ++l)
+        sx = fma(gx[a1 * N1 + l], Xch<NV>::get(xr, stride, gbase + a2 * N1 + l, c, false), sx);
 #pragma unroll
-      for (int l = 0; l < N2; ++l) sy = fma(g1y[l], Xch<NV>::get(xr, stride, gbase + l * N1 + a1, c, true), sy);
+      for (int l = 0; l < N2; ++l)
+        sy = fma(gy[a2 * N2 + l], Xch<NV>::get(xr, stride, gbase + l * N1 + a1, c, true), sy);
       U[kk - 1][c] = -lamx * sx - lamy * sy;
     }
     buf ^= 1;
@@ -394,9 +395,9 @@ __device__ __forceinline__ void corner_adjoint(const Phys& ph, double lamx, doub
     for (int c = 0; c < NV; ++c) {
       double sx = 0.0, sy = 0.0;
 #pragma unroll
-      for (int j = 0; j < N1; ++j) sx += g1xT[j] * Xch<NV>::get(xr, stride, gbase + a2 * N1 + j, c, false);
+      for (int j = 0; j < N1; ++j) sx += gx[j * N1 + a1] * Xch<NV>::get(xr, stride, gbase + a2 * N1 + j, c, false);
 #pragma unroll
-      for (int j = 0; j < N2; ++j) sy += g1yT[j] * Xch<NV>::get(xr, stride, gbase + j * N1 + a1, c, true);
+      for (int j = 0; j < N2; ++j) sy += gy[j * N2 + a2] * Xch<NV>::get(xr, stride, gbase + j * N1 + a1, c, true);
       fhb[c] = TB.INVFACT[kk - 1] * sfb[c] - lamx * sx;
       ghb[c] = TB.INVFACT[kk - 1] * sgb[c] - lamy * sy;
     }
@@ -434,17 +435,13 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
   const int64_t nitems = pb.n1 * pb.n2;
   const int64_t cstride = nitems * LMAX;
 
-  double g1x[N1], g1y[N2], g1xT[N1], g1yT[N2];
-#pragma unroll
-  for (int l = 0; l < N1; ++l) {
-    g1x[l] = TB.G1[Q1][a1][l];
-    g1xT[l] = TB.G1[Q1][l][a1];
-  }
-#pragma unroll
-  for (int l = 0; l < N2; ++l) {
-    g1y[l] = TB.G1[Q2][a2][l];
-    g1yT[l] = TB.G1[Q2][l][a2];
-  }
+  // derivative weights in LDS, row-major: rows for the recursion, columns for its transpose
+  __shared__ double g1s[N1 * N1 + N2 * N2];
+  for (int i = tid; i < N1 * N1 + N2 * N2; i += BLOCK)
+    g1s[i] = i < N1 * N1 ? TB.G1[Q1][i / N1][i % N1] : TB.G1[Q2][(i - N1 * N1) / N2][(i - N1 * N1) % N2];
+  __syncthreads();
+  const double* gx = g1s;
+  const double* gy = g1s + N1 * N1;
   const bool on_row = a2 == Q2 - 1, on_col = a1 == Q1 - 1;
 
   int buf = 0;
@@ -500,13 +497,13 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
     }
     const int slot = g * L + nd;
     if constexpr (Q1 == Q2) {
-      corner_adjoint<FLUX, NV, Q1, Q2, Q1>(pb.ph, lamx, lamy, u, f0, g0, g1x, g1y, g1xT, g1yT, xs[0], xs[1],
-                                           STRIDE, buf, slot, g * L, a1, a2, sfb, sgb, ub, f0b, g0b);
+      corner_adjoint<FLUX, NV, Q1, Q2, Q1>(pb.ph, lamx, lamy, u, f0, g0, gx, gy, xs[0], xs[1], STRIDE, buf, slot,
+                                           g * L, a1, a2, sfb, sgb, ub, f0b, g0b);
     } else {
-      corner_adjoint<FLUX, NV, Q1, Q2, Q1>(pb.ph, lamx, lamy, u, f0, g0, g1x, g1y, g1xT, g1yT, xs[0], xs[1],
-                                           STRIDE, buf, slot, g * L, a1, a2, sfb, zero, ub, f0b, g0b);
-      corner_adjoint<FLUX, NV, Q1, Q2, Q2>(pb.ph, lamx, lamy, u, f0, g0, g1x, g1y, g1xT, g1yT, xs[0], xs[1],
-                                           STRIDE, buf, slot, g * L, a1, a2, zero, sgb, ub, f0b, g0b);
+      corner_adjoint<FLUX, NV, Q1, Q2, Q1>(pb.ph, lamx, lamy, u, f0, g0, gx, gy, xs[0], xs[1], STRIDE, buf, slot,
+                                           g * L, a1, a2, sfb, zero, ub, f0b, g0b);
+      corner_adjoint<FLUX, NV, Q1, Q2, Q2>(pb.ph, lamx, lamy, u, f0, g0, gx, gy, xs[0], xs[1], STRIDE, buf, slot,
+                                           g * L, a1, a2, zero, sgb, ub, f0b, g0b);
     }
     // Rusanov parts of the FL-CAT2 blends, on the two nodes each one reads
     if (Q1 == 1 && on_row && (a1 == Q1 - 1 || a1 == Q1)) {

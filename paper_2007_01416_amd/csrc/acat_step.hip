@@ -359,7 +359,7 @@ __global__ __launch_bounds__(BLOCK) void k_classify2d(KProb pb, KStep st) {
 template <int FLUX, int NV, int Q1, int Q2, int QT, bool DOF, bool DOG>
 __device__ __forceinline__ void corner_pass(const Phys& ph, double lamx, double lamy, const double (&u)[NV],
                                             const double (&f0)[NV], const double (&g0)[NV],
-                                            const double (&g1x)[2 * Q1], const double (&g1y)[2 * Q2],
+                                            const double* g1x, const double* g1y,
                                             double2* xsb0, double2* xsb1, int stride, int& buf, int slot,
                                             int gbase, int a1, int a2, double (&SF)[NV], double (&SG)[NV]) {
   constexpr int N1 = 2 * Q1;
@@ -460,11 +460,13 @@ __global__ __launch_bounds__(BLOCK) void k_flux2d(KProb pb, KStep st) {
   const int nx32 = (int)pb.nx, ny32 = (int)pb.ny, ioff = (int)pb.ioff;
   const uint32_t n1u = (uint32_t)pb.n1;
 
-  double g1x[N1], g1y[N2];
-#pragma unroll
-  for (int l = 0; l < N1; ++l) g1x[l] = TB.G1[Q1][a1][l];
-#pragma unroll
-  for (int l = 0; l < N2; ++l) g1y[l] = TB.G1[Q2][a2][l];
+  // derivative weights in LDS (read at each use rather than held in registers)
+  __shared__ double g1s[N1 * N1 + N2 * N2];
+  for (int i = tid; i < N1 * N1 + N2 * N2; i += BLOCK)
+    g1s[i] = i < N1 * N1 ? TB.G1[Q1][i / N1][i % N1] : TB.G1[Q2][(i - N1 * N1) / N2][(i - N1 * N1) % N2];
+  __syncthreads();
+  const double* g1x = g1s + a1 * N1;
+  const double* g1y = g1s + N1 * N1 + a2 * N2;
 
   int buf = 0;
   const Slice sl(st.counts, st.list, cls);
