@@ -174,47 +174,90 @@ class AdjointRun:
     record_all, the decisions of every step for replay()).  backward(ubar_n)
     -> ubar_0 = (d u_n / d u0)^T ubar_n with the decisions and time steps of
     the forward run frozen; segments are recomputed from their checkpoints.
-    With verify, the order maps of the recomputation are checked against
-    checksums taken in the forward pass.
+    With verify, the order maps and time steps of the recomputation are
+    checked against the forward pass.  With graphs, each segment (k forward
+    steps; k recomputed steps and k adjoint steps) is captured once into a
+    HIP graph on fixed buffers and replayed per segment.
     """
 
     def __init__(self, prob: Problem, cfl: float, nsteps: int, checkpoint_every: int = 20,
-                 record_all: bool = False, verify: bool = True, device="cuda"):
+                 record_all: bool = False, verify: bool = True, graphs: bool = True, device="cuda"):
         if nsteps < 1 or checkpoint_every < 1:
             raise ValueError("nsteps and checkpoint_every must be >= 1")
         self.prob, self.cfl, self.nsteps, self.k = prob, float(cfl), int(nsteps), int(checkpoint_every)
         self.device = device
+        k = min(self.k, self.nsteps)
+        shape = prob.shape
         self.ws = workspace(prob, device)
         self.aws = adjoint_workspace(prob, device)
-        self.smax = torch.zeros(2, dtype=torch.float64, device=device)
         self.dts = torch.zeros(self.nsteps, dtype=torch.float64, device=device)
-        self.seg_dec = [Decisions(prob, device) for _ in range(min(self.k, self.nsteps))]
-        self.seg_u = [torch.empty(prob.shape, dtype=torch.float64, device=device)
-                      for _ in range(min(self.k, self.nsteps))]
+        self.seg_dt = torch.zeros(k, dtype=torch.float64, device=device)
+        self.seg_dec = [Decisions(prob, device) for _ in range(k)]
+        self.seg_u = [torch.empty(shape, dtype=torch.float64, device=device) for _ in range(k)]
+        self.seg_cls = torch.zeros((k, 16), dtype=torch.int32, device=device)
+        self.fa = torch.empty(shape, dtype=torch.float64, device=device)    # forward state at segment bounds
+        self.fb = torch.empty(shape, dtype=torch.float64, device=device)
+        self.ub = torch.empty(shape, dtype=torch.float64, device=device)    # adjoint state
+        self.tmp = torch.empty(shape, dtype=torch.float64, device=device)
         self.record_all = record_all
         self.all_dec = [Decisions(prob, device) for _ in range(self.nsteps)] if record_all else None
         self.verify = verify
+        self.graphs = graphs
+        self._fgraphs, self._bgraphs = {}, {}
         self.hashes = torch.zeros(self.nsteps, dtype=torch.int64, device=device) if verify else None
-        self.tmp = torch.empty(prob.shape, dtype=torch.float64, device=device)
         self.checkpoints = []
         self.class_log = None   # optional int32 [nsteps, 16]: per-class item counts of each adjoint step
 
-    def _step(self, u, out, n, dec):
-        step_cfl(self.prob, u, self.cfl, self.dts[n:n + 1], out=out, ws=self.ws, dec=dec)
+    # ------------------------------------------------------------ segments
+    def _fwd_body(self, m, decs):
+        a, b = self.fa, self.fb
+        for j in range(m):
+            step_cfl(self.prob, a, self.cfl, self.seg_dt[j:j + 1], out=b, ws=self.ws, dec=decs[j])
+            a, b = b, a
+        if a is not self.fa:
+            self.fa.copy_(a)
+
+    def _bwd_body(self, m):
+        for j in range(m):
+            out = self.seg_u[j + 1] if j + 1 < m else self.tmp   # the segment's last state is not needed
+            step_cfl(self.prob, self.seg_u[j], self.cfl, self.seg_dt[j:j + 1], out=out, ws=self.ws,
+                     dec=self.seg_dec[j])
+        for j in reversed(range(m)):
+            step_adjoint(self.prob, self.seg_u[j], self.seg_dt[j:j + 1], self.seg_dec[j], self.ub,
+                         ubar_in=self.ub, ws=self.aws)
+            self.seg_cls[j].copy_(self.aws[:64].view(torch.int32))
+
+    def _run(self, cache, m, body):
+        """Run body(m) once; with graphs, the first run of a length is eager
+        and is followed by a capture that later segments of that length replay."""
+        if not self.graphs:
+            body()
+        elif m in cache:
+            cache[m].replay()
+        else:
+            body()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                body()
+            cache[m] = g
 
     def forward(self, u0: torch.Tensor) -> torch.Tensor:
-        u = torch.as_tensor(u0, dtype=torch.float64, device=self.device).contiguous().clone()
-        nxt = torch.empty_like(u)
+        self.fa.copy_(torch.as_tensor(u0, dtype=torch.float64, device=self.device))
         self.checkpoints = []
-        for n in range(self.nsteps):
-            if n % self.k == 0:
-                self.checkpoints.append(u.clone())
-            dec = self.all_dec[n] if self.record_all else (self.seg_dec[0] if self.verify else None)
-            self._step(u, nxt, n, dec)
+        for s, n0 in enumerate(range(0, self.nsteps, self.k)):
+            m = min(self.k, self.nsteps - n0)
+            self.checkpoints.append(self.fa.clone())
+            if self.record_all:       # every step's decisions kept: eager, into their own buffers
+                self._fwd_body(m, self.all_dec[n0:n0 + m])
+            else:
+                decs = self.seg_dec if self.verify else [None] * m
+                self._run(self._fgraphs, m, lambda: self._fwd_body(m, decs))
+            self.dts[n0:n0 + m].copy_(self.seg_dt[:m])
             if self.verify:
-                self.hashes[n] = _order_hash(dec)
-            u, nxt = nxt, u
-        return u
+                for j in range(m):
+                    d = self.all_dec[n0 + j] if self.record_all else self.seg_dec[j]
+                    self.hashes[n0 + j] = _order_hash(d)
+        return self.fa.clone()
 
     def replay(self, u0: torch.Tensor) -> torch.Tensor:
         """The frozen forward map (decisions and time steps of the last
@@ -231,29 +274,24 @@ class AdjointRun:
     def backward(self, ubar: torch.Tensor) -> torch.Tensor:
         if not self.checkpoints:
             raise RuntimeError("backward before forward")
-        ub = torch.as_tensor(ubar, dtype=torch.float64, device=self.device).contiguous().clone()
+        self.ub.copy_(torch.as_tensor(ubar, dtype=torch.float64, device=self.device))
         dts = torch.zeros(self.nsteps, dtype=torch.float64, device=self.device)
         hashes = torch.zeros_like(self.hashes) if self.verify else None
         for s in reversed(range(len(self.checkpoints))):
             n0 = s * self.k
             m = min(self.k, self.nsteps - n0)
-            u = self.seg_u[0]
-            u.copy_(self.checkpoints[s])
-            for j in range(m):
-                out = self.seg_u[j + 1] if j + 1 < m else self.tmp   # the segment's last state is not needed
-                step_cfl(self.prob, self.seg_u[j], self.cfl, dts[n0 + j:n0 + j + 1], out=out, ws=self.ws,
-                         dec=self.seg_dec[j])
-                if self.verify:
+            self.seg_u[0].copy_(self.checkpoints[s])
+            self._run(self._bgraphs, m, lambda: self._bwd_body(m))
+            dts[n0:n0 + m].copy_(self.seg_dt[:m])
+            if self.class_log is not None:
+                self.class_log[n0:n0 + m].copy_(self.seg_cls[:m])
+            if self.verify:
+                for j in range(m):
                     hashes[n0 + j] = _order_hash(self.seg_dec[j])
-            for j in reversed(range(m)):
-                step_adjoint(self.prob, self.seg_u[j], dts[n0 + j:n0 + j + 1], self.seg_dec[j], ub, ubar_in=ub,
-                             ws=self.aws)
-                if self.class_log is not None:
-                    self.class_log[n0 + j].copy_(self.aws[:64].view(torch.int32))
         if self.verify:
             if not torch.equal(hashes, self.hashes) or not torch.equal(dts, self.dts):
                 raise RuntimeError("recomputed decisions differ from the forward run")
-        return ub
+        return self.ub.clone()
 
 
 class ACATRun(torch.autograd.Function):

@@ -240,3 +240,23 @@ def test_checkpointed_run_matches_fd_of_replay(acat):
         best = min(abs((loss(run.replay(u0 + h * v)) - loss(run.replay(u0 - h * v))) / (2 * h) - ad)
                    for h in (1e-4, 1e-5, 1e-6))
         assert best <= TOL_FD * abs(ad), (j, best, ad)
+
+
+def test_graph_captured_segments_match_eager(acat):
+    """AdjointRun with graph-captured segments (k = 4, 10 steps: lengths 4
+    and 2) gives the same forward state and gradient, bit for bit, as the
+    eager run."""
+    import torch
+    w = workloads.adjoint_2d(n=64)
+    po, pg = from_workload(w)
+    u0 = torch.from_numpy(w["u"]).cuda()
+    res = []
+    for graphs in (False, True):
+        run = acat.AdjointRun(pg, w["cfl"], 10, checkpoint_every=4, graphs=graphs)
+        uT = run.forward(u0)
+        g = run.backward(uT * 0.5)
+        uT2 = run.forward(u0)                       # replayed graphs the second time
+        g2 = run.backward(uT2 * 0.5)
+        assert torch.equal(uT, uT2) and torch.equal(g, g2)
+        res.append((uT, g))
+    assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
