@@ -157,6 +157,7 @@ def bench_adjoint(acat, workloads, F, fd_dirs=32, fd_h=(1e-4, 1e-5, 1e-6, 1e-7, 
     plain.replay(1)
     plain = acat.Solver(pg, w["u"], cfl)
     plain.capture(k)
+    plain.u.copy_(u0)                            # the capture's warm-up steps moved the state
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plain.replay(nsteps // k)
