@@ -288,7 +288,7 @@ hipError_t step_b_impl(const KBatch& bt, const KBStep& st, hipStream_t s) {
     k_classify_b<FLUX, NV><<<cblocks, BLOCK, 0, s>>>(bt, st);
   }
   ACAT_CHECK_LAUNCH();
-  k_scan_hist<<<bt.Pmax, BLOCK, 0, s>>>(st.hist, cblocks, st.offs, st.counts);
+  k_scan_hist<<<bt.Pmax, SCAN_T, 0, s>>>(st.hist, cblocks, st.offs, st.counts, bt.Pmax, CflReduce{});
   ACAT_CHECK_LAUNCH();
   k_scatter<PMAX><<<cblocks, BLOCK, 0, s>>>(st.ord, 1, bt.nif, cblocks, st.offs, st.counts, st.list);
   ACAT_CHECK_LAUNCH();

@@ -626,36 +626,29 @@ __global__ __launch_bounds__(BLOCK) void k_max_speed(KProb pb, const double* __r
   }
 }
 
-// CFL rule: 1D cfl dx / s; 2D (Sec. 5.5) cfl/2 min(dx/s_x, dy/s_y); clipped at t_final
-__device__ __forceinline__ void cfl_rule(int dim, double dx, double dy, double s0, double s1, double cfl,
-                                         double t_final, double* t_dev, double* dt_dev) {
-  double dt = dim == 1 ? cfl * dx / s0 : 0.5 * cfl * fmin(dx / s0, dy / s1);
-  if (t_dev) {
-    const double t = *t_dev;
-    if (t >= t_final) dt = 0.0;
-    else if (t + dt > t_final) dt = t_final - t;
-    *t_dev = t + dt;
-  }
-  *dt_dev = dt;
-}
-
 __global__ void k_cfl_dt(int dim, double dx, double dy, const double* smax, double cfl, double t_final,
                          double* t_dev, double* dt_dev) {
   cfl_rule(dim, dx, dy, smax[0], dim == 2 ? smax[1] : 0.0, cfl, t_final, t_dev, dt_dev);
 }
 
-// time step from the classification's per-block partial maxima (one block)
-__global__ __launch_bounds__(BLOCK) void k_cfl_part(KProb pb, KStep st, int nparts) {
-  double m0 = 0.0, m1 = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += BLOCK) {
-    m0 = fmax(m0, st.part[pb.dim * i]);
-    if (pb.dim == 2) m1 = fmax(m1, st.part[2 * i + 1]);
-  }
-  block_max2(m0, m1);
-  if (threadIdx.x == 0) cfl_rule(pb.dim, pb.dx, pb.dy, m0, m1, st.cfl, st.t_final, st.t_dev, st.dt_out);
-}
 
 // ================================================================ launchers
+CflReduce cfl_reduce(const KProb& pb, const KStep& st, int nparts) {
+  CflReduce r{};
+  if (st.cfl_mode) {
+    r.part = st.part;
+    r.nparts = nparts;
+    r.dim = pb.dim;
+    r.dx = pb.dx;
+    r.dy = pb.dy;
+    r.cfl = st.cfl;
+    r.t_final = st.t_final;
+    r.t_dev = st.t_dev;
+    r.dt_out = st.dt_out;
+  }
+  return r;
+}
+
 #define ACAT_CHECK_LAUNCH()                  \
   do {                                       \
     hipError_t e_ = hipGetLastError();       \
@@ -688,14 +681,10 @@ hipError_t lists1d_impl(const KProb& pb, const KStep& st, hipStream_t s) {
     k_classify1d<FLUX, NV, P><<<cblocks, BLOCK, 0, s>>>(pb, st);
   }
   ACAT_CHECK_LAUNCH();
-  if (st.cfl_mode) {
-    ProfScope ps("cfl_from_classify", s);
-    k_cfl_part<<<1, BLOCK, 0, s>>>(pb, st, cblocks);
-  }
-  ACAT_CHECK_LAUNCH();
   {
     ProfScope ps("class_lists", s);
-    k_scan_hist<<<P, BLOCK, 0, s>>>(st.hist, cblocks, st.offs, st.counts);
+    k_scan_hist<<<P + (st.cfl_mode ? 1 : 0), SCAN_T, 0, s>>>(st.hist, cblocks, st.offs, st.counts, P,
+                                                            cfl_reduce(pb, st, cblocks));
     k_scatter<P><<<cblocks, BLOCK, 0, s>>>(st.cls, 0, nI, cblocks, st.offs, st.counts, st.list);
   }
   ACAT_CHECK_LAUNCH();
@@ -745,14 +734,10 @@ hipError_t lists2d_impl(const KProb& pb, const KStep& st, hipStream_t s) {
     k_classify2d<FLUX, NV, P><<<cblocks, BLOCK, 0, s>>>(pb, st);
   }
   ACAT_CHECK_LAUNCH();
-  if (st.cfl_mode) {
-    ProfScope ps("cfl_from_classify", s);
-    k_cfl_part<<<1, BLOCK, 0, s>>>(pb, st, cblocks);
-  }
-  ACAT_CHECK_LAUNCH();
   {
     ProfScope ps("class_lists", s);
-    k_scan_hist<<<P * P, BLOCK, 0, s>>>(st.hist, cblocks, st.offs, st.counts);
+    k_scan_hist<<<P * P + (st.cfl_mode ? 1 : 0), SCAN_T, 0, s>>>(st.hist, cblocks, st.offs, st.counts, P * P,
+                                                                cfl_reduce(pb, st, cblocks));
     k_scatter<P * P><<<cblocks, BLOCK, 0, s>>>(st.cls, 0, nc, cblocks, st.offs, st.counts, st.list);
   }
   ACAT_CHECK_LAUNCH();

@@ -124,30 +124,91 @@ __device__ __forceinline__ void block_hist(int* sh, bool valid, int cls, int32_t
   if (threadIdx.x < MAX_CLASSES) out[(int64_t)blockIdx.x * MAX_CLASSES + threadIdx.x] = sh[threadIdx.x];
 }
 
-// offs[c][t] = items of class c in tiles < t, counts[c] = total; one block per class.
-__global__ __launch_bounds__(BLOCK) void k_scan_hist(const int32_t* hist, int ntiles, int32_t* offs,
-                                                     int32_t* counts) {
-  __shared__ int part[BLOCK];
-  const int c = blockIdx.x;
-  const int per = (ntiles + BLOCK - 1) / BLOCK;
-  const int t0 = threadIdx.x * per;
+// CFL rule: 1D cfl dx / s; 2D (Sec. 5.5) cfl/2 min(dx/s_x, dy/s_y); clipped at t_final
+__device__ __forceinline__ void cfl_rule(int dim, double dx, double dy, double s0, double s1, double cfl,
+                                         double t_final, double* t_dev, double* dt_dev) {
+  double dt = dim == 1 ? cfl * dx / s0 : 0.5 * cfl * fmin(dx / s0, dy / s1);
+  if (t_dev) {
+    const double t = *t_dev;
+    if (t >= t_final) dt = 0.0;
+    else if (t + dt > t_final) dt = t_final - t;
+    *t_dev = t + dt;
+  }
+  *dt_dev = dt;
+}
+
+// Optional time step from per-block partial wave-speed maxima [nparts][dim].
+struct CflReduce {
+  const double* part;   // null: none
+  int nparts, dim;
+  double dx, dy, cfl, t_final;
+  double* t_dev;
+  double* dt_out;
+};
+
+constexpr int SCAN_T = 1024;   // threads of the class-list prefix kernel
+
+// offs[c][t] = items of class c in tiles < t, counts[c] = total: one block per
+// class, each thread summing a contiguous chunk of tiles, then a block-wide
+// exclusive scan of the chunk sums.  With cr.part, block ncls reduces the
+// partial maxima and writes the CFL time step.
+__global__ __launch_bounds__(SCAN_T) void k_scan_hist(const int32_t* hist, int ntiles, int32_t* offs,
+                                                      int32_t* counts, int ncls, CflReduce cr) {
+  __shared__ int wsum[SCAN_T / 64];
+  __shared__ double wmax[2][SCAN_T / 64];
+  const int c = blockIdx.x, tid = threadIdx.x, lane = __lane_id(), wid = tid >> 6;
+  if (c == ncls) {   // time step
+    double m0 = 0.0, m1 = 0.0;
+    for (int i = tid; i < cr.nparts; i += SCAN_T) {
+      m0 = fmax(m0, cr.part[cr.dim * i]);
+      if (cr.dim == 2) m1 = fmax(m1, cr.part[2 * i + 1]);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      m0 = fmax(m0, __shfl_xor(m0, off));
+      m1 = fmax(m1, __shfl_xor(m1, off));
+    }
+    if (lane == 0) {
+      wmax[0][wid] = m0;
+      wmax[1][wid] = m1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int w = 1; w < SCAN_T / 64; ++w) {
+        m0 = fmax(m0, wmax[0][w]);
+        m1 = fmax(m1, wmax[1][w]);
+      }
+      cfl_rule(cr.dim, cr.dx, cr.dy, m0, m1, cr.cfl, cr.t_final, cr.t_dev, cr.dt_out);
+    }
+    return;
+  }
+  const int per = (ntiles + SCAN_T - 1) / SCAN_T;
+  const int t0 = tid * per;
+  const int t1 = min(t0 + per, ntiles);
   int acc = 0;
-  for (int t = t0; t < t0 + per && t < ntiles; ++t) acc += hist[(int64_t)t * MAX_CLASSES + c];
-  part[threadIdx.x] = acc;
+  for (int t = t0; t < t1; ++t) acc += hist[(int64_t)t * MAX_CLASSES + c];
+  // block-wide exclusive scan of acc: wave inclusive scan, then the wave totals
+  int inc = acc;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(inc, off);
+    if (lane >= off) inc += v;
+  }
+  if (lane == 63) wsum[wid] = inc;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     int run = 0;
-    for (int k = 0; k < BLOCK; ++k) {
-      const int v = part[k];
-      part[k] = run;
+    for (int w = 0; w < SCAN_T / 64; ++w) {
+      const int v = wsum[w];
+      wsum[w] = run;
       run += v;
     }
     counts[c] = run;
     offs[(int64_t)c * (ntiles + 1) + ntiles] = run;
   }
   __syncthreads();
-  int run = part[threadIdx.x];
-  for (int t = t0; t < t0 + per && t < ntiles; ++t) {
+  int run = wsum[wid] + inc - acc;
+  for (int t = t0; t < t1; ++t) {
     offs[(int64_t)c * (ntiles + 1) + t] = run;
     run += hist[(int64_t)t * MAX_CLASSES + c];
   }
