@@ -113,6 +113,29 @@ def bench_batched(acat, workloads, steps_batched=500, steps_single=10):
             s.step()
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
+    # roofline of the dominant per-order flux kernel: a few eager steps with the
+    # library's kernel timer and the per-order interface counts of each step
+    from paper_2007_01416_amd import flops as F
+    batch.set_launch({p: v[:2] for p, v in best.items()})
+    ue = torch.from_numpy(u0).cuda()
+    uo = torch.empty_like(ue)
+    dte = torch.empty(batch.nprob, dtype=torch.float64, device="cuda")
+    counts = batch.ws[:16].view(torch.int32)
+    nprof = 20
+    hist = torch.zeros((nprof, 4), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    acat.profile(True)
+    for k in range(nprof):
+        batch.cfl_dt(ue, w["cfl"], dte)
+        batch.step(ue, dte, out=uo)
+        hist[k].copy_(counts)
+        ue, uo = uo, ue
+    prof = acat.profile_read()
+    acat.profile(False)
+    per_p = hist.cpu().numpy().astype(np.int64).sum(0)
+    kern = {p: prof[f"flux_b_p{p}"] for p in batch.orders if f"flux_b_p{p}" in prof}
+    dom = max(kern, key=lambda p: kern[p][1])
+    ach = per_p[dom - 1] * F.interface_flops_1d(dom, 3, F.C_F[("euler", 1)]) / (kern[dom][1] * 1e-3) / 1e12
     cells = batch.ncell
     vb = cells * steps_batched / tb
     vs = cells * steps_single / ts
@@ -123,7 +146,10 @@ def bench_batched(acat, workloads, steps_batched=500, steps_single=10):
             "per_instance_ms_per_step": 1e3 * ts / steps_single, "speedup_vs_per_instance": vb / vs,
             "autotuned_launch": {f"p{p}": {"waves_per_block": v[0], "blocks_per_cu": v[1],
                                            "kernel_us": round(1e3 * v[2], 2)} for p, v in best.items()},
-            "default_launch_ms_per_step": 1e3 * tdef / steps_batched}
+            "default_launch_ms_per_step": 1e3 * tdef / steps_batched,
+            "roofline": {"bound": "alu", "kernel": f"flux_b_p{dom}", "achieved": ach, "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS,
+                         "avg_launch_us": 1e3 * kern[dom][1] / kern[dom][0]}}
 
 
 def bench_adjoint(acat, workloads, F, fd_dirs=32, fd_h=(1e-4, 1e-5, 1e-6, 1e-7, 1e-8)):

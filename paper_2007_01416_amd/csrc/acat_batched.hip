@@ -221,13 +221,15 @@ __global__ __launch_bounds__(BLOCK) void k_update_b(KBatch bt, KBStep st) {
   if (bad) atomicOr(st.status, bad);
 }
 
-// smax[b] = max spectral radius over problem b: one block per problem, no atomics.
+// smax[b] = max spectral radius over problem b: one 1024-thread block per
+// problem (a few cells per thread even for the largest problems), no atomics.
+constexpr int MSB_T = 1024;
 template <int FLUX, int NV>
-__global__ __launch_bounds__(BLOCK) void k_max_speed_b(KBatch bt, const double* __restrict__ u, double* smax) {
+__global__ __launch_bounds__(MSB_T) void k_max_speed_b(KBatch bt, const double* __restrict__ u, double* smax) {
   const int b = blockIdx.x;
   const int64_t c0 = bt.coff[b], c1 = bt.coff[b + 1];
   double m = 0.0;
-  for (int64_t e = c0 + threadIdx.x; e < c1; e += BLOCK) {
+  for (int64_t e = c0 + threadIdx.x; e < c1; e += MSB_T) {
     double w[NV];
 #pragma unroll
     for (int c = 0; c < NV; ++c) w[c] = u[c * bt.ncell + e];
@@ -235,12 +237,12 @@ __global__ __launch_bounds__(BLOCK) void k_max_speed_b(KBatch bt, const double* 
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
-  __shared__ double red[BLOCK / 64];
+  __shared__ double red[MSB_T / 64];
   if (__lane_id() == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int w = 1; w < BLOCK / 64; ++w) m = fmax(m, red[w]);
+    for (int w = 1; w < MSB_T / 64; ++w) m = fmax(m, red[w]);
     smax[b] = m;
   }
 }
@@ -309,7 +311,7 @@ template <int FLUX, int NV>
 hipError_t cfl_b_impl(const KBatch& bt, const double* u, double cfl, double* smax, double* dt, hipStream_t s) {
   {
     ProfScope ps("max_speed_b", s);
-    k_max_speed_b<FLUX, NV><<<bt.nprob, BLOCK, 0, s>>>(bt, u, smax);
+    k_max_speed_b<FLUX, NV><<<bt.nprob, MSB_T, 0, s>>>(bt, u, smax);
   }
   ACAT_CHECK_LAUNCH();
   k_dt_b<<<(bt.nprob + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(bt, smax, cfl, dt);
