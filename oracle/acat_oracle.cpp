@@ -27,8 +27,10 @@
 //   * the robust first-order flux F^lo is Rusanov (local Lax-Friedrichs)
 //     with alpha = max of the two cells' spectral radii;
 //   * psi^1 is the speed-free min form of the superbee limiter (Sec. 3.1),
-//     applied per conserved component; a component with u_{i+1} = u_i
-//     contributes 1;
+//     applied per conserved component; where u_{i+1} = u_i the ratios are
+//     undefined: the component contributes 1 if it is constant on the four
+//     points, 0 otherwise (a plateau beside a variation is an extremum or a
+//     corner; for a scalar law F^1 = F^lo there and the value is immaterial);
 //   * 2D: corner i uses the rectangle J_{q1} x J_{q2}, q1 the order of the
 //     x-interface i+e1/2 and q2 the order of the y-interface i+e2/2 (Sec. 4,
 //     rectangular stencils); F is computed with Taylor order 2 q1 and time
@@ -349,7 +351,7 @@ double superbee(double r) {
 double limiter_psi1(const double* v, int P) {
   auto at = [&](int j) { return v[j + P - 1]; };
   double dloc = at(1) - at(0);
-  if (dloc == 0.0) return 1.0;
+  if (dloc == 0.0) return (at(0) - at(-1) == 0.0 && at(2) - at(1) == 0.0) ? 1.0 : 0.0;
   double rm = (at(0) - at(-1)) / dloc;
   double rp = (at(2) - at(1)) / dloc;
   return std::min(superbee(rp), superbee(rm));

@@ -131,8 +131,8 @@ def superbee(r):
 def limiter(v):
     """psi^1 = min(phi(r+), phi(r-)) on values at offsets -1..2 (Sec. 3.1)."""
     dl = v[2] - v[1]
-    if dl == 0:
-        return Fr(1)
+    if dl == 0:   # ratios undefined: constant on the four points -> 1, else 0
+        return Fr(1) if (v[1] == v[0] and v[3] == v[2]) else Fr(0)
     return min(superbee((v[3] - v[2]) / dl), superbee((v[1] - v[0]) / dl))
 
 

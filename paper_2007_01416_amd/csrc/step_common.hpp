@@ -64,12 +64,12 @@ __device__ __forceinline__ double limiter(const double (&v)[NV][2 * G]) {
 #pragma unroll
   for (int c = 0; c < NV; ++c) {
     const double dl = v[c][G] - v[c][G - 1];
-    double l = 1.0;
-    if (dl != 0.0) {
-      const double rm = (v[c][G - 1] - v[c][G - 2]) / dl;
-      const double rp = (v[c][G + 1] - v[c][G]) / dl;
-      l = fmin(superbee(rp), superbee(rm));
-    }
+    const double dm = v[c][G - 1] - v[c][G - 2], dp = v[c][G + 1] - v[c][G];
+    // ratio undefined when the central difference vanishes: a locally
+    // constant component is smooth (1), a plateau next to a variation is an
+    // extremum or a corner (0)
+    double l = (dm == 0.0 && dp == 0.0) ? 1.0 : 0.0;
+    if (dl != 0.0) l = fmin(superbee(dp / dl), superbee(dm / dl));
     psi = fmin(psi, l);
   }
   return psi;

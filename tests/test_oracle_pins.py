@@ -239,7 +239,9 @@ def test_superbee_limiter():
     # r = (du_upw)/(du_loc); values at -1, 0, 1, 2
     assert oracle.limiter([0, 1, 2, 3]) == 1.0              # r = 1 both sides
     assert oracle.limiter([0, 0, 1, 1]) == 0.0              # flat neighbours: r = 0
-    assert oracle.limiter([0, 1, 1, 1]) == 1.0              # du_loc = 0 reading: 1
+    assert oracle.limiter([0, 1, 1, 1]) == 0.0              # du_loc = 0 beside a variation: 0
+    assert oracle.limiter([1, 1, 1, 1]) == 1.0              # du_loc = 0, locally constant: 1
+    assert oracle.limiter([1, 0.4, 0.4, 1]) == 0.0          # du_loc = 0 at an extremum: 0
     assert oracle.limiter([0, 2, 3, 5]) == 2.0              # r = 2 both sides: phi = 2 (not clipped to 1)
     assert oracle.limiter([0, 0.25, 1.25, 1.5]) == 0.5       # r = 1/4: phi = 2r
     assert oracle.limiter([0, 3, 4, 9]) == 2.0               # r- = 3, r+ = 5: phi = 2

@@ -184,3 +184,84 @@ def smooth_direction(seed, k, shape):
         for ax in (-1, -2):
             d = (np.roll(d, 1, axis=ax) + 2 * d + np.roll(d, -1, axis=ax)) / 4
     return d / np.abs(d).max()
+
+
+# ---------------------------------------------------------------------------
+# The paper's own experiments (Sec. 5), with the printed initial data, grids,
+# CFL numbers and final times.  Each returns the same dict as above plus
+# `t_final` and, for Riemann problems, the primitive left/right states.
+RIEMANN_1D = {
+    # Sec. 5.3: discontinuity at x = 1/2 on [0, 1], 200 points, CFL 0.8
+    "sod": dict(left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1), n=200, cfl=0.8, t_final=0.25),
+    "einfeldt123": dict(left=(1.0, -2.0, 0.4), right=(1.0, 2.0, 0.4), n=200, cfl=0.8, t_final=0.15),
+    "blast_right": dict(left=(1.0, 0.0, 1000.0), right=(1.0, 0.0, 0.01), n=450, cfl=0.8, t_final=0.012),
+}
+
+
+def paper_riemann_1d(name, n=None, P=3):
+    """Shock-tube problems of the 1D Euler experiments (Sec. 5.3); outflow
+    (transmissive) boundaries, gamma = 1.4."""
+    c = RIEMANN_1D[name]
+    n = n or c["n"]
+    x, dx = centres(0.0, 1.0, n)
+    (rl, ul, pl), (rr, ur, pr) = c["left"], c["right"]
+    left = x < 0.5
+    u = euler1d_conserved(np.where(left, rl, rr), np.where(left, ul, ur), np.where(left, pl, pr))
+    return dict(u=u, dx=dx, flux="euler", P=P, bc="transmissive", cfl=c["cfl"], t_final=c["t_final"], nvar=3,
+                dim=1, gamma=GAMMA, left=c["left"], right=c["right"], x=x)
+
+
+def paper_scalar_1d(name, n=160, P=3):
+    """Scalar experiments of Sec. 5.1-5.2 on [0, 2], periodic, CFL 0.9:
+    transport of 1/2 sin(pi x) (t = 4) or of the square wave (t = 2),
+    Burgers from 1/2 sin(pi x) (t = 1)."""
+    x, dx = centres(0.0, 2.0, n)
+    if name == "transport_sine":
+        u, flux, t = 0.5 * np.sin(np.pi * x), "advection", 4.0
+    elif name == "transport_square":
+        u = np.where((x >= 0.5) & (x <= 1.0), 1.0, np.where((x > 1.0) & (x <= 1.5), -1.0, 0.0))
+        flux, t = "advection", 2.0
+    elif name == "burgers_sine":
+        u, flux, t = 0.5 * np.sin(np.pi * x), "burgers", 1.0
+    else:
+        raise KeyError(name)
+    return dict(u=u[None, :].copy(), dx=dx, flux=flux, P=P, bc="periodic", cfl=0.9, t_final=t, nvar=1, dim=1,
+                x=x, ax=1.0)
+
+
+LAX_LIU = {
+    # Sec. 5.5 tables of the 2D Riemann problems: quadrant -> (rho, u, v, p);
+    # quadrant 1: x > 1/2, y > 1/2; 2: x < 1/2, y > 1/2; 3: x < 1/2, y < 1/2; 4: x > 1/2, y < 1/2
+    4: dict(q={1: (1.1, 0.0, 0.0, 1.1), 2: (0.5065, 0.8939, 0.0, 0.35), 3: (1.1, 0.8939, 0.8939, 1.1),
+               4: (0.5065, 0.0, 0.8939, 0.35)}, t_final=0.25),
+    6: dict(q={1: (1.0, 0.75, -0.5, 1.0), 2: (2.0, 0.75, 0.5, 1.0), 3: (1.0, -0.75, 0.5, 1.0),
+               4: (3.0, -0.75, -0.5, 1.0)}, t_final=0.3),
+    8: dict(q={1: (0.5197, 0.1, 0.1, 0.4), 2: (1.0, -0.6259, 0.1, 1.0), 3: (0.8, 0.1, 0.1, 1.0),
+               4: (1.0, 0.1, -0.6259, 1.0)}, t_final=0.25),
+}
+
+
+def paper_lax_liu(config, n=400, P=2):
+    """2D Riemann problems of Sec. 5.5 on [0, 1]^2 (free, i.e. transmissive,
+    boundaries, CFL 0.475 with the halved 2D rule)."""
+    c = LAX_LIU[config]
+    x, dx = centres(0.0, 1.0, n)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    quad = np.where(X > 0.5, np.where(Y > 0.5, 1, 4), np.where(Y > 0.5, 2, 3))
+    prim = np.zeros((4,) + X.shape)
+    for q, st in c["q"].items():
+        for k in range(4):
+            prim[k] = np.where(quad == q, st[k], prim[k])
+    u = euler2d_conserved(prim[0], prim[1], prim[2], prim[3])
+    return dict(u=np.ascontiguousarray(u), dx=dx, dy=dx, flux="euler", P=P, bc="transmissive", cfl=0.475,
+                t_final=c["t_final"], nvar=4, dim=2, gamma=GAMMA)
+
+
+def paper_transport_2d(n=100, P=2):
+    """2D transport u_t + u_x + u_y = 0 on [0, 2]^2 from the indicator of
+    x + y <= 1/4, free boundaries, CFL 0.5, t = 1 (Sec. 5.4)."""
+    x, dx = centres(0.0, 2.0, n)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    u = np.where(X + Y <= 0.25, 1.0, 0.0)[None]
+    return dict(u=np.ascontiguousarray(u), dx=dx, dy=dx, flux="advection", P=P, bc="transmissive", cfl=0.5,
+                t_final=1.0, nvar=1, dim=2, ax=1.0, ay=1.0)
