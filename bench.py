@@ -261,6 +261,40 @@ def bench_adjoint(acat, workloads, F, fd_dirs=32, fd_h=(1e-4, 1e-5, 1e-6, 1e-7, 
                          "seconds": t_fd}}
 
 
+def bench_paper(acat, workloads):
+    """Cost of ACAT2 / ACAT4 / ACAT6 (P = 1, 2, 3) on the paper's two timed
+    experiments, next to the paper's CPU-time ratios (Matlab, Sec. 5.3 and
+    Sec. 5.5 tables): the right blast wave (450 points, t = 0.012) and the
+    2D Riemann problem of configuration 8 (400 x 400, t = 0.25), each run to
+    its final time from a cold state (graph-free time loop)."""
+    import torch
+    out = {}
+    cases = [("blast_right_1d_450", lambda P: workloads.paper_riemann_1d("blast_right", P=P),
+              {"ACAT2": 1.0, "ACAT4": 5.88, "ACAT6": 12.46}),
+             ("lax_liu_8_2d_400x400", lambda P: workloads.paper_lax_liu(8, n=400, P=P),
+              {"ACAT2": 1.0, "ACAT4": 9.98, "ACAT6": 96.91})]
+    for name, make, paper in cases:
+        res = {}
+        for P in (1, 2, 3):
+            w = make(P)
+            kw = dict(dim=w["dim"], nvar=w["nvar"], nx=w["u"].shape[-1], flux="euler", P=P, bc=w["bc"], dx=w["dx"],
+                      gamma=w["gamma"])
+            if w["dim"] == 2:
+                kw.update(ny=w["u"].shape[1], dy=w["dy"])
+            prob = acat.Problem(**kw)
+            s = acat.Solver(prob, w["u"], w["cfl"], t_final=w["t_final"])
+            s.step()
+            s = acat.Solver(prob, w["u"], w["cfl"], t_final=w["t_final"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.run_to_end(check_every=32)
+            torch.cuda.synchronize()
+            res[f"ACAT{2 * P}"] = {"ms": 1e3 * (time.perf_counter() - t0), "steps": s.nsteps}
+        base = res["ACAT2"]["ms"]
+        out[name] = {k: dict(v, ratio=round(v["ms"] / base, 3), paper_ratio=paper[k]) for k, v in res.items()}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,7 +304,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and adjoint workloads")
     ap.add_argument("--fd-dirs", type=int, default=32, help="finite-difference directions of the adjoint check")
-    ap.add_argument("--only", choices=["batched", "adjoint"],
+    ap.add_argument("--only", choices=["batched", "adjoint", "paper"],
                     help="run only that workload and print its object (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference dispatch for HBM byte counters)")
@@ -288,6 +322,9 @@ def main():
     acat.load()
     if args.only == "batched":
         print(json.dumps(bench_batched(acat, workloads)), flush=True)
+        return
+    if args.only == "paper":
+        print(json.dumps(bench_paper(acat, workloads)), flush=True)
         return
     if args.only == "adjoint":
         print(json.dumps(bench_adjoint(acat, workloads, F, fd_dirs=args.fd_dirs)), flush=True)
@@ -366,6 +403,8 @@ def main():
     if not args.no_extra:
         print("[bench] batched 1D workload", file=sys.stderr, flush=True)
         out["batched"] = bench_batched(acat, workloads)
+        print("[bench] paper experiments", file=sys.stderr, flush=True)
+        out["paper_cost_ratios"] = bench_paper(acat, workloads)
         print("[bench] adjoint workload", file=sys.stderr, flush=True)
         out["adjoint"] = bench_adjoint(acat, workloads, F, fd_dirs=args.fd_dirs)
     if not args.no_cpu_baseline:

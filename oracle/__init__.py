@@ -25,6 +25,9 @@ _LIB = os.path.join(_HERE, "_oracle.so")
 
 FLUX_ADVECTION, FLUX_BURGERS, FLUX_EULER = 0, 1, 2
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
+# variants (Problem.flags): first-order flux Lax-Friedrichs / HLL instead of
+# Rusanov, modified p = 2 indicator, Roe-speed upwind psi^1 (scalar laws)
+FLAG_FLO_LF, FLAG_FLO_HLL, FLAG_PSI2_MODIFIED, FLAG_PSI1_ROE = 1, 2, 4, 8
 
 
 def build(force: bool = True) -> str:
@@ -41,7 +44,7 @@ class _Problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("nvar", ctypes.c_int32),
                 ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
                 ("flux", ctypes.c_int32), ("P", ctypes.c_int32), ("bc", ctypes.c_int32),
-                ("psi1_mode", ctypes.c_int32),
+                ("flags", ctypes.c_int32),
                 ("gamma", ctypes.c_double), ("ax", ctypes.c_double), ("ay", ctypes.c_double),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double),
                 ("eps", ctypes.c_double), ("theta", ctypes.c_double)]
@@ -63,9 +66,10 @@ class Problem:
     dy: float = 1.0
     eps: float = 1e-12
     theta: float = 0.5
+    flags: int = 0      # FLAG_* variants (default method: 0)
 
     def c(self) -> _Problem:
-        return _Problem(self.dim, self.nvar, self.nx, self.ny, self.flux, self.P, self.bc, 0,
+        return _Problem(self.dim, self.nvar, self.nx, self.ny, self.flux, self.P, self.bc, self.flags,
                         self.gamma, self.ax, self.ay, self.dx, self.dy, self.eps, self.theta)
 
     @property
@@ -91,6 +95,8 @@ def lib():
         L.oracle_indicator.restype = ctypes.c_double
         L.oracle_limiter.argtypes = [d]
         L.oracle_limiter.restype = ctypes.c_double
+        L.oracle_indicator2_modified.argtypes = [d, ctypes.c_double]
+        L.oracle_indicator2_modified.restype = ctypes.c_double
         L.oracle_step1d.argtypes = [P(_Problem), d, d, ctypes.c_double, ctypes.c_int, i8, d, d, d, ctypes.c_int]
         L.oracle_step1d_jvp.argtypes = [P(_Problem), d, d, d, d, ctypes.c_double, i8, d, d, ctypes.c_int]
         L.oracle_step2d.argtypes = [P(_Problem), d, d, ctypes.c_double, ctypes.c_int, i8, i8, d, d, d, d, d, d,
@@ -132,6 +138,13 @@ def limiter(v) -> float:
     v = np.ascontiguousarray(v, dtype=np.float64)
     assert v.shape == (4,)
     return lib().oracle_limiter(_p(v))
+
+
+def indicator2_modified(v, eps: float = 1e-12) -> float:
+    """Modified p = 2 indicator (Sec. 3.2) on values at offsets -1..2."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    assert v.shape == (4,)
+    return lib().oracle_indicator2_modified(_p(v), eps)
 
 
 def _state(prob: Problem, u):

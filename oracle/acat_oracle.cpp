@@ -241,7 +241,7 @@ extern "C" {
 typedef struct {
   int32_t dim, nvar;
   int64_t nx, ny;
-  int32_t flux, P, bc, psi1_mode;
+  int32_t flux, P, bc, flags;
   double gamma, ax, ay, dx, dy, eps, theta;
 } oracle_problem;
 }
@@ -327,6 +327,37 @@ int64_t bc_index(int64_t i, int64_t n, int bc) {
 // ---------------------------------------------------------------------------
 
 // psi^p for one component, stencil S_p centred at the interface i+1/2.
+// Variants the paper describes beside the default method (bits of flags):
+// the first-order flux F^lo of the blend is Lax-Friedrichs or HLL instead of
+// Rusanov (Sec. 5 lists LF and HLL as the first-order schemes), the p = 2
+// indicator is the modified one of Sec. 3.2, and for scalar laws psi^1 may
+// use the upwind ratio chosen by the sign of Roe's speed (Sec. 3.1).
+enum { FLAG_FLO_LF = 1, FLAG_FLO_HLL = 2, FLAG_PSI2_MODIFIED = 4, FLAG_PSI1_ROE = 8 };
+
+// Modified p = 2 indicator (Sec. 3.2): two pairs of lateral weights, each
+// joining the central sub-interval to one side; the larger ratio.
+double indicator_psi2_modified(const double* v, int P, double eps) {
+  const Tables& T = tables();
+  auto at = [&](int j) { return v[j + P - 1]; };
+  const double dl = at(0) - at(-1), dc = at(1) - at(0), dr = at(2) - at(1);
+  double I1L = dl * dl;
+  I1L += eps;
+  double I1R = dc * dc;
+  I1R += dr * dr;
+  I1R += eps;
+  double I2L = dl * dl;
+  I2L += dc * dc;
+  I2L += eps;
+  double I2R = dr * dr;
+  I2R += eps;
+  const double I1 = I1L * I1R / (I1L + I1R), I2 = I2L * I2R / (I2L + I2R);
+  double s = 0.0;
+  for (int j = -1; j <= 2; ++j) s += T.tau[2][j + 1] * at(j);
+  double tau = T.fact2pm1[2] * s;
+  tau = tau * tau;
+  return std::max(I1 / (I1 + tau), I2 / (I2 + tau));
+}
+
 double indicator_psi(const double* v, int P, int p, double eps) {
   const Tables& T = tables();
   auto at = [&](int j) { return v[j + P - 1]; };
@@ -357,6 +388,22 @@ double limiter_psi1(const double* v, int P) {
   return std::min(superbee(rp), superbee(rm));
 }
 
+// psi^1 of a scalar law with the upwind ratio chosen by the sign of Roe's
+// speed a = (f(u_{i+1}) - f(u_i)) / (u_{i+1} - u_i) (f'(u_i) if equal):
+// r^- if a > 0, r^+ otherwise (Sec. 3.1).
+double limiter_psi1_roe(const oracle_problem& pb, const double* v, int P) {
+  auto at = [&](int j) { return v[j + P - 1]; };
+  const double u0 = at(0), u1 = at(1);
+  const double dloc = u1 - u0;
+  double f0, f1, fp;
+  if (pb.flux == FLUX_BURGERS) { f0 = 0.5 * (u0 * u0); f1 = 0.5 * (u1 * u1); fp = u0; }
+  else { f0 = pb.ax * u0; f1 = pb.ax * u1; fp = pb.ax; }
+  const double a = dloc != 0.0 ? (f1 - f0) / dloc : fp;
+  const double dupw = a > 0.0 ? u0 - at(-1) : at(2) - u1;
+  if (dloc == 0.0) return dupw == 0.0 ? 1.0 : 0.0;
+  return superbee(dupw / dloc);
+}
+
 // Order selection at one interface: p_s = max{p in 2..P : psi^p >= theta},
 // 1 if the admissible set is empty (Sec. 3, admissible set; Sec. 3.4 min over
 // components).  comp[c] holds component c at offsets -P+1..P (P >= 2 needs
@@ -365,12 +412,17 @@ int select_order(const oracle_problem& pb, const double* const* comp, int G, dou
   int ps = 1;
   for (int p = pb.P; p >= 2; --p) {
     double psi = 1.0;
-    for (int c = 0; c < pb.nvar; ++c) psi = std::min(psi, indicator_psi(comp[c] + (G - pb.P), pb.P, p, pb.eps));
+    for (int c = 0; c < pb.nvar; ++c)
+      psi = std::min(psi, (p == 2 && (pb.flags & FLAG_PSI2_MODIFIED))
+                              ? indicator_psi2_modified(comp[c] + (G - pb.P) + (pb.P - 2), 2, pb.eps)
+                              : indicator_psi(comp[c] + (G - pb.P), pb.P, p, pb.eps));
     if (psi >= pb.theta) { ps = p; break; }
   }
   if (ps == 1) {
     double psi1 = 1e300;
-    for (int c = 0; c < pb.nvar; ++c) psi1 = std::min(psi1, limiter_psi1(comp[c] + (G - 2), 2));
+    for (int c = 0; c < pb.nvar; ++c)
+      psi1 = std::min(psi1, (pb.flags & FLAG_PSI1_ROE) ? limiter_psi1_roe(pb, comp[c] + (G - 2), 2)
+                                                       : limiter_psi1(comp[c] + (G - 2), 2));
     *psi1_out = psi1;
   } else {
     *psi1_out = -1.0;
@@ -432,13 +484,54 @@ void cat_flux_1d(const oracle_problem& pb, int p, const T (*u)[VMAX], double lam
   }
 }
 
-// Rusanov flux along direction d between states uL, uR with speed alpha.
+// Smallest and largest characteristic speed along direction d (Davis
+// estimates for HLL): Euler v -+ c, Burgers u, advection a.
+void wave_speeds(const oracle_problem& pb, const double* u, int d, double* lo, double* hi) {
+  if (pb.flux == FLUX_ADVECTION) { *lo = *hi = d == 0 ? pb.ax : pb.ay; return; }
+  if (pb.flux == FLUX_BURGERS) { *lo = *hi = u[0]; return; }
+  double v, c;
+  if (pb.dim == 1) {
+    const double rho = u[0];
+    v = u[1] / rho;
+    const double p = (pb.gamma - 1.0) * (u[2] - 0.5 * rho * v * v);
+    c = std::sqrt(pb.gamma * p / rho);
+  } else {
+    const double rho = u[0], vx = u[1] / rho, vy = u[2] / rho;
+    const double p = (pb.gamma - 1.0) * (u[3] - 0.5 * rho * (vx * vx + vy * vy));
+    c = std::sqrt(pb.gamma * p / rho);
+    v = d == 0 ? vx : vy;
+  }
+  *lo = v - c;
+  *hi = v + c;
+}
+
+// First-order flux F^lo along direction d between states uL, uR: Rusanov
+// with speed alpha (default), Lax-Friedrichs with dx_d / (dim dt) (so that
+// the unsplit 2D sum is the classical 2D scheme), or HLL with the Davis
+// speeds of the two states (taken at their values: frozen in a tangent).
 template <class T>
-void rusanov(const oracle_problem& pb, int d, const T* uL, const T* uR, double alpha, T* F) {
+void lo_flux(const oracle_problem& pb, int d, const T* uL, const T* uR, double alpha, double dt, T* F) {
   T fL[VMAX], fR[VMAX];
   if (d == 0) { flux_f(pb, uL, fL); flux_f(pb, uR, fR); }
   else { flux_g(pb, uL, fL); flux_g(pb, uR, fR); }
-  for (int c = 0; c < pb.nvar; ++c) F[c] = 0.5 * (fL[c] + fR[c]) - (0.5 * alpha) * (uR[c] - uL[c]);
+  if (pb.flags & FLAG_FLO_HLL) {
+    double uLd[VMAX], uRd[VMAX], l0, h0, l1, h1;
+    for (int c = 0; c < pb.nvar; ++c) { uLd[c] = val(uL[c]); uRd[c] = val(uR[c]); }
+    wave_speeds(pb, uLd, d, &l0, &h0);
+    wave_speeds(pb, uRd, d, &l1, &h1);
+    const double sl = std::min(l0, l1), sr = std::max(h0, h1);
+    for (int c = 0; c < pb.nvar; ++c) {
+      if (sl >= 0.0) { F[c] = fL[c]; continue; }
+      if (sr <= 0.0) { F[c] = fR[c]; continue; }
+      T t = sr * fL[c] - sl * fR[c];
+      t = t + (sl * sr) * (uR[c] - uL[c]);
+      F[c] = t / (sr - sl);
+    }
+    return;
+  }
+  double a = alpha;
+  if (pb.flags & FLAG_FLO_LF) a = (d == 0 ? pb.dx : pb.dy) / (pb.dim * dt);
+  for (int c = 0; c < pb.nvar; ++c) F[c] = 0.5 * (fL[c] + fR[c]) - (0.5 * a) * (uR[c] - uL[c]);
 }
 
 // ---------------------------------------------------------------------------
@@ -450,6 +543,7 @@ struct Step1D {
   const T* u;         // [nvar][nx]
   int64_t nx, nI, ioff;
   int G;
+  double dt = 0.0;     // time step (the Lax-Friedrichs flux uses it)
   Step1D(const oracle_problem& p, const T* u_) : pb(p), u(u_) {
     nx = pb.nx;
     nI = (pb.bc == BC_PERIODIC) ? nx : nx + 1;
@@ -486,7 +580,7 @@ struct Step1D {
       }
       if (decide) al = std::max(spectral_radius(pb, uLd, 0), spectral_radius(pb, uRd, 0));
       T Flo[VMAX];
-      rusanov(pb, 0, uL, uR, al, Flo);
+      lo_flux(pb, 0, uL, uR, al, dt, Flo);
       // FL-CAT2 blend (Sec. 3.1)
       for (int c = 0; c < pb.nvar; ++c) F[c] = ps1 * F[c] + (1.0 - ps1) * Flo[c];
     }
@@ -497,6 +591,7 @@ template <class T>
 int step1d(const oracle_problem& pb, const T* u, T* uout, double dt, int mode, int8_t* ord,
            double* psi1, double* alpha, T* flux_out, int nthreads) {
   Step1D<T> S(pb, u);
+  S.dt = dt;
   const int64_t nx = pb.nx, nI = S.nI;
   const int nv = pb.nvar;
   const double lam = dt / pb.dx;
@@ -622,6 +717,7 @@ struct Step2D {
   const T* u;   // [nvar][ny][nx]
   int64_t nx, ny, nIx, nIy, ioff;
   int G;
+  double dt = 0.0;     // time step (the Lax-Friedrichs flux uses it)
   Step2D(const oracle_problem& p, const T* u_) : pb(p), u(u_) {
     nx = pb.nx; ny = pb.ny;
     bool per = pb.bc == BC_PERIODIC;
@@ -672,12 +768,12 @@ struct Step2D {
     // 2D FL-CAT2 blends (Sec. 4), one per direction with order 1
     if (F && q1 == 1) {
       T Flo[VMAX];
-      rusanov(pb, 0, u0, ux, alx, Flo);
+      lo_flux(pb, 0, u0, ux, alx, dt, Flo);
       for (int c = 0; c < pb.nvar; ++c) F[c] = ps1x * F[c] + (1.0 - ps1x) * Flo[c];
     }
     if (G_ && q2 == 1) {
       T Glo[VMAX];
-      rusanov(pb, 1, u0, uy, aly, Glo);
+      lo_flux(pb, 1, u0, uy, aly, dt, Glo);
       for (int c = 0; c < pb.nvar; ++c) G_[c] = ps1y * G_[c] + (1.0 - ps1y) * Glo[c];
     }
   }
@@ -687,6 +783,7 @@ template <class T>
 int step2d(const oracle_problem& pb, const T* u, T* uout, double dt, int mode, int8_t* ordx, int8_t* ordy,
            double* psix, double* psiy, double* alx, double* aly, T* Fout, T* Gout, int nthreads) {
   Step2D<T> S(pb, u);
+  S.dt = dt;
   const int64_t nx = S.nx, ny = S.ny, nIx = S.nIx, nIy = S.nIy, off = S.ioff;
   const int nv = pb.nvar;
   const double lamx = dt / pb.dx, lamy = dt / pb.dy;
@@ -767,6 +864,9 @@ int check_problem(const oracle_problem* pb) {
   if (pb->flux == FLUX_BURGERS && (pb->nvar != 1 || pb->dim != 1)) return -2;
   if (pb->flux == FLUX_EULER && pb->nvar != (pb->dim == 1 ? 3 : 4)) return -2;
   if (pb->nx < 2 * std::max(pb->P, 2) || (pb->dim == 2 && pb->ny < 2 * std::max(pb->P, 2))) return -2;
+  if (pb->flags & ~(FLAG_FLO_LF | FLAG_FLO_HLL | FLAG_PSI2_MODIFIED | FLAG_PSI1_ROE)) return -2;
+  if ((pb->flags & FLAG_FLO_LF) && (pb->flags & FLAG_FLO_HLL)) return -2;
+  if ((pb->flags & FLAG_PSI1_ROE) && pb->flux == FLUX_EULER) return -2;   // scalar laws only
   return 0;
 }
 
@@ -796,6 +896,8 @@ int oracle_coeffs(int p, double* g1, double* gt, double* eta, double* tau, doubl
 double oracle_indicator(const double* v, int p, double eps) { return indicator_psi(v, p, p, eps); }
 // psi^1 of one component on 4 values (offsets -1..2).
 double oracle_limiter(const double* v) { return limiter_psi1(v, 2); }
+// Modified p = 2 indicator on 4 values (offsets -1..2), for pins.
+double oracle_indicator2_modified(const double* v, double eps) { return indicator_psi2_modified(v, 2, eps); }
 
 // One ACAT step.  mode 0: adaptive (decisions written to ord/psi1/alpha when
 // non-null); mode 1: frozen replay of the given decisions.
@@ -855,6 +957,7 @@ int oracle_update_cells(const oracle_problem* pb, const double* u, double dt, in
   if (nthreads > 0) omp_set_num_threads(nthreads);
   if (pb->dim == 1) {
     Step1D<double> S(*pb, u);
+    S.dt = dt;
     const double lam = dt / pb->dx;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t s = 0; s < ncell; ++s) {
@@ -870,6 +973,7 @@ int oracle_update_cells(const oracle_problem* pb, const double* u, double dt, in
     return 0;
   }
   Step2D<double> S(*pb, u);
+  S.dt = dt;
   const double lamx = dt / pb->dx, lamy = dt / pb->dy;
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t s = 0; s < ncell; ++s) {
