@@ -62,6 +62,19 @@ typedef enum {
 enum { ACAT_FLUX_ADVECTION = 0, ACAT_FLUX_BURGERS = 1, ACAT_FLUX_EULER = 2 };
 enum { ACAT_BC_PERIODIC = 0, ACAT_BC_TRANSMISSIVE = 1 };
 
+/* Variants (acat_problem.flags, bitwise or; 0 = the default method).
+ *   FLO_LF / FLO_HLL: the first-order flux of the FL-CAT2 blend (Sec. 3.1) is
+ *     Lax-Friedrichs (speed dx/(dim dt) per direction, so the 2D sum is the
+ *     classical 2D scheme) or HLL (Davis speed estimates) instead of Rusanov;
+ *     the paper's experiments compare with both (Sec. 5).  Exclusive.
+ *   PSI2_MODIFIED: the modified p = 2 indicator of Sec. 3.2 (two pairs of
+ *     lateral weights), which keeps order 4 at extrema lying at the midpoint
+ *     of a lateral sub-interval.
+ *   PSI1_ROE: scalar laws only; psi^1 from the upwind ratio chosen by the
+ *     sign of Roe's speed (Sec. 3.1) instead of the min form.
+ * The batched step has no variants; acat_step_adjoint rejects FLO_HLL. */
+enum { ACAT_FLAG_FLO_LF = 1, ACAT_FLAG_FLO_HLL = 2, ACAT_FLAG_PSI2_MODIFIED = 4, ACAT_FLAG_PSI1_ROE = 8 };
+
 /* Device status bits (acat_device_status): non-finite output state,
  * non-positive density or pressure (Euler), and (replay) a recorded order
  * outside 1..P, replaced by 1. */
@@ -76,7 +89,7 @@ typedef struct {
   int32_t flux;   /* ACAT_FLUX_*                                                 */
   int32_t P;      /* largest stencil half-width: 1..4 in 1D, 1..3 in 2D          */
   int32_t bc;     /* ACAT_BC_PERIODIC (wrap) or ACAT_BC_TRANSMISSIVE (clamp)     */
-  int32_t flags;  /* reserved, must be 0                                         */
+  int32_t flags;  /* ACAT_FLAG_* variants, 0 for the default method              */
   double gamma;   /* Euler: ratio of specific heats (Sec. 5.3 / 5.5 EOS)         */
   double ax, ay;  /* advection speeds (f = ax u, g = ay u)                       */
   double dx, dy;  /* grid spacings (> 0)                                         */

@@ -391,13 +391,13 @@ double limiter_psi1(const double* v, int P) {
 // psi^1 of a scalar law with the upwind ratio chosen by the sign of Roe's
 // speed a = (f(u_{i+1}) - f(u_i)) / (u_{i+1} - u_i) (f'(u_i) if equal):
 // r^- if a > 0, r^+ otherwise (Sec. 3.1).
-double limiter_psi1_roe(const oracle_problem& pb, const double* v, int P) {
+double limiter_psi1_roe(const oracle_problem& pb, const double* v, int P, int d) {
   auto at = [&](int j) { return v[j + P - 1]; };
   const double u0 = at(0), u1 = at(1);
   const double dloc = u1 - u0;
   double f0, f1, fp;
   if (pb.flux == FLUX_BURGERS) { f0 = 0.5 * (u0 * u0); f1 = 0.5 * (u1 * u1); fp = u0; }
-  else { f0 = pb.ax * u0; f1 = pb.ax * u1; fp = pb.ax; }
+  else { const double a = d == 0 ? pb.ax : pb.ay; f0 = a * u0; f1 = a * u1; fp = a; }
   const double a = dloc != 0.0 ? (f1 - f0) / dloc : fp;
   const double dupw = a > 0.0 ? u0 - at(-1) : at(2) - u1;
   if (dloc == 0.0) return dupw == 0.0 ? 1.0 : 0.0;
@@ -408,7 +408,7 @@ double limiter_psi1_roe(const oracle_problem& pb, const double* v, int P) {
 // 1 if the admissible set is empty (Sec. 3, admissible set; Sec. 3.4 min over
 // components).  comp[c] holds component c at offsets -P+1..P (P >= 2 needs
 // offsets -1..2 as well, which the caller guarantees by using max(P,2)).
-int select_order(const oracle_problem& pb, const double* const* comp, int G, double* psi1_out) {
+int select_order(const oracle_problem& pb, const double* const* comp, int G, double* psi1_out, int d = 0) {
   int ps = 1;
   for (int p = pb.P; p >= 2; --p) {
     double psi = 1.0;
@@ -421,7 +421,7 @@ int select_order(const oracle_problem& pb, const double* const* comp, int G, dou
   if (ps == 1) {
     double psi1 = 1e300;
     for (int c = 0; c < pb.nvar; ++c)
-      psi1 = std::min(psi1, (pb.flags & FLAG_PSI1_ROE) ? limiter_psi1_roe(pb, comp[c] + (G - 2), 2)
+      psi1 = std::min(psi1, (pb.flags & FLAG_PSI1_ROE) ? limiter_psi1_roe(pb, comp[c] + (G - 2), 2, d)
                                                        : limiter_psi1(comp[c] + (G - 2), 2));
     *psi1_out = psi1;
   } else {
@@ -738,7 +738,7 @@ struct Step2D {
         vals[c][j + G - 1] = val(d == 0 ? at(c, i1 + j, i2) : at(c, i1, i2 + j));
       comp[c] = vals[c];
     }
-    int ps = select_order(pb, comp, G, psi1);
+    int ps = select_order(pb, comp, G, psi1, d);
     *alpha = -1.0;
     if (ps == 1) {
       double uL[VMAX], uR[VMAX];

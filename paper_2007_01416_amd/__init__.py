@@ -24,6 +24,10 @@ STATUS = {0: "ok", -1: "null", -2: "arg", -3: "alias", -4: "unsupported", -5: "d
 DEV_NONFINITE, DEV_NONPHYSICAL = 1, 2
 
 
+# variants (Problem.flags), as ACAT_FLAG_* in acat.h
+FLAG_FLO_LF, FLAG_FLO_HLL, FLAG_PSI2_MODIFIED, FLAG_PSI1_ROE = 1, 2, 4, 8
+
+
 class AcatError(RuntimeError):
     def __init__(self, code, what=""):
         self.code = code
@@ -115,11 +119,12 @@ class Problem:
     dy: float = 1.0
     eps: float = 1e-12
     theta: float = 0.5
+    flags: int = 0      # FLAG_* variants (0: the default method)
     _c: _Problem = field(default=None, init=False, repr=False)
 
     def c(self) -> _Problem:
         self._c = _Problem(self.dim, self.nvar, self.nx, self.ny if self.dim == 2 else 1, FLUX[self.flux],
-                           self.P, BC[self.bc], 0, self.gamma, self.ax, self.ay, self.dx, self.dy, self.eps,
+                           self.P, BC[self.bc], self.flags, self.gamma, self.ax, self.ay, self.dx, self.dy, self.eps,
                            self.theta)
         return self._c
 

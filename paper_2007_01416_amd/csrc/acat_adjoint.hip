@@ -212,8 +212,9 @@ __global__ __launch_bounds__(BLOCK) void k_adj1d(KProb pb, KStep st, const doubl
         zero[c] = 0.0;
       }
       flux1d_vjp<FLUX, NV>(pb.ph, u, lb, zero);
+      const double sp = (pb.flags & FLAG_FLO_LF) ? pb.dx / ((double)pb.dim * step_dt(st)) : al;
 #pragma unroll
-      for (int c = 0; c < NV; ++c) ub[c] += zero[c] + (a == 0 ? al : -al) * lb[c];
+      for (int c = 0; c < NV; ++c) ub[c] += zero[c] + (a == 0 ? sp : -sp) * lb[c];
     }
     if (valid) {
 #pragma unroll
@@ -429,7 +430,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
   const int cls = (Q1 - 1) * pb.P + (Q2 - 1);
   const double dt = step_dt(st);
   const double lamx = dt / pb.dx, lamy = dt / pb.dy;
-  const int64_t nx = pb.nx, ny = pb.ny, plane = pb.nx * pb.ny;
+  const int64_t nx = pb.nx, plane = pb.nx * pb.ny;
   const int nx32 = (int)pb.nx, ny32 = (int)pb.ny, ioff = (int)pb.ioff;
   const uint32_t n1u = (uint32_t)pb.n1;
   const int64_t nitems = pb.n1 * pb.n2;
@@ -505,7 +506,12 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
       corner_adjoint<FLUX, NV, Q1, Q2, Q2>(pb.ph, lamx, lamy, u, f0, g0, gx, gy, xs[0], xs[1], STRIDE, buf, slot,
                                            g * L, a1, a2, zero, sgb, ub, f0b, g0b);
     }
-    // Rusanov parts of the FL-CAT2 blends, on the two nodes each one reads
+    // first-order parts (Rusanov or Lax-Friedrichs) of the FL-CAT2 blends, on
+    // the two nodes each one reads
+    if (pb.flags & FLAG_FLO_LF) {
+      alx = pb.dx / ((double)pb.dim * dt);
+      aly = pb.dy / ((double)pb.dim * dt);
+    }
     if (Q1 == 1 && on_row && (a1 == Q1 - 1 || a1 == Q1)) {
 #pragma unroll
       for (int c = 0; c < NV; ++c) {

@@ -18,7 +18,10 @@ inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 acat_status check_problem(const acat_problem* pb) {
   if (!pb) return ACAT_ERR_NULL;
   if (pb->dim != 1 && pb->dim != 2) return ACAT_ERR_ARG;
-  if (pb->flags != 0) return ACAT_ERR_ARG;
+  if (pb->flags & ~(ACAT_FLAG_FLO_LF | ACAT_FLAG_FLO_HLL | ACAT_FLAG_PSI2_MODIFIED | ACAT_FLAG_PSI1_ROE))
+    return ACAT_ERR_ARG;
+  if ((pb->flags & ACAT_FLAG_FLO_LF) && (pb->flags & ACAT_FLAG_FLO_HLL)) return ACAT_ERR_ARG;
+  if ((pb->flags & ACAT_FLAG_PSI1_ROE) && pb->flux == ACAT_FLUX_EULER) return ACAT_ERR_UNSUPPORTED;
   if (pb->bc != ACAT_BC_PERIODIC && pb->bc != ACAT_BC_TRANSMISSIVE) return ACAT_ERR_ARG;
   if (pb->flux < ACAT_FLUX_ADVECTION || pb->flux > ACAT_FLUX_EULER) return ACAT_ERR_ARG;
   if (pb->P < 1 || pb->P > 4) return ACAT_ERR_ARG;
@@ -47,6 +50,7 @@ KProb make_kprob(const acat_problem* p) {
   k.flux = p->flux;
   k.P = p->P;
   k.bc = p->bc;
+  k.flags = p->flags;
   k.nx = p->nx;
   k.ny = p->dim == 2 ? p->ny : 1;
   const int64_t ext = p->bc == ACAT_BC_PERIODIC ? 0 : 1;
@@ -219,6 +223,7 @@ acat_status check_adjoint(const acat_problem* prob) {
   acat_status rc = check_problem(prob);
   if (rc != ACAT_OK) return rc;
   if (prob->dim == 2 && prob->bc != ACAT_BC_PERIODIC) return ACAT_ERR_UNSUPPORTED;
+  if (prob->flags & ACAT_FLAG_FLO_HLL) return ACAT_ERR_UNSUPPORTED;
   return ACAT_OK;
 }
 

@@ -17,6 +17,7 @@ constexpr int MAX_CLASSES = 16;   // order classes: P in 1D, P*P in 2D
 // Problem geometry and parameters as the kernels see them.
 struct KProb {
   int dim, nvar, flux, P, bc;
+  int flags;          // FLAG_* variants
   int64_t nx, ny;
   int64_t nIx, nIy;   // x-interfaces per row, y-interfaces per column
   int64_t ioff;       // interface entry k <-> cell i = k + ioff (0 or -1)

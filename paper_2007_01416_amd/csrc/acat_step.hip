@@ -65,10 +65,13 @@ __global__ __launch_bounds__(BLOCK) void k_classify1d(KProb pb, KStep st) {
         for (int c = 0; c < NV; ++c) uc[c] = v[c][G - 1];
         smax = spectral_radius<FLUX, 1, NV>(pb.ph, uc, 0);
       }
-      ps = Select<NV, G, P>::run(v, pb.eps, pb.theta);
+      ps = Select<NV, G, P>::run(v, pb.eps, pb.theta, (pb.flags & FLAG_PSI2_MODIFIED) != 0);
       double psi1 = -1.0, al = -1.0;
       if (ps == 1) {
         psi1 = limiter<NV, G>(v);
+        if constexpr (NV == 1) {
+          if (pb.flags & FLAG_PSI1_ROE) psi1 = limiter_roe<FLUX, G>(pb.ph, v, 0);
+        }
         double uL[NV], uR[NV];
 #pragma unroll
         for (int c = 0; c < NV; ++c) {
@@ -221,11 +224,12 @@ __global__ __launch_bounds__(BLOCK) void k_flux1d(KProb pb, KStep st) {
             }
             flux1d<FLUX, NV>(pb.ph, uL, fL);
             flux1d<FLUX, NV>(pb.ph, uR, fR);
-            double flo = 0.0, ul = 0.0, ur = 0.0, fl = 0.0, fr = 0.0;
+            double ul = 0.0, ur = 0.0, fl = 0.0, fr = 0.0;
 #pragma unroll
             for (int cc = 0; cc < NV; ++cc)
               if (cc == c) { ul = uL[cc]; ur = uR[cc]; fl = fL[cc]; fr = fR[cc]; }
-            flo = 0.5 * (fl + fr) - (0.5 * al) * (ur - ul);
+            const double alf = pb.dx / ((double)pb.dim * step_dt(st));
+            const double flo = lo_flux<FLUX, 1, NV>(pb.ph, pb.flags, 0, uL, uR, fl, fr, ul, ur, al, alf);
             F = psi * F + (1.0 - psi) * flo;
           }
           st.Fx[c * nI + k] = F;
@@ -293,11 +297,14 @@ __global__ __launch_bounds__(BLOCK) void k_classify2d(KProb pb, KStep st) {
         sx = spectral_radius<FLUX, 2, NV>(pb.ph, uc, 0);
         sy = spectral_radius<FLUX, 2, NV>(pb.ph, uc, 1);
       }
-      q1 = Select<NV, G, P>::run(v, pb.eps, pb.theta);
+      q1 = Select<NV, G, P>::run(v, pb.eps, pb.theta, (pb.flags & FLAG_PSI2_MODIFIED) != 0);
       if (needF) {
         double psi1 = -1.0, al = -1.0;
         if (q1 == 1) {
           psi1 = limiter<NV, G>(v);
+          if constexpr (NV == 1) {
+            if (pb.flags & FLAG_PSI1_ROE) psi1 = limiter_roe<FLUX, G>(pb.ph, v, 0);
+          }
           double uL[NV], uR[NV];
 #pragma unroll
           for (int c = 0; c < NV; ++c) {
@@ -318,11 +325,14 @@ __global__ __launch_bounds__(BLOCK) void k_classify2d(KProb pb, KStep st) {
 #pragma unroll
         for (int c = 0; c < NV; ++c) v[c][a] = st.u[(c * ny + y) * nx + r1];
       }
-      q2 = Select<NV, G, P>::run(v, pb.eps, pb.theta);
+      q2 = Select<NV, G, P>::run(v, pb.eps, pb.theta, (pb.flags & FLAG_PSI2_MODIFIED) != 0);
       if (needG) {
         double psi1 = -1.0, al = -1.0;
         if (q2 == 1) {
           psi1 = limiter<NV, G>(v);
+          if constexpr (NV == 1) {
+            if (pb.flags & FLAG_PSI1_ROE) psi1 = limiter_roe<FLUX, G>(pb.ph, v, 1);
+          }
           double uL[NV], uR[NV];
 #pragma unroll
           for (int c = 0; c < NV; ++c) {
@@ -555,7 +565,8 @@ __global__ __launch_bounds__(BLOCK) void k_flux2d(KProb pb, KStep st) {
               hl = isG ? gL[cc] : fL[cc];
               hr = isG ? gR[cc] : fR[cc];
             }
-          const double lo = 0.5 * (hl + hr) - (0.5 * al) * (ur - ul);
+          const double alf = (isG ? pb.dy : pb.dx) / ((double)pb.dim * dt);
+          const double lo = lo_flux<FLUX, 2, NV>(pb.ph, pb.flags, isG ? 1 : 0, uL, uR, hl, hr, ul, ur, al, alf);
           v = psi * v + (1.0 - psi) * lo;
         }
         if (isG) st.Gy[((int64_t)c * pb.nIy + (i2 - ioff)) * nx + i1] = v;

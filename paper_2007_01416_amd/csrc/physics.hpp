@@ -189,4 +189,55 @@ __device__ __forceinline__ int bc_index32(int i, int n, int bc) {
   return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
+// Variants of the method (acat_problem.flags; ACAT_FLAG_* in acat.h).
+enum { FLAG_FLO_LF = 1, FLAG_FLO_HLL = 2, FLAG_PSI2_MODIFIED = 4, FLAG_PSI1_ROE = 8 };
+
+// Smallest and largest characteristic speed along direction d (the Davis
+// estimates of HLL): Euler v -+ c, Burgers u, advection a.
+template <int FLUX, int DIM, int NV>
+__device__ __forceinline__ void wave_speeds(const Phys& ph, const double (&u)[NV], int d, double& lo, double& hi) {
+  if constexpr (FLUX == ADV) {
+    lo = hi = (d == 0 ? ph.ax : ph.ay);
+  } else if constexpr (FLUX == BURG) {
+    lo = hi = u[0];
+  } else if constexpr (DIM == 1) {
+    const double rho = u[0];
+    const double v = u[1] / rho;
+    const double p = ph.gm1 * (u[2] - 0.5 * rho * v * v);
+    const double c = sqrt(ph.gamma * p / rho);
+    lo = v - c;
+    hi = v + c;
+  } else {
+    const double rho = u[0], vx = u[1] / rho, vy = u[2] / rho;
+    const double p = ph.gm1 * (u[3] - 0.5 * rho * (vx * vx + vy * vy));
+    const double c = sqrt(ph.gamma * p / rho);
+    const double v = d == 0 ? vx : vy;
+    lo = v - c;
+    hi = v + c;
+  }
+}
+
+// One component of the first-order flux F^lo between uL and uR along d:
+// Rusanov with speed alpha (default), Lax-Friedrichs with speed alf
+// (dx_d / (dim dt)), or HLL with the Davis speeds of the two states.
+// fl, fr, ul, ur: component c of f(uL), f(uR), uL, uR.
+template <int FLUX, int DIM, int NV>
+__device__ __forceinline__ double lo_flux(const Phys& ph, int flags, int d, const double (&uL)[NV],
+                                          const double (&uR)[NV], double fl, double fr, double ul, double ur,
+                                          double alpha, double alf) {
+  if (flags & FLAG_FLO_HLL) {
+    double l0, h0, l1, h1;
+    wave_speeds<FLUX, DIM, NV>(ph, uL, d, l0, h0);
+    wave_speeds<FLUX, DIM, NV>(ph, uR, d, l1, h1);
+    const double sl = fmin(l0, l1), sr = fmax(h0, h1);
+    if (sl >= 0.0) return fl;
+    if (sr <= 0.0) return fr;
+    double t = sr * fl - sl * fr;
+    t = t + (sl * sr) * (ur - ul);
+    return t / (sr - sl);
+  }
+  const double a = (flags & FLAG_FLO_LF) ? alf : alpha;
+  return 0.5 * (fl + fr) - (0.5 * a) * (ur - ul);
+}
+
 }  // namespace acat

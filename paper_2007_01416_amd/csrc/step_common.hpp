@@ -16,6 +16,30 @@ constexpr int NXCD = 8;   // MI355X: 8 accelerator complex dies, each with its o
 // ---------------------------------------------------------------- helpers
 __device__ __forceinline__ double superbee(double r) { return fmax(0.0, fmax(fmin(2.0 * r, 1.0), fmin(r, 2.0))); }
 
+// Modified p = 2 indicator of one component (Sec. 3.2): the lateral weights
+// joined with the central sub-interval on either side, the larger ratio.
+template <int G>
+__device__ __forceinline__ double psi2_modified(const double (&v)[2 * G], double eps) {
+  const double dl = v[G - 1] - v[G - 2], dc = v[G] - v[G - 1], dr = v[G + 1] - v[G];
+  double I1L = dl * dl;
+  I1L += eps;
+  double I1R = dc * dc;
+  I1R += dr * dr;
+  I1R += eps;
+  double I2L = dl * dl;
+  I2L += dc * dc;
+  I2L += eps;
+  double I2R = dr * dr;
+  I2R += eps;
+  const double I1 = I1L * I1R / (I1L + I1R), I2 = I2L * I2R / (I2L + I2R);
+  double s = 0.0;
+#pragma unroll
+  for (int j = -1; j <= 2; ++j) s += TB.TAU[2][j + 1] * v[j + G - 1];
+  double tau = TB.FACT2PM1[2] * s;
+  tau = tau * tau;
+  return fmax(I1 / (I1 + tau), I2 / (I2 + tau));
+}
+
 // psi^p of one component; v holds offsets -G+1 .. G (index j + G - 1).
 template <int G, int p>
 __device__ __forceinline__ double psi_comp(const double (&v)[2 * G], double eps) {
@@ -44,18 +68,44 @@ __device__ __forceinline__ double psi_comp(const double (&v)[2 * G], double eps)
 // p_s = max{p in 2..P : min_c psi^{c,p} >= theta}, else 1 (evaluated from P down)
 template <int NV, int G, int p>
 struct Select {
-  __device__ static __forceinline__ int run(const double (&v)[NV][2 * G], double eps, double theta) {
+  __device__ static __forceinline__ int run(const double (&v)[NV][2 * G], double eps, double theta,
+                                            bool mod2 = false) {
     double psi = 1.0;
 #pragma unroll
-    for (int c = 0; c < NV; ++c) psi = fmin(psi, psi_comp<G, p>(v[c], eps));
+    for (int c = 0; c < NV; ++c)
+      psi = fmin(psi, (p == 2 && mod2) ? psi2_modified<G>(v[c], eps) : psi_comp<G, p>(v[c], eps));
     if (psi >= theta) return p;
-    return Select<NV, G, p - 1>::run(v, eps, theta);
+    return Select<NV, G, p - 1>::run(v, eps, theta, mod2);
   }
 };
 template <int NV, int G>
 struct Select<NV, G, 1> {
-  __device__ static __forceinline__ int run(const double (&)[NV][2 * G], double, double) { return 1; }
+  __device__ static __forceinline__ int run(const double (&)[NV][2 * G], double, double, bool = false) { return 1; }
 };
+
+// Scalar law: psi^1 = phi(r) with the upwind ratio chosen by the sign of
+// Roe's speed a = (f(u_{i+1}) - f(u_i)) / (u_{i+1} - u_i) (f'(u_i) if equal):
+// r^- if a > 0, r^+ otherwise (Sec. 3.1).
+template <int FLUX, int G>
+__device__ __forceinline__ double limiter_roe(const Phys& ph, const double (&v)[1][2 * G], int d) {
+  const double u0 = v[0][G - 1], u1 = v[0][G];
+  const double dloc = u1 - u0;
+  double f0, f1, fp;
+  if constexpr (FLUX == BURG) {
+    f0 = 0.5 * (u0 * u0);
+    f1 = 0.5 * (u1 * u1);
+    fp = u0;
+  } else {
+    const double a = d == 0 ? ph.ax : ph.ay;
+    f0 = a * u0;
+    f1 = a * u1;
+    fp = a;
+  }
+  const double a = dloc != 0.0 ? (f1 - f0) / dloc : fp;
+  const double dupw = a > 0.0 ? u0 - v[0][G - 2] : v[0][G + 1] - u1;
+  if (dloc == 0.0) return dupw == 0.0 ? 1.0 : 0.0;
+  return superbee(dupw / dloc);
+}
 
 // psi^1 = min_c min(phi(r+), phi(r-)); a component with u_{i+1} = u_i gives 1
 template <int NV, int G>

@@ -8,14 +8,14 @@ THETA_BAND = 1e-12      # |psi^p - theta| within this: decision may flip
 PSI1_BAND = 1e-12       # |u_{i+1,c} - u_{i,c}| <= band * max|u_c|: superbee may jump
 
 
-def both_problems(dim, nvar, nx, flux, P, bc, dx, ny=1, dy=1.0, gamma=1.4, ax=1.0, ay=1.0):
+def both_problems(dim, nvar, nx, flux, P, bc, dx, ny=1, dy=1.0, gamma=1.4, ax=1.0, ay=1.0, flags=0):
     import paper_2007_01416_amd as acat
     fid = {"advection": oracle.FLUX_ADVECTION, "burgers": oracle.FLUX_BURGERS, "euler": oracle.FLUX_EULER}[flux]
     bid = {"periodic": oracle.BC_PERIODIC, "transmissive": oracle.BC_TRANSMISSIVE}[bc]
     po = oracle.Problem(dim=dim, nvar=nvar, nx=nx, ny=ny, flux=fid, P=P, bc=bid, gamma=gamma, ax=ax, ay=ay,
-                        dx=dx, dy=dy)
+                        dx=dx, dy=dy, flags=flags)
     pg = acat.Problem(dim=dim, nvar=nvar, nx=nx, ny=ny, flux=flux, P=P, bc=bc, gamma=gamma, ax=ax, ay=ay, dx=dx,
-                      dy=dy)
+                      dy=dy, flags=flags)
     return po, pg
 
 

@@ -195,3 +195,18 @@ def test_step_cfl_argument_errors_before_launch(lib):
     assert f(ctypes.byref(pc), a, b, 0.0, 1.0, None, b, ws, 16, None, None) == -2      # cfl > 0
     assert f(ctypes.byref(pc), a, a, 0.5, 1.0, None, b, ws, 16, None, None) == -3      # aliasing
     assert f(ctypes.byref(pc), a, b, 0.5, 1.0, None, b, ws, 16, None, None) == -6      # workspace
+
+
+@pytest.mark.parametrize("flags,code,adj", [
+    (1, 0, 0), (2, 0, -4), (4, 0, 0), (1 | 4, 0, 0), (1 | 2, -2, -2), (16, -2, -2), (8, -4, -4),
+])
+def test_flags_validation(lib, flags, code, adj):
+    """Variants: Lax-Friedrichs and HLL exclusive, Roe-speed limiter for
+    scalar laws only (Euler here), unknown bits rejected; no HLL adjoint."""
+    n = ctypes.c_size_t(0)
+    pc = _prob(flags=flags).c()
+    assert lib.acat_workspace_size(ctypes.byref(pc), ctypes.byref(n)) == code
+    assert lib.acat_adjoint_workspace_size(ctypes.byref(pc), ctypes.byref(n)) == adj
+    # the Roe-speed limiter is accepted for a scalar law
+    pb = _prob(flux="burgers", nvar=1, flags=8).c()
+    assert lib.acat_workspace_size(ctypes.byref(pb), ctypes.byref(n)) == 0

@@ -1,0 +1,91 @@
+"""GPU parity of the variants (acat_problem.flags) against the oracle:
+Lax-Friedrichs or HLL as the first-order flux, the modified p = 2
+indicator, the Roe-speed limiter ratio for scalar laws.  Lockstep, bit for
+bit, on shocked data where the fallback and all orders occur; the adjoint
+with Lax-Friedrichs against the dense oracle adjoint."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from gpu_helpers import both_problems, from_workload
+from test_gpu_parity import lockstep
+
+pytestmark = pytest.mark.gpu
+
+LF, HLL, PSI2M, ROE = 1, 2, 4, 8
+
+
+@pytest.mark.parametrize("flags", [LF, HLL, PSI2M, PSI2M | LF, PSI2M | HLL])
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+def test_variants_lockstep_euler1d(acat, flags, bc):
+    w = workloads.euler_1d(n=600, P=4)
+    po, pg = from_workload(w, bc=bc, flags=flags)
+    lockstep(acat, po, pg, w["u"], 0.5, 12, label=f"euler1d flags={flags} {bc}")
+
+
+@pytest.mark.parametrize("flags", [ROE, ROE | PSI2M, ROE | HLL])
+def test_variants_lockstep_burgers(acat, flags):
+    w = workloads.burgers_1d(n=300)
+    po, pg = from_workload(w, P=3, flags=flags)
+    lockstep(acat, po, pg, w["u"], 0.5, 20, label=f"burgers flags={flags}")
+
+
+@pytest.mark.parametrize("name", ["einfeldt123", "blast_right"])
+@pytest.mark.parametrize("flags", [LF, HLL])
+def test_variants_shock_tubes_lockstep(acat, name, flags):
+    w = workloads.paper_riemann_1d(name, P=3)
+    po, pg = from_workload(w, flags=flags)
+    lockstep(acat, po, pg, w["u"], w["cfl"], 15, label=f"{name} flags={flags}")
+
+
+@pytest.mark.parametrize("flags", [LF, HLL, PSI2M])
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+def test_variants_lockstep_euler2d(acat, flags, bc):
+    w = workloads.euler_2d(n=64, P=3)
+    po, pg = from_workload(w, bc=bc, flags=flags)
+    lockstep(acat, po, pg, w["u"], 0.4, 4, label=f"euler2d flags={flags} {bc}")
+
+
+def test_variants_lockstep_advection2d_roe(acat):
+    rng = np.random.default_rng(9)
+    n = 40
+    u = np.where(rng.uniform(size=(1, n, n)) > 0.5, 1.0, 0.0) + 0.1 * rng.standard_normal((1, n, n))
+    po, pg = both_problems(2, 1, n, "advection", 3, "periodic", 0.1, ny=n, dy=0.1, ax=0.7, ay=-0.4,
+                           flags=ROE | HLL)
+    lockstep(acat, po, pg, u, 0.4, 5, label="advection2d roe+hll")
+
+
+def _dense(acat, po, pg, u, dt):
+    r = oracle.step1d(po, u, dt) if po.dim == 1 else oracle.step2d(po, u, dt)
+    maps = oracle.maps_of(po, r)
+    ub = np.random.default_rng(3).standard_normal(u.shape)
+    want = oracle.vjp_dense(po, u, ub, dt, maps)
+    dec = acat.Decisions(pg)
+    names = ("order", "psi1", "alpha") if po.dim == 1 else ("ordx", "psix", "alx", "ordy", "psiy", "aly")
+    dst = (dec.order_x, dec.psi1_x, dec.alpha_x) if po.dim == 1 else \
+        (dec.order_x, dec.psi1_x, dec.alpha_x, dec.order_y, dec.psi1_y, dec.alpha_y)
+    for nm, t in zip(names, dst):
+        t.copy_(torch.from_numpy(np.ascontiguousarray(r[nm])))
+    got = acat.step_adjoint(pg, torch.from_numpy(np.ascontiguousarray(u)).cuda(), dt, dec,
+                            torch.from_numpy(ub).cuda()).cpu().numpy()
+    return got, want
+
+
+def test_adjoint_with_lax_friedrichs_1d(acat):
+    w = workloads.euler_1d(n=32, P=3)
+    po, pg = from_workload(w, bc="transmissive", flags=LF | PSI2M)
+    dt = oracle.dt_cfl(po, w["u"], 0.5)
+    got, want = _dense(acat, po, pg, w["u"], dt)
+    assert np.abs(got - want).max() <= 1e-11 * np.abs(want).max()
+
+
+def test_adjoint_with_lax_friedrichs_2d(acat):
+    from test_gpu_adjoint import smooth_2d
+    n = 20
+    u = smooth_2d(n)
+    po, pg = both_problems(2, 4, n, "euler", 2, "periodic", 1.0 / n, ny=n, dy=1.0 / n, flags=LF)
+    dt = oracle.dt_cfl(po, u, 0.4)
+    got, want = _dense(acat, po, pg, u, dt)
+    assert np.abs(got - want).max() <= 1e-11 * np.abs(want).max()
