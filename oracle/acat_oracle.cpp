@@ -117,8 +117,8 @@ void lagrange_weights(int nn, const int* x, Rat q, int k, Rat* w) {
   }
 }
 
-const int PMAX = 4;   // largest stencil half-width supported
-const int NMAX = 8;   // 2 * PMAX nodes
+const int PMAX = 6;   // largest stencil half-width supported (1D; 4 in 2D)
+const int NMAX = 12;  // 2 * PMAX nodes
 const int VMAX = 4;   // largest number of conserved variables
 
 struct Tables {
@@ -859,7 +859,7 @@ int step2d(const oracle_problem& pb, const T* u, T* uout, double dt, int mode, i
 int check_problem(const oracle_problem* pb) {
   if (!pb) return -1;
   if (pb->dim != 1 && pb->dim != 2) return -2;
-  if (pb->P < 1 || pb->P > PMAX) return -2;
+  if (pb->P < 1 || pb->P > PMAX || (pb->dim == 2 && pb->P > 4)) return -2;
   if (pb->nvar < 1 || pb->nvar > VMAX) return -2;
   if (pb->flux == FLUX_BURGERS && (pb->nvar != 1 || pb->dim != 1)) return -2;
   if (pb->flux == FLUX_EULER && pb->nvar != (pb->dim == 1 ? 3 : 4)) return -2;

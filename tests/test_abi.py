@@ -41,7 +41,7 @@ def test_status_strings(lib):
         assert lib.acat_status_string(code)
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
 def test_kernel_tables_equal_oracle_tables(p):
     import paper_2007_01416_amd as acat
     a = acat.coefficients(p)

@@ -11,7 +11,7 @@ import oracle
 from oracle import rational as R
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
 def test_tables_match_independent_rational_derivation(p):
     # C++ tables: expanded Lagrange basis; rational.py: moment-condition solve.
     c = oracle.coeffs(p)
@@ -26,19 +26,19 @@ def test_tables_match_independent_rational_derivation(p):
     assert np.array_equal(eta, c["eta"])
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
 def test_moment_identities(p):
     # sum_j gamma^{k,q}_j (j - q)^m = k! delta_{mk} for m < 2p (exactness on polynomials)
     c = oracle.coeffs(p)
     J = np.arange(-p + 1, p + 1, dtype=float)
     for a, q in enumerate(J):
         for m in range(2 * p):
-            s = np.sum(c["g1"][a] * (J - q) ** m)
-            assert abs(s - (1.0 if m == 1 else 0.0)) < 1e-11
+            terms = c["g1"][a] * (J - q) ** m
+            assert abs(terms.sum() - (1.0 if m == 1 else 0.0)) < 1e-14 * max(1.0, np.abs(terms).sum())
     for k in range(2 * p):
         for m in range(2 * p):
-            s = np.sum(c["gt"][k] * J ** m)
-            assert abs(s - (factorial(k) if m == k else 0.0)) < 1e-9 * factorial(k)
+            terms = c["gt"][k] * J ** m
+            assert abs(terms.sum() - (factorial(k) if m == k else 0.0)) < 1e-14 * max(1.0, np.abs(terms).sum())
 
 
 def test_textbook_tables():
@@ -56,7 +56,7 @@ def test_textbook_tables():
     assert np.array_equal(oracle.coeffs(4)["tau"], [-1, 7, -21, 35, -35, 21, -7, 1])
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
 def test_eta_telescopes_to_centred_derivative(p):
     # A_i - A_{i-1} with weights eta reproduces the centred (2p+1)-point D^1
     c = oracle.coeffs(p)
