@@ -87,7 +87,7 @@ typedef struct {
   int64_t nx;     /* cells in x, >= 2 max(P, 2)                                  */
   int64_t ny;     /* cells in y (2D), >= 2 max(P, 2); ignored in 1D              */
   int32_t flux;   /* ACAT_FLUX_*                                                 */
-  int32_t P;      /* largest stencil half-width: 1..4 in 1D, 1..3 in 2D          */
+  int32_t P;      /* largest stencil half-width: 1..6 in 1D, 1..4 in 2D          */
   int32_t bc;     /* ACAT_BC_PERIODIC (wrap) or ACAT_BC_TRANSMISSIVE (clamp)     */
   int32_t flags;  /* ACAT_FLAG_* variants, 0 for the default method              */
   double gamma;   /* Euler: ratio of specific heats (Sec. 5.3 / 5.5 EOS)         */
@@ -154,8 +154,8 @@ acat_status acat_step_replay(const acat_problem* prob, const double* u_in, doubl
  *     the forward step's input state; dt / dt_dev as in acat_step.
  *   - ubar_out, ubar_in: state-shaped adjoints; ubar_in may equal ubar_out
  *     (in place) but may not partially overlap it or overlap u_in.
- *   - 1D: every flux and boundary; 2D: periodic only (else
- *     ACAT_ERR_UNSUPPORTED).  Recorded orders outside 1..P are taken as 1
+ *   - 1D: every flux and boundary, P <= 4; 2D: periodic only, P <= 3
+ *     (else ACAT_ERR_UNSUPPORTED).  Recorded orders outside 1..P are taken as 1
  *     and set ACAT_DEV_BAD_ORDER.
  * --------------------------------------------------------------------- */
 acat_status acat_adjoint_workspace_size(const acat_problem* prob, size_t* bytes /* host */);
@@ -231,7 +231,7 @@ acat_status acat_profile_enable(int32_t on);
 acat_status acat_profile_read(int32_t max_kernels, char* names /* host [max][64] */, double* total_ms,
                               int64_t* launches, int32_t* n_kernels);
 
-/* Coefficient tables the kernels use for half-width p (host arrays, row
+/* Coefficient tables the kernels use for half-width p = 1..6 (host arrays, row
  * major): g1[2p][2p] first derivatives at the nodes, gt[2p][2p] k-th time
  * derivatives at 0 (k = 0..2p-1), eta[2p] interface weights, tau[2p] the
  * (2p-1)-th derivative weights.  For inspection and tests. */

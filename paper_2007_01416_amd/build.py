@@ -23,7 +23,10 @@ SOURCES = ["acat_step.hip", "acat_batched.hip", "acat_adjoint.hip", "acat_api.hi
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -ffp-contract=off: no implicit fused multiply-add; the kernels write every
 # fma they use explicitly, so the rounding of each operation is fixed.
+# -fconstexpr-steps: the coefficient tables (exact rationals up to 12 nodes)
+# are evaluated at compile time.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=off",
+         "-fconstexpr-steps=400000000",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

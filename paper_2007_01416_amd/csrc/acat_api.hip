@@ -24,7 +24,7 @@ acat_status check_problem(const acat_problem* pb) {
   if ((pb->flags & ACAT_FLAG_PSI1_ROE) && pb->flux == ACAT_FLUX_EULER) return ACAT_ERR_UNSUPPORTED;
   if (pb->bc != ACAT_BC_PERIODIC && pb->bc != ACAT_BC_TRANSMISSIVE) return ACAT_ERR_ARG;
   if (pb->flux < ACAT_FLUX_ADVECTION || pb->flux > ACAT_FLUX_EULER) return ACAT_ERR_ARG;
-  if (pb->P < 1 || pb->P > 4) return ACAT_ERR_ARG;
+  if (pb->P < 1 || pb->P > PMAX) return ACAT_ERR_ARG;
   const int64_t G = pb->P > 2 ? pb->P : 2;
   if (pb->nx < 2 * G || pb->nx > (int64_t)1 << 31) return ACAT_ERR_ARG;
   if (pb->dim == 2 && (pb->ny < 2 * G || pb->ny > (int64_t)1 << 31)) return ACAT_ERR_ARG;
@@ -36,7 +36,7 @@ acat_status check_problem(const acat_problem* pb) {
   if (pb->flux == ACAT_FLUX_ADVECTION && pb->nvar < 1) return ACAT_ERR_ARG;
   // valid problems without kernels
   if (pb->flux == ACAT_FLUX_ADVECTION && pb->nvar != 1) return ACAT_ERR_UNSUPPORTED;
-  if (pb->dim == 2 && pb->P > 3) return ACAT_ERR_UNSUPPORTED;
+  if (pb->dim == 2 && pb->P > PMAX_2D) return ACAT_ERR_UNSUPPORTED;
   const int64_t cells = pb->nx * (pb->dim == 2 ? pb->ny : 1);
   const int64_t items = (pb->dim == 2) ? (pb->nx + 1) * (pb->ny + 1) : pb->nx + 1;
   if (cells * pb->nvar >= ((int64_t)1 << 40) || items >= ((int64_t)1 << 31) - 1) return ACAT_ERR_UNSUPPORTED;
@@ -224,6 +224,7 @@ acat_status check_adjoint(const acat_problem* prob) {
   if (rc != ACAT_OK) return rc;
   if (prob->dim == 2 && prob->bc != ACAT_BC_PERIODIC) return ACAT_ERR_UNSUPPORTED;
   if (prob->flags & ACAT_FLAG_FLO_HLL) return ACAT_ERR_UNSUPPORTED;
+  if (prob->P > (prob->dim == 1 ? 4 : 3)) return ACAT_ERR_UNSUPPORTED;   // adjoint kernels up to P = 4 (1D), 3 (2D)
   return ACAT_OK;
 }
 
@@ -237,7 +238,7 @@ acat_status check_batch(const acat_batch* bt) {
   if (bt->flux != ACAT_FLUX_EULER && bt->nvar != 1) return bt->nvar < 1 ? ACAT_ERR_ARG : ACAT_ERR_UNSUPPORTED;
   if (!(bt->eps >= 0.0) || !(bt->theta > 0.0 && bt->theta <= 1.0)) return ACAT_ERR_ARG;
   if (bt->launch) {
-    for (int p = 0; p < PMAX; ++p) {
+    for (int p = 0; p < BATCH_PMAX; ++p) {
       const int w = bt->launch[2 * p], c = bt->launch[2 * p + 1];
       if (!(w == 0 || w == 1 || w == 2 || w == 4) || c < 0 || c > 32) return ACAT_ERR_ARG;
     }
@@ -313,7 +314,7 @@ KBatch make_kbatch(const acat_batch* bt, const BLayout& L, char* w) {
   k.P = reinterpret_cast<const int32_t*>(w + L.P);
   k.bc = reinterpret_cast<const int32_t*>(w + L.bc);
   k.dx = reinterpret_cast<const double*>(w + L.dx);
-  for (int p = 1; p <= PMAX; ++p) {
+  for (int p = 1; p <= BATCH_PMAX; ++p) {
     k.waves[p] = bt->launch && bt->launch[2 * (p - 1)] > 0 ? bt->launch[2 * (p - 1)] : 4;
     k.per_cu[p] = bt->launch ? bt->launch[2 * (p - 1) + 1] : 0;
   }
@@ -531,7 +532,7 @@ const char* acat_status_string(acat_status s) {
 }
 
 acat_status acat_coefficients(int32_t p, double* g1, double* gt, double* eta, double* tau) {
-  if (p < 1 || p > 4) return ACAT_ERR_ARG;
+  if (p < 1 || p > PMAX) return ACAT_ERR_ARG;
   copy_tables(p, g1, gt, eta, tau);
   return ACAT_OK;
 }

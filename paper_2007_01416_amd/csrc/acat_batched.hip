@@ -30,7 +30,7 @@ __device__ __forceinline__ int find_seg(const int64_t* off, int n, int64_t x) {
   return a;
 }
 
-constexpr int GW = PMAX;   // indicator window half-width for every problem (offsets -3 .. 4)
+constexpr int GW = BATCH_PMAX;   // indicator window half-width for every problem (offsets -3 .. 4)
 
 template <int FLUX, int NV>
 __global__ __launch_bounds__(BLOCK) void k_classify_b(KBatch bt, KBStep st) {
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(BLOCK) void k_classify_b(KBatch bt, KBStep st) {
 #pragma unroll
       for (int c = 0; c < NV; ++c) v[c][a] = ub[c * bt.ncell + node];
     }
-    ps = SelectRT<NV, GW, PMAX>::run(v, bt.P[b], bt.eps, bt.theta);
+    ps = SelectRT<NV, GW, BATCH_PMAX>::run(v, bt.P[b], bt.eps, bt.theta);
     double psi1 = -1.0, al = -1.0;
     if (ps == 1) {
       psi1 = limiter<NV, GW>(v);
@@ -292,7 +292,7 @@ hipError_t step_b_impl(const KBatch& bt, const KBStep& st, hipStream_t s) {
   ACAT_CHECK_LAUNCH();
   k_scan_hist<<<bt.Pmax, SCAN_T, 0, s>>>(st.hist, cblocks, st.offs, st.counts, bt.Pmax, CflReduce{});
   ACAT_CHECK_LAUNCH();
-  k_scatter<PMAX><<<cblocks, BLOCK, 0, s>>>(st.ord, 1, bt.nif, cblocks, st.offs, st.counts, st.list);
+  k_scatter<BATCH_PMAX><<<cblocks, BLOCK, 0, s>>>(st.ord, 1, bt.nif, cblocks, st.offs, st.counts, st.list);
   ACAT_CHECK_LAUNCH();
   hipError_t e;
   if ((e = launch_flux_b<FLUX, NV, 1>(bt, st, s)) != hipSuccess) return e;

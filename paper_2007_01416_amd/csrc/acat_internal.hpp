@@ -13,6 +13,7 @@ namespace acat {
 
 constexpr int BLOCK = 256;        // threads per block of every step kernel
 constexpr int MAX_CLASSES = 16;   // order classes: P in 1D, P*P in 2D
+constexpr int BATCH_PMAX = 4;     // largest half-width of a batched problem
 
 // Problem geometry and parameters as the kernels see them.
 struct KProb {
@@ -93,8 +94,8 @@ struct KBatch {
   const int32_t* P;         // [nprob] largest half-width
   const int32_t* bc;        // [nprob] boundary
   const double* dx;         // [nprob]
-  int waves[PMAX + 1];      // per order class p: waves per block of the flux kernel (1, 2 or 4)
-  int per_cu[PMAX + 1];     // per order class p: persistent blocks per CU (0: occupancy limit)
+  int waves[BATCH_PMAX + 1];    // per order class p: waves per block of the flux kernel (1, 2 or 4)
+  int per_cu[BATCH_PMAX + 1];   // per order class p: persistent blocks per CU (0: occupancy limit)
 };
 
 struct KBStep {

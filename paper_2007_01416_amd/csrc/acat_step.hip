@@ -669,7 +669,8 @@ CflReduce cfl_reduce(const KProb& pb, const KStep& st, int nparts) {
 template <int FLUX, int NV, int P, int p>
 hipError_t launch_class1d(const KProb& pb, const KStep& st, int cap, hipStream_t s) {
   if constexpr (p <= P) {
-    static const char* names[5] = {"", "flux1d_p1", "flux1d_p2", "flux1d_p3", "flux1d_p4"};
+    static const char* names[7] = {"", "flux1d_p1", "flux1d_p2", "flux1d_p3", "flux1d_p4", "flux1d_p5",
+                                   "flux1d_p6"};
     auto kern = k_flux1d<FLUX, NV, p>;
     const int grid = persistent_grid(kern, pb.nIx, cap);
     {
@@ -710,6 +711,8 @@ hipError_t step1d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s)
   if ((e = launch_class1d<FLUX, NV, P, 2>(pb, st, cap, s)) != hipSuccess) return e;
   if ((e = launch_class1d<FLUX, NV, P, 3>(pb, st, cap, s)) != hipSuccess) return e;
   if ((e = launch_class1d<FLUX, NV, P, 4>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class1d<FLUX, NV, P, 5>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class1d<FLUX, NV, P, 6>(pb, st, cap, s)) != hipSuccess) return e;
   {
     ProfScope ps("update1d", s);
     k_update1d<FLUX, NV><<<(unsigned)((pb.nx + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st);
@@ -721,10 +724,11 @@ hipError_t step1d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s)
 template <int FLUX, int NV, int P, int Q1, int Q2>
 hipError_t launch_class2d(const KProb& pb, const KStep& st, int cap, hipStream_t s) {
   if constexpr (Q1 <= P && Q2 <= P) {
-    static const char* names[4][4] = {{"", "", "", ""},
-                                      {"", "flux2d_q11", "flux2d_q12", "flux2d_q13"},
-                                      {"", "flux2d_q21", "flux2d_q22", "flux2d_q23"},
-                                      {"", "flux2d_q31", "flux2d_q32", "flux2d_q33"}};
+    static const char* names[5][5] = {{"", "", "", "", ""},
+                                      {"", "flux2d_q11", "flux2d_q12", "flux2d_q13", "flux2d_q14"},
+                                      {"", "flux2d_q21", "flux2d_q22", "flux2d_q23", "flux2d_q24"},
+                                      {"", "flux2d_q31", "flux2d_q32", "flux2d_q33", "flux2d_q34"},
+                                      {"", "flux2d_q41", "flux2d_q42", "flux2d_q43", "flux2d_q44"}};
     auto kern = k_flux2d<FLUX, NV, Q1, Q2>;
     const int grid = persistent_grid(kern, pb.n1 * pb.n2, cap);
     {
@@ -768,6 +772,13 @@ hipError_t step2d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s)
   if ((e = launch_class2d<FLUX, NV, P, 2, 3>(pb, st, cap, s)) != hipSuccess) return e;
   if ((e = launch_class2d<FLUX, NV, P, 3, 2>(pb, st, cap, s)) != hipSuccess) return e;
   if ((e = launch_class2d<FLUX, NV, P, 3, 3>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 1, 4>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 4, 1>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 2, 4>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 4, 2>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 3, 4>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 4, 3>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 4, 4>(pb, st, cap, s)) != hipSuccess) return e;
   {
     ProfScope ps("update2d", s);
     k_update2d<FLUX, NV><<<(unsigned)((pb.nx * pb.ny + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st);
@@ -786,6 +797,8 @@ hipError_t launch_step_1d(const KProb& pb, const KStep& st, int grid_blocks, hip
       case 2: return step1d_impl<EUL, 3, 2>(pb, st, cap, s);
       case 3: return step1d_impl<EUL, 3, 3>(pb, st, cap, s);
       case 4: return step1d_impl<EUL, 3, 4>(pb, st, cap, s);
+      case 5: return step1d_impl<EUL, 3, 5>(pb, st, cap, s);
+      case 6: return step1d_impl<EUL, 3, 6>(pb, st, cap, s);
     }
   } else if (pb.flux == BURG) {
     switch (pb.P) {
@@ -793,6 +806,8 @@ hipError_t launch_step_1d(const KProb& pb, const KStep& st, int grid_blocks, hip
       case 2: return step1d_impl<BURG, 1, 2>(pb, st, cap, s);
       case 3: return step1d_impl<BURG, 1, 3>(pb, st, cap, s);
       case 4: return step1d_impl<BURG, 1, 4>(pb, st, cap, s);
+      case 5: return step1d_impl<BURG, 1, 5>(pb, st, cap, s);
+      case 6: return step1d_impl<BURG, 1, 6>(pb, st, cap, s);
     }
   } else {
     switch (pb.P) {
@@ -800,6 +815,8 @@ hipError_t launch_step_1d(const KProb& pb, const KStep& st, int grid_blocks, hip
       case 2: return step1d_impl<ADV, 1, 2>(pb, st, cap, s);
       case 3: return step1d_impl<ADV, 1, 3>(pb, st, cap, s);
       case 4: return step1d_impl<ADV, 1, 4>(pb, st, cap, s);
+      case 5: return step1d_impl<ADV, 1, 5>(pb, st, cap, s);
+      case 6: return step1d_impl<ADV, 1, 6>(pb, st, cap, s);
     }
   }
   return hipErrorInvalidValue;
@@ -812,12 +829,14 @@ hipError_t launch_step_2d(const KProb& pb, const KStep& st, int grid_blocks, hip
       case 1: return step2d_impl<EUL, 4, 1>(pb, st, cap, s);
       case 2: return step2d_impl<EUL, 4, 2>(pb, st, cap, s);
       case 3: return step2d_impl<EUL, 4, 3>(pb, st, cap, s);
+      case 4: return step2d_impl<EUL, 4, 4>(pb, st, cap, s);
     }
   } else if (pb.flux == ADV) {
     switch (pb.P) {
       case 1: return step2d_impl<ADV, 1, 1>(pb, st, cap, s);
       case 2: return step2d_impl<ADV, 1, 2>(pb, st, cap, s);
       case 3: return step2d_impl<ADV, 1, 3>(pb, st, cap, s);
+      case 4: return step2d_impl<ADV, 1, 4>(pb, st, cap, s);
     }
   }
   return hipErrorInvalidValue;
@@ -831,6 +850,8 @@ hipError_t launch_lists(const KProb& pb, const KStep& st, hipStream_t s) {
         case 2: return lists1d_impl<EUL, 3, 2>(pb, st, s);
         case 3: return lists1d_impl<EUL, 3, 3>(pb, st, s);
         case 4: return lists1d_impl<EUL, 3, 4>(pb, st, s);
+        case 5: return lists1d_impl<EUL, 3, 5>(pb, st, s);
+        case 6: return lists1d_impl<EUL, 3, 6>(pb, st, s);
       }
     } else if (pb.flux == BURG) {
       switch (pb.P) {
@@ -838,6 +859,8 @@ hipError_t launch_lists(const KProb& pb, const KStep& st, hipStream_t s) {
         case 2: return lists1d_impl<BURG, 1, 2>(pb, st, s);
         case 3: return lists1d_impl<BURG, 1, 3>(pb, st, s);
         case 4: return lists1d_impl<BURG, 1, 4>(pb, st, s);
+        case 5: return lists1d_impl<BURG, 1, 5>(pb, st, s);
+        case 6: return lists1d_impl<BURG, 1, 6>(pb, st, s);
       }
     } else {
       switch (pb.P) {
@@ -845,6 +868,8 @@ hipError_t launch_lists(const KProb& pb, const KStep& st, hipStream_t s) {
         case 2: return lists1d_impl<ADV, 1, 2>(pb, st, s);
         case 3: return lists1d_impl<ADV, 1, 3>(pb, st, s);
         case 4: return lists1d_impl<ADV, 1, 4>(pb, st, s);
+        case 5: return lists1d_impl<ADV, 1, 5>(pb, st, s);
+        case 6: return lists1d_impl<ADV, 1, 6>(pb, st, s);
       }
     }
   } else if (pb.flux == EUL) {
@@ -852,12 +877,14 @@ hipError_t launch_lists(const KProb& pb, const KStep& st, hipStream_t s) {
       case 1: return lists2d_impl<EUL, 4, 1>(pb, st, s);
       case 2: return lists2d_impl<EUL, 4, 2>(pb, st, s);
       case 3: return lists2d_impl<EUL, 4, 3>(pb, st, s);
+      case 4: return lists2d_impl<EUL, 4, 4>(pb, st, s);
     }
   } else if (pb.flux == ADV) {
     switch (pb.P) {
       case 1: return lists2d_impl<ADV, 1, 1>(pb, st, s);
       case 2: return lists2d_impl<ADV, 1, 2>(pb, st, s);
       case 3: return lists2d_impl<ADV, 1, 3>(pb, st, s);
+      case 4: return lists2d_impl<ADV, 1, 4>(pb, st, s);
     }
   }
   return hipErrorInvalidValue;

@@ -22,7 +22,8 @@
 
 namespace acat {
 
-constexpr int PMAX = 4;
+constexpr int PMAX = 6;     // largest stencil half-width (1D; 2D stops at 4)
+constexpr int PMAX_2D = 4;
 constexpr int NMAX = 2 * PMAX;
 
 namespace detail {
@@ -55,9 +56,14 @@ constexpr Frac add(Frac a, Frac b) { return mk(a.n * b.d + b.n * a.d, a.d * b.d)
 constexpr Frac sub(Frac a, Frac b) { return mk(a.n * b.d - b.n * a.d, a.d * b.d); }
 constexpr Frac mul(Frac a, Frac b) { return mk(a.n * b.n, a.d * b.d); }
 constexpr Frac dvd(Frac a, Frac b) { return mk(a.n * b.d, a.d * b.n); }
-// numerator and denominator stay below 2^53 for every table here, so one
-// IEEE division rounds the exact value correctly
-constexpr double to_f64(Frac a) { return (double)(int64_t)a.n / (double)(int64_t)a.d; }
+// numerator and denominator stay below 2^53 for every table here (checked:
+// a larger one stops the constant evaluation), so one IEEE division rounds
+// the exact value correctly
+constexpr __int128 TWO53 = (__int128)1 << 53;
+constexpr double exact_or_fail(double v, bool ok) { return ok ? v : throw "table entry not exact"; }
+constexpr double to_f64(Frac a) {
+  return exact_or_fail((double)(int64_t)a.n / (double)(int64_t)a.d, iabs(a.n) < TWO53 && a.d < TWO53);
+}
 
 // Fornberg's recursion: weights w[k][j] of the k-th derivative (k <= m) at
 // z from the values at nodes x[0..n-1].

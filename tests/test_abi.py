@@ -58,10 +58,10 @@ def _prob(**kw):
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(dim=3), -2), (dict(P=0), -2), (dict(P=5), -2), (dict(nvar=2), -2), (dict(dx=0.0), -2),
+    (dict(dim=3), -2), (dict(P=0), -2), (dict(P=7), -2), (dict(nvar=2), -2), (dict(dx=0.0), -2),
     (dict(nx=3), -2), (dict(theta=0.0), -2), (dict(theta=1.5), -2), (dict(eps=-1.0), -2),
     (dict(flux="burgers", nvar=1, dim=2, ny=16, dy=0.1), -2),
-    (dict(flux="advection", nvar=2), -4), (dict(dim=2, nvar=4, ny=64, dy=0.1, P=4), -4),
+    (dict(flux="advection", nvar=2), -4), (dict(dim=2, nvar=4, ny=64, dy=0.1, P=5), -4),
     (dict(gamma=1.0), -2),
 ])
 def test_workspace_size_rejects_invalid_problems(lib, kw, code):
@@ -158,7 +158,8 @@ def test_adjoint_argument_errors_before_launch(lib):
     # 2D transmissive has no adjoint kernel
     p2 = _prob(dim=2, nvar=4, ny=32, dy=0.1, bc="transmissive")
     assert lib.acat_adjoint_workspace_size(ctypes.byref(p2.c()), ctypes.byref(n)) == -4
-    assert lib.acat_adjoint_workspace_size(ctypes.byref(_prob(P=5).c()), ctypes.byref(n)) == -2
+    assert lib.acat_adjoint_workspace_size(ctypes.byref(_prob(P=7).c()), ctypes.byref(n)) == -2
+    assert lib.acat_adjoint_workspace_size(ctypes.byref(_prob(P=5).c()), ctypes.byref(n)) == -4
     ub = (ctypes.c_double * (3 * 64))()
     ub2 = (ctypes.c_double * (3 * 64))()
     u = (ctypes.c_double * (3 * 64))()
