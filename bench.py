@@ -295,6 +295,73 @@ def bench_paper(acat, workloads):
     return out
 
 
+def _class_profile(acat, s, nclass, steps, warmup):
+    """Steps a Solver under the kernel profiler; returns (seconds, per-class
+    item totals, kernel table)."""
+    import numpy as np
+    import torch
+    for _ in range(warmup):
+        s.step()
+    counts = s.ws[:64].view(torch.int32)
+    hist = torch.zeros((steps, 16), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    acat.profile(True)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        s.step()
+        hist[k].copy_(counts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = acat.profile_read()
+    acat.profile(False)
+    return el, hist.cpu().numpy().astype(np.int64)[:, :nclass].sum(0), prof
+
+
+def bench_high_order(acat, workloads, F, steps=20, warmup=3, n1d=1 << 22, n2d=2048):
+    """Orders above the headline's: 1D Euler with P = 5 and 6 (orders 10 and
+    12) on the Riemann-plus-sine data, and 2D Euler with P = 4 (order 8,
+    corner rectangles up to 8 x 8 nodes) on the vortex-and-band data.  For
+    each: cell-updates/s, the order classes selected and each flux kernel's
+    share of the FP64 peak under the algorithmic flop count."""
+    out = {}
+    for P in (5, 6):
+        w = workloads.euler_1d(n=n1d, P=P)
+        prob = acat.Problem(dim=1, nvar=3, nx=n1d, flux="euler", P=P, bc="transmissive", dx=w["dx"],
+                            gamma=w["gamma"])
+        s = acat.Solver(prob, w["u"], w["cfl"])
+        el, per, prof = _class_profile(acat, s, P, steps, warmup)
+        kern = {}
+        for p in range(1, P + 1):
+            name = f"flux1d_p{p}"
+            if name in prof and per[p - 1] > 0:
+                c, ms = prof[name]
+                fl = per[p - 1] * F.interface_flops_1d(p, 3, F.C_F[("euler", 1)])
+                kern[name] = {"avg_us": round(1e3 * ms / c, 2), "items": int(per[p - 1]),
+                              "frac": round(fl / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)}
+        out[f"euler1d_P{P}_n{n1d}"] = {"value": n1d * steps / el, "unit": "cell-updates/s",
+                                       "ms_per_step": 1e3 * el / steps, "kernels": kern,
+                                       "device_status": acat.device_status()}
+    P = 4
+    w = workloads.euler_2d(n=n2d, P=P)
+    prob = acat.Problem(dim=2, nvar=4, nx=n2d, ny=n2d, flux="euler", P=P, bc="periodic", dx=w["dx"], dy=w["dy"],
+                        gamma=w["gamma"])
+    s = acat.Solver(prob, w["u"], w["cfl"])
+    el, per, prof = _class_profile(acat, s, P * P, steps, warmup)
+    kern = {}
+    for q1 in range(1, P + 1):
+        for q2 in range(1, P + 1):
+            name, cnt = f"flux2d_q{q1}{q2}", per[(q1 - 1) * P + (q2 - 1)]
+            if name in prof and cnt > 0:
+                c, ms = prof[name]
+                fl = cnt * F.corner_flops_2d(q1, q2)
+                kern[name] = {"avg_us": round(1e3 * ms / c, 2), "items": int(cnt),
+                              "frac": round(fl / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)}
+    out[f"euler2d_P4_{n2d}x{n2d}"] = {"value": n2d * n2d * steps / el, "unit": "cell-updates/s",
+                                      "ms_per_step": 1e3 * el / steps, "kernels": kern,
+                                      "device_status": acat.device_status()}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,7 +371,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and adjoint workloads")
     ap.add_argument("--fd-dirs", type=int, default=32, help="finite-difference directions of the adjoint check")
-    ap.add_argument("--only", choices=["batched", "adjoint", "paper"],
+    ap.add_argument("--only", choices=["batched", "adjoint", "paper", "high"],
                     help="run only that workload and print its object (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference dispatch for HBM byte counters)")
@@ -325,6 +392,9 @@ def main():
         return
     if args.only == "paper":
         print(json.dumps(bench_paper(acat, workloads)), flush=True)
+        return
+    if args.only == "high":
+        print(json.dumps(bench_high_order(acat, workloads, F)), flush=True)
         return
     if args.only == "adjoint":
         print(json.dumps(bench_adjoint(acat, workloads, F, fd_dirs=args.fd_dirs)), flush=True)
@@ -405,6 +475,8 @@ def main():
         out["batched"] = bench_batched(acat, workloads)
         print("[bench] paper experiments", file=sys.stderr, flush=True)
         out["paper_cost_ratios"] = bench_paper(acat, workloads)
+        print("[bench] higher orders", file=sys.stderr, flush=True)
+        out["high_order"] = bench_high_order(acat, workloads, F)
         print("[bench] adjoint workload", file=sys.stderr, flush=True)
         out["adjoint"] = bench_adjoint(acat, workloads, F, fd_dirs=args.fd_dirs)
     if not args.no_cpu_baseline:

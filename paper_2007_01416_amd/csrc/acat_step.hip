@@ -102,16 +102,17 @@ __global__ __launch_bounds__(BLOCK) void k_classify1d(KProb pb, KStep st) {
 template <int FLUX, int NV, int p>
 __global__ __launch_bounds__(BLOCK) void k_flux1d(KProb pb, KStep st) {
   constexpr int L = 2 * p;            // lanes per interface = stencil nodes
-  constexpr int GPB = BLOCK / L;      // interfaces per round
+  using Grp = Groups<L>;
+  constexpr int GPB = Grp::PER_BLOCK; // interfaces per round
   constexpr int SL = L + 1;           // LDS slots per interface (one pad slot against bank conflicts)
-  constexpr int NS = GPB * SL + SL;   // slots per component, idle lanes included
+  constexpr int NS = Grp::TOTAL * SL; // slots per component, idle lanes included
   __shared__ double xs[2][NV][NS];
 
-  const int tid = threadIdx.x;
-  const int g = tid / L;
-  const int a = tid - g * L;          // node index, offset j = a - p + 1
+  const Grp grp(threadIdx.x);
+  const int g = grp.g;
+  const int a = grp.node;             // node index, offset j = a - p + 1
   const int slot = g * SL + a;
-  const bool inblk = g < GPB;
+  const bool inblk = grp.in;
   const double lam = step_dt(st) / pb.dx;
   const int64_t nx = pb.nx, nI = pb.nIx;
 
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(BLOCK) void k_flux1d(KProb pb, KStep st) {
         // share Fh^{kk-2} of every node of the stencil
 #pragma unroll
         for (int c = 0; c < NV; ++c) xs[buf][c][slot] = cur[c];
-        __syncthreads();
+        Grp::sync();
         // U^{kk-1} = -lambda * (spatial derivative of Fh^{kk-2} at this node)
         double Uk[NV];
 #pragma unroll
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(BLOCK) void k_flux1d(KProb pb, KStep st) {
       // F_c = sum_j eta_j S_j,c on lane a = c (and a + L when NV > L)
 #pragma unroll
       for (int c = 0; c < NV; ++c) xs[buf][c][slot] = S[c];
-      __syncthreads();
+      Grp::sync();
       double F0 = 0.0, F1 = 0.0;
       if (valid && a < NV) {
 #pragma unroll
@@ -394,7 +395,7 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, double lamx, double 
   for (int kk = 2; kk <= 2 * QT; ++kk) {
     double2* xsw = buf ? xsb1 : xsb0;
     Xch<NV>::put(xsw, stride, slot, fc, gc);
-    __syncthreads();
+    Groups<(2 * Q1) * (2 * Q2)>::sync();
     const double* xr = reinterpret_cast<const double*>(xsw);
     // U^{kk-1} = -lamx d_x Fh^{kk-2} - lamy d_y Gh^{kk-2} at this node
     double Uk[NV];
@@ -452,17 +453,21 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, double lamx, double 
 
 // Fluxes of the corners of order class (Q1, Q2) (Sec. 4; rectangle J_Q1 x J_Q2).
 template <int FLUX, int NV, int Q1, int Q2>
-__global__ __launch_bounds__(BLOCK) void k_flux2d(KProb pb, KStep st) {
-  constexpr int N1 = 2 * Q1, N2 = 2 * Q2, L = N1 * N2, CPB = BLOCK / L;
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_flux2d(KProb pb, KStep st) {
+  constexpr int N1 = 2 * Q1, N2 = 2 * Q2, L = N1 * N2;
+  using Grp = Groups<L>;
+  constexpr int CPB = Grp::PER_BLOCK;
   constexpr int NP = Xch<NV>::NP;
-  constexpr int STRIDE = BLOCK + L;        // slots per plane (idle lanes included)
+  // slots per plane (idle lanes included)
+  constexpr int STRIDE = Grp::WAVE_LOCAL ? Grp::TOTAL * L : BLOCK + L;
   __shared__ double2 xs[2][NP * STRIDE];
 
   const int tid = threadIdx.x;
-  const int g = tid / L;
-  const int nd = tid - g * L;
+  const Grp grp(tid);
+  const int g = grp.g;
+  const int nd = grp.node;
   const int a1 = nd % N1, a2 = nd / N1;     // node (j1, j2) = (a1 - Q1 + 1, a2 - Q2 + 1)
-  const bool inblk = g < CPB;
+  const bool inblk = grp.in;
   const int cls = (Q1 - 1) * pb.P + (Q2 - 1);
   const double dt = step_dt(st);
   const double lamx = dt / pb.dx, lamy = dt / pb.dy;
@@ -509,7 +514,7 @@ __global__ __launch_bounds__(BLOCK) void k_flux2d(KProb pb, KStep st) {
       {
         double2* xsw = buf ? xs[1] : xs[0];
         Xch<NV>::put(xsw, STRIDE, slot, SF, SG);
-        __syncthreads();
+        Grp::sync();
       }
       const double* xr = reinterpret_cast<const double*>(buf ? xs[1] : xs[0]);
       double acc[2] = {0.0, 0.0};

@@ -342,6 +342,54 @@ int persistent_grid(K kernel, int64_t nitems, int cap, int bs = BLOCK, int per_c
 
 }  // namespace
 
+// Orders a wavefront's LDS stores before its later LDS loads.  The LDS
+// operations of one wave are performed in issue order, so only the compiler
+// has to be kept from moving loads above stores; no hardware barrier.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Assignment of a block's lanes to groups of L lanes (a 1D interface's or a
+// 2D corner's stencil nodes).  When whole groups fill a 64-lane wavefront with
+// at most 1/16 of its lanes idle, groups are packed per wave: no group spans
+// two waves and its LDS exchange needs only wave_sync().  Otherwise groups
+// are packed densely over the block and exchange across a workgroup barrier.
+// Idle lanes get a spare group of their own (per wave, or one per block), so
+// their stores never touch a live group's slots.
+template <int L>
+struct Groups {
+  static constexpr int WAVE = 64;
+  static constexpr int GPW = WAVE / L;
+  static constexpr bool WAVE_LOCAL = L <= WAVE && (WAVE - GPW * L) * 16 <= WAVE;
+  static constexpr int PER_BLOCK = WAVE_LOCAL ? (BLOCK / WAVE) * GPW : BLOCK / L;
+  static constexpr int SPARE = WAVE_LOCAL ? (WAVE % L ? BLOCK / WAVE : 0) : 1;
+  static constexpr int TOTAL = PER_BLOCK + SPARE;     // groups with LDS slots, spares included
+  int g;      // group of this lane
+  int node;   // node within the group
+  bool in;    // false for idle lanes
+  __device__ __forceinline__ explicit Groups(int tid) {
+    if constexpr (WAVE_LOCAL) {
+      const int w = tid / WAVE, lw = tid % WAVE;
+      in = lw / L < GPW;
+      g = in ? w * GPW + lw / L : PER_BLOCK + w;
+      node = lw % L;
+    } else {
+      g = tid / L;
+      node = tid - g * L;
+      in = g < PER_BLOCK;
+    }
+  }
+  static __device__ __forceinline__ void sync() {
+    if constexpr (WAVE_LOCAL) {
+      wave_sync();
+    } else {
+      __syncthreads();
+    }
+  }
+};
+
 // LDS exchange of the time-derivative fluxes of a 2D corner: per node, the
 // NV components of Fh and of Gh stored as double2 pairs in component-major
 // planes (consecutive lanes write consecutive 16-byte words).
