@@ -29,16 +29,17 @@ template <int FLUX, int NV, int p>
 __global__ __launch_bounds__(BLOCK) void k_adj1d(KProb pb, KStep st, const double* __restrict__ ubo,
                                                  double* __restrict__ C, int LMAX) {
   constexpr int L = 2 * p;
-  constexpr int GPB = BLOCK / L;
+  using Grp = Groups<L>;
+  constexpr int GPB = Grp::PER_BLOCK;
   constexpr int SL = L + 1;
-  constexpr int NS = GPB * SL + SL;
+  constexpr int NS = Grp::TOTAL * SL;
   __shared__ double xs[2][NV][NS];
 
-  const int tid = threadIdx.x;
-  const int g = tid / L;
-  const int a = tid - g * L;
+  const Grp grp(threadIdx.x);
+  const int g = grp.g;
+  const int a = grp.node;
   const int slot = g * SL + a;
-  const bool inblk = g < GPB;
+  const bool inblk = grp.in;
   const double lam = step_dt(st) / pb.dx;
   const int64_t nx = pb.nx, nI = pb.nIx;
   const int nx32 = (int)nx;
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj1d(KProb pb, KStep st, const doubl
     for (int kk = 2; kk <= 2 * p - 1; ++kk) {   // Fh^{2p-1} is not needed backwards
 #pragma unroll
       for (int c = 0; c < NV; ++c) xs[buf][c][slot] = cur[c];
-      __syncthreads();
+      Grp::sync();
 #pragma unroll
       for (int c = 0; c < NV; ++c) {
         double sacc = 0.0;
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj1d(KProb pb, KStep st, const doubl
     if (2 * p >= 2) {
 #pragma unroll
       for (int c = 0; c < NV; ++c) xs[buf][c][slot] = cur[c];
-      __syncthreads();
+      Grp::sync();
 #pragma unroll
       for (int c = 0; c < NV; ++c) {
         double sacc = 0.0;
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj1d(KProb pb, KStep st, const doubl
       // U^{kk-1}_a = -lam sum_l g1[a][l] Fh^{kk-2}_l  =>  Fhbar^{kk-2}_a += -lam sum_j g1[j][a] Ubar_j
 #pragma unroll
       for (int c = 0; c < NV; ++c) xs[buf][c][slot] = Ub[kk - 1][c];
-      __syncthreads();
+      Grp::sync();
 #pragma unroll
       for (int c = 0; c < NV; ++c) {
         double sacc = 0.0;
@@ -284,7 +285,7 @@ __device__ __forceinline__ void corner_adjoint(const Phys& ph, double lamx, doub
   for (int kk = 2; kk <= T; ++kk) {
     double2* xsw = buf ? xsb1 : xsb0;
     Xch<NV>::put(xsw, stride, slot, fc, gc);
-    __syncthreads();
+    Groups<(2 * Q1) * (2 * Q2)>::sync();
     const double* xr = reinterpret_cast<const double*>(xsw);
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
@@ -390,7 +391,7 @@ __device__ __forceinline__ void corner_adjoint(const Phys& ph, double lamx, doub
     //  => Fhbar_(a1,a2) += -lamx sum_j g1x[j][a1] Ubar_(j,a2); Ghbar likewise along the column
     double2* xsw = buf ? xsb1 : xsb0;
     Xch<NV>::put(xsw, stride, slot, Ub[kk - 1], Ub[kk - 1]);
-    __syncthreads();
+    Groups<(2 * Q1) * (2 * Q2)>::sync();
     const double* xr = reinterpret_cast<const double*>(xsw);
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
@@ -417,16 +418,19 @@ __device__ __forceinline__ void corner_adjoint(const Phys& ph, double lamx, doub
 template <int FLUX, int NV, int Q1, int Q2>
 __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const double* __restrict__ ubo,
                                                  double* __restrict__ C, int LMAX) {
-  constexpr int N1 = 2 * Q1, N2 = 2 * Q2, L = N1 * N2, CPB = BLOCK / L;
+  constexpr int N1 = 2 * Q1, N2 = 2 * Q2, L = N1 * N2;
+  using Grp = Groups<L>;
+  constexpr int CPB = Grp::PER_BLOCK;
   constexpr int NP = Xch<NV>::NP;
-  constexpr int STRIDE = BLOCK + L;
+  constexpr int STRIDE = Grp::WAVE_LOCAL ? Grp::TOTAL * L : BLOCK + L;
   __shared__ double2 xs[2][NP * STRIDE];
 
   const int tid = threadIdx.x;
-  const int g = tid / L;
-  const int nd = tid - g * L;
+  const Grp grp(tid);
+  const int g = grp.g;
+  const int nd = grp.node;
   const int a1 = nd % N1, a2 = nd / N1;
-  const bool inblk = g < CPB;
+  const bool inblk = grp.in;
   const int cls = (Q1 - 1) * pb.P + (Q2 - 1);
   const double dt = step_dt(st);
   const double lamx = dt / pb.dx, lamy = dt / pb.dy;

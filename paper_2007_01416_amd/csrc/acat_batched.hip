@@ -74,16 +74,17 @@ __global__ __launch_bounds__(BLOCK) void k_classify_b(KBatch bt, KBStep st) {
 template <int FLUX, int NV, int p, int BS>
 __global__ __launch_bounds__(BS) void k_flux_b(KBatch bt, KBStep st) {
   constexpr int L = 2 * p;
-  constexpr int GPB = BS / L;
+  using Grp = Groups<L, BS>;
+  constexpr int GPB = Grp::PER_BLOCK;
   constexpr int SL = L + 1;
-  constexpr int NS = GPB * SL + SL;
+  constexpr int NS = Grp::TOTAL * SL;
   __shared__ double xs[2][NV][NS];
 
-  const int tid = threadIdx.x;
-  const int g = tid / L;
-  const int a = tid - g * L;
+  const Grp grp(threadIdx.x);
+  const int g = grp.g;
+  const int a = grp.node;
   const int slot = g * SL + a;
-  const bool inblk = g < GPB;
+  const bool inblk = grp.in;
 
   double g1[L];
 #pragma unroll
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(BS) void k_flux_b(KBatch bt, KBStep st) {
     for (int kk = 2; kk <= 2 * p; ++kk) {
 #pragma unroll
       for (int c = 0; c < NV; ++c) xs[buf][c][slot] = cur[c];
-      __syncthreads();
+      Grp::sync();
       double Uk[NV];
 #pragma unroll
       for (int c = 0; c < NV; ++c) {
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(BS) void k_flux_b(KBatch bt, KBStep st) {
     }
 #pragma unroll
     for (int c = 0; c < NV; ++c) xs[buf][c][slot] = S[c];
-    __syncthreads();
+    Grp::sync();
     if (valid && a < NV) {
       for (int task = 0; task < 2; ++task) {
         const int c = a + task * L;

@@ -358,13 +358,13 @@ __device__ __forceinline__ void wave_sync() {
 // are packed densely over the block and exchange across a workgroup barrier.
 // Idle lanes get a spare group of their own (per wave, or one per block), so
 // their stores never touch a live group's slots.
-template <int L>
+template <int L, int BS = BLOCK>
 struct Groups {
   static constexpr int WAVE = 64;
   static constexpr int GPW = WAVE / L;
   static constexpr bool WAVE_LOCAL = L <= WAVE && (WAVE - GPW * L) * 16 <= WAVE;
-  static constexpr int PER_BLOCK = WAVE_LOCAL ? (BLOCK / WAVE) * GPW : BLOCK / L;
-  static constexpr int SPARE = WAVE_LOCAL ? (WAVE % L ? BLOCK / WAVE : 0) : 1;
+  static constexpr int PER_BLOCK = WAVE_LOCAL ? (BS / WAVE) * GPW : BS / L;
+  static constexpr int SPARE = WAVE_LOCAL ? (WAVE % L ? BS / WAVE : 0) : 1;
   static constexpr int TOTAL = PER_BLOCK + SPARE;     // groups with LDS slots, spares included
   int g;      // group of this lane
   int node;   // node within the group
