@@ -18,6 +18,22 @@ struct Phys {
   double ax, ay;
 };
 
+// a / b, correctly rounded, for b and nonzero a of magnitude in [2^-300, 2^300]
+// and for a = +0: the compiler's IEEE division sequence (reciprocal estimate,
+// two Newton steps, quotient, residual, correction) without its operand
+// scaling and special-case fix-up, which are identities there.  (a = -0 gives
+// +0 instead of -0.)
+__device__ __forceinline__ double div_rn(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  double e = fma(-b, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-b, r, 1.0);
+  r = fma(r, e, r);
+  const double q = a * r;
+  const double rem = fma(-b, q, a);
+  return fma(rem, r, q);
+}
+
 // x-direction flux of a 1D law
 template <int FLUX, int NV>
 __device__ __forceinline__ void flux1d(const Phys& ph, const double (&u)[NV], double (&f)[NV]) {
@@ -28,7 +44,7 @@ __device__ __forceinline__ void flux1d(const Phys& ph, const double (&u)[NV], do
     f[0] = 0.5 * (u[0] * u[0]);
   } else {
     static_assert(NV == 3, "1D Euler has 3 conserved variables");
-    const double v = u[1] / u[0];
+    const double v = div_rn(u[1], u[0]);
     const double p = ph.gm1 * (u[2] - 0.5 * (u[1] * v));
     f[0] = u[1];
     f[1] = u[1] * v + p;
@@ -90,7 +106,7 @@ __device__ __forceinline__ void flux1d_vjp(const Phys& ph, const double (&u)[NV]
   } else {
     // f = (m, m v + p, v (E + p)), v = m / rho, p = (gamma-1)(E - m v / 2)
     const double rho = u[0], m = u[1], E = u[2];
-    const double v = m / rho;
+    const double v = div_rn(m, rho);
     const double p = ph.gm1 * (E - 0.5 * (m * v));
     double mb = fb[0] + fb[1] * v, vb = fb[1] * m + fb[2] * (E + p);
     const double epb = fb[2] * v;
@@ -100,8 +116,8 @@ __device__ __forceinline__ void flux1d_vjp(const Phys& ph, const double (&u)[NV]
     const double q = ph.gm1 * pb;
     mb -= 0.5 * q * v;
     vb -= 0.5 * q * m;
-    mb += vb / rho;
-    ub[0] += -vb * v / rho;
+    mb += div_rn(vb, rho);
+    ub[0] += div_rn(-vb * v, rho);
     ub[1] += mb;
     ub[2] += Eb;
   }
@@ -116,7 +132,7 @@ __device__ __forceinline__ void flux2d_vjp(const Phys& ph, const double (&u)[NV]
     for (int c = 0; c < NV; ++c) ub[c] += ph.ax * fb[c] + ph.ay * gb[c];
   } else {
     const double rho = u[0], m = u[1], n = u[2], E = u[3];
-    const double ir = 1.0 / rho;
+    const double ir = recip(rho);
     const double v = m * ir, w = n * ir;
     const double p = ph.gm1 * (E - 0.5 * (m * v + n * w));
     const double ep = E + p;
