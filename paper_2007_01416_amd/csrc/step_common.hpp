@@ -14,6 +14,9 @@ constexpr CoeffTables TB = make_tables();
 constexpr int NXCD = 8;   // MI355X: 8 accelerator complex dies, each with its own L2
 
 // ---------------------------------------------------------------- helpers
+// Quotients below use div_rn (physics.hpp): the indicator's operands are sums
+// of squares plus epsilon and the limiter's are state differences, inside the
+// range where it equals IEEE division.
 __device__ __forceinline__ double superbee(double r) { return fmax(0.0, fmax(fmin(2.0 * r, 1.0), fmin(r, 2.0))); }
 
 // Modified p = 2 indicator of one component (Sec. 3.2): the lateral weights
@@ -31,13 +34,13 @@ __device__ __forceinline__ double psi2_modified(const double (&v)[2 * G], double
   I2L += eps;
   double I2R = dr * dr;
   I2R += eps;
-  const double I1 = I1L * I1R / (I1L + I1R), I2 = I2L * I2R / (I2L + I2R);
+  const double I1 = div_rn(I1L * I1R, I1L + I1R), I2 = div_rn(I2L * I2R, I2L + I2R);
   double s = 0.0;
 #pragma unroll
   for (int j = -1; j <= 2; ++j) s += TB.TAU[2][j + 1] * v[j + G - 1];
   double tau = TB.FACT2PM1[2] * s;
   tau = tau * tau;
-  return fmax(I1 / (I1 + tau), I2 / (I2 + tau));
+  return fmax(div_rn(I1, I1 + tau), div_rn(I2, I2 + tau));
 }
 
 // psi^p of one component; v holds offsets -G+1 .. G (index j + G - 1).
@@ -56,13 +59,13 @@ __device__ __forceinline__ double psi_comp(const double (&v)[2 * G], double eps)
   }
   IL += eps;
   IR += eps;
-  const double I = IL * IR / (IL + IR);
+  const double I = div_rn(IL * IR, IL + IR);
   double s = 0.0;
 #pragma unroll
   for (int j = -p + 1; j <= p; ++j) s += TB.TAU[p][j + p - 1] * v[j + G - 1];
   double tau = TB.FACT2PM1[p] * s;
   tau = tau * tau;
-  return I / (I + tau);
+  return div_rn(I, I + tau);
 }
 
 // p_s = max{p in 2..P : min_c psi^{c,p} >= theta}, else 1 (evaluated from P down)
@@ -101,10 +104,10 @@ __device__ __forceinline__ double limiter_roe(const Phys& ph, const double (&v)[
     f1 = a * u1;
     fp = a;
   }
-  const double a = dloc != 0.0 ? (f1 - f0) / dloc : fp;
+  const double a = dloc != 0.0 ? div_rn(f1 - f0, dloc) : fp;
   const double dupw = a > 0.0 ? u0 - v[0][G - 2] : v[0][G + 1] - u1;
   if (dloc == 0.0) return dupw == 0.0 ? 1.0 : 0.0;
-  return superbee(dupw / dloc);
+  return superbee(div_rn(dupw, dloc));
 }
 
 // psi^1 = min_c min(phi(r+), phi(r-)); a component with u_{i+1} = u_i gives 1
@@ -119,7 +122,7 @@ __device__ __forceinline__ double limiter(const double (&v)[NV][2 * G]) {
     // constant component is smooth (1), a plateau next to a variation is an
     // extremum or a corner (0)
     double l = (dm == 0.0 && dp == 0.0) ? 1.0 : 0.0;
-    if (dl != 0.0) l = fmin(superbee(dp / dl), superbee(dm / dl));
+    if (dl != 0.0) l = fmin(superbee(div_rn(dp, dl)), superbee(div_rn(dm, dl)));
     psi = fmin(psi, l);
   }
   return psi;
