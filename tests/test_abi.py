@@ -63,6 +63,11 @@ def _prob(**kw):
     (dict(flux="burgers", nvar=1, dim=2, ny=16, dy=0.1), -2),
     (dict(flux="advection", nvar=2), -4), (dict(dim=2, nvar=4, ny=64, dy=0.1, P=5), -4),
     (dict(gamma=1.0), -2),
+    # smallest grid: 2 max(P, 2) cells per direction
+    (dict(nx=7, P=4), -2), (dict(nx=11, P=6), -2), (dict(dim=2, nvar=4, nx=64, ny=5, dy=0.1, P=3), -2),
+    # largest: item indices are 32-bit
+    (dict(nx=(1 << 31) + 1), -2), (dict(nx=1 << 31), -4),
+    (dict(dim=2, nvar=4, nx=1 << 16, ny=1 << 16, dy=0.1), -4),
 ])
 def test_workspace_size_rejects_invalid_problems(lib, kw, code):
     n = ctypes.c_size_t(0)
@@ -92,6 +97,16 @@ def test_step_argument_errors_before_launch(lib):
     # cfl: non-positive cfl
     assert lib.acat_cfl_dt(ctypes.byref(pc), a, 0.0, 1.0, None, b, None) == -2
     assert lib.acat_max_wave_speed(ctypes.byref(pc), None, b, None) == -1
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4, 5, 6])
+def test_smallest_grid_is_accepted(lib, P):
+    n = ctypes.c_size_t(0)
+    g = 2 * max(P, 2)
+    assert lib.acat_workspace_size(ctypes.byref(_prob(nx=g, P=P).c()), ctypes.byref(n)) == 0 and n.value > 0
+    if P <= 4:
+        p2 = _prob(dim=2, nvar=4, nx=g, ny=g, dy=0.1, P=P)
+        assert lib.acat_workspace_size(ctypes.byref(p2.c()), ctypes.byref(n)) == 0 and n.value > 0
 
 
 def test_workspace_grows_with_problem(lib):
