@@ -27,14 +27,24 @@ WORKLOAD = ("2D Euler gamma=1.4, 2048x2048, periodic, ACAT P=3, CFL 0.4, 8 isent
             "4 axis-aligned contact/shock lines (p jumps U[2,10])")
 
 
+# the sources the single-problem step kernels are compiled from
+STEP_SOURCES = ("acat_step.hip", "step_common.hpp", "physics.hpp", "coeffs.hpp", "acat_internal.hpp")
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in STEP_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2007_01416_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def traffic_from_profiles(kernel: str):
     """HBM bytes per launch of `kernel` from the committed counter summary,
     if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_c3_counters.txt")
-    src = os.path.join(ROOT, "paper_2007_01416_amd", "csrc", "acat_step.hip")
     if not os.path.exists(path):
         return None
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    digest = kernel_source_digest()
     vals = {}
     for line in open(path):
         if ":" in line:
