@@ -372,6 +372,42 @@ def bench_high_order(acat, workloads, F, steps=20, warmup=3, n1d=1 << 22, n2d=20
     return out
 
 
+def measured_peaks(acat, reps=5):
+    """FP64 FMA rate (acat_fp64_fma_rate: 16 independent FMA chains per lane,
+    8 blocks of 256 threads per CU) and HBM copy bandwidth (1 GiB device to
+    device copy, read + write bytes), each the best of `reps` launches timed
+    with events on the current stream, at the running clock."""
+    import torch
+    blocks, iters = 256 * 8, 4096
+    out = torch.empty(blocks * acat.FMA_THREADS, dtype=torch.float64, device="cuda")
+    acat.fp64_fma_rate(out, blocks, 64)
+    best_fma = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        flops = acat.fp64_fma_rate(out, blocks, iters)
+        b.record()
+        torch.cuda.synchronize()
+        best_fma = min(best_fma, a.elapsed_time(b) * 1e-3)
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best_copy = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        best_copy = min(best_copy, a.elapsed_time(b) * 1e-3)
+    finite = bool(torch.isfinite(out).all().item())
+    del src, dst
+    return {"fp64_fma_tflops": flops / best_fma / 1e12, "hbm_copy_tb_s": 2 * (1 << 30) / best_copy / 1e12,
+            "fma_output_finite": finite,
+            "method": "best of %d: FMA-chain kernel %d blocks x 256 threads x %d iterations x 16 chains; "
+                      "1 GiB device-to-device copy" % (reps, blocks, iters)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -453,6 +489,7 @@ def main():
     alg_total = sum(class_flops.values()) + args.steps * cells * (F.classify_flops(P, 4, 2) + F.update_flops(4, 2))
     kern_ms = sum(v["total_ms"] for v in kernels.values())
     hist_cls = hist[:, :P * P].sum(0)
+    peaks = measured_peaks(acat)
     out = {
         "metric": "ACAT FP64 cell-updates/s, 2D Euler 2048^2",
         "value": value,
@@ -472,7 +509,9 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": traffic, "launches": dom_launches,
                      "avg_launch_us": kernels[dom]["avg_us"],
-                     "alg_flops_per_launch": class_flops[dom] / max(dom_launches, 1)},
+                     "alg_flops_per_launch": class_flops[dom] / max(dom_launches, 1),
+                     "frac_of_measured_fp64": achieved / peaks["fp64_fma_tflops"]},
+        "measured_peaks": peaks,
         "step_alg_tflops": alg_total / el / 1e12,
         "kernel_time_fraction": kern_ms / (1e3 * el),
         "order_classes": {f"q{q1}{q2}": int(hist_cls[(q1 - 1) * P + (q2 - 1)]) for q1 in range(1, P + 1)

@@ -231,6 +231,16 @@ acat_status acat_profile_enable(int32_t on);
 acat_status acat_profile_read(int32_t max_kernels, char* names /* host [max][64] */, double* total_ms,
                               int64_t* launches, int32_t* n_kernels);
 
+/* Measured FP64 issue rate: launches `blocks` blocks of 256 threads, each
+ * thread running 16 independent chains of `iters` fused multiply-adds
+ * (blocks * 256 * iters * 16 FMAs = that many times 2 flops), and writes one
+ * value per thread to out[blocks * 256] (device, caller-owned; out_len
+ * elements).  The caller times the launch on `stream` (events) to obtain the
+ * FP64 rate at the running clock, which the roofline reports next to the
+ * published peak.  ACAT_ERR_ARG if blocks is outside 1..2^20, iters < 1 or
+ * out_len < blocks * 256. */
+acat_status acat_fp64_fma_rate(int32_t blocks, int32_t iters, double* out, int64_t out_len, void* stream);
+
 /* Coefficient tables the kernels use for half-width p = 1..6 (host arrays, row
  * major): g1[2p][2p] first derivatives at the nodes, gt[2p][2p] k-th time
  * derivatives at 0 (k = 0..2p-1), eta[2p] interface weights, tau[2p] the

@@ -76,6 +76,7 @@ _SIGS = {
     "acat_batched_cfl_dt": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                             ctypes.c_size_t, ctypes.c_void_p],
     "acat_profile_enable": [ctypes.c_int32],
+    "acat_fp64_fma_rate": [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p],
     "acat_profile_read": [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                           ctypes.POINTER(ctypes.c_int32)],
 }
@@ -379,6 +380,19 @@ class Batch:
 def profile(on: bool = True):
     """Start (clear) or stop the library's kernel timer."""
     _check(load().acat_profile_enable(1 if on else 0), "acat_profile_enable")
+
+
+FMA_THREADS, FMA_CHAINS = 256, 16
+
+
+def fp64_fma_rate(out: torch.Tensor, blocks: int, iters: int, stream=None) -> int:
+    """Launch the FP64 FMA-chain kernel; returns the flops of the launch
+    (the caller times it on the stream)."""
+    if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 CUDA tensor")
+    _check(load().acat_fp64_fma_rate(blocks, iters, out.data_ptr(), out.numel(), _stream(stream)),
+           "acat_fp64_fma_rate")
+    return 2 * blocks * FMA_THREADS * iters * FMA_CHAINS
 
 
 def profile_read(max_kernels: int = 64) -> dict:

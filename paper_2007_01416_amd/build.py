@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libacat.so")
-SOURCES = ["acat_step.hip", "acat_batched.hip", "acat_adjoint.hip", "acat_api.hip", "acat_profile.cpp"]
+SOURCES = ["acat_step.hip", "acat_batched.hip", "acat_adjoint.hip", "acat_api.hip", "acat_measure.hip",
+           "acat_profile.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -ffp-contract=off: no implicit fused multiply-add; the kernels write every

@@ -226,3 +226,12 @@ def test_flags_validation(lib, flags, code, adj):
     # the Roe-speed limiter is accepted for a scalar law
     pb = _prob(flux="burgers", nvar=1, flags=8).c()
     assert lib.acat_workspace_size(ctypes.byref(pb), ctypes.byref(n)) == 0
+
+
+def test_fma_rate_argument_errors(lib):
+    buf = (ctypes.c_double * 256)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    assert lib.acat_fp64_fma_rate(1, 1, None, 256, None) == -1
+    assert lib.acat_fp64_fma_rate(0, 1, p, 256, None) == -2
+    assert lib.acat_fp64_fma_rate(1, 0, p, 256, None) == -2
+    assert lib.acat_fp64_fma_rate(2, 1, p, 256, None) == -2
