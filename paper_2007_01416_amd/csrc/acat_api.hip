@@ -91,7 +91,7 @@ Layout layout(const KProb& k) {
   const int64_t nx_if = k.ny * k.nIx;             // 1D: nI
   const int64_t ny_if = k.dim == 2 ? k.nIy * k.nx : 0;
   L.nItems = k.dim == 2 ? k.n1 * k.n2 : k.nIx;
-  const int64_t cblocks = (L.nItems + BLOCK - 1) / BLOCK;
+  const int64_t cblocks = class_tiles(k);
   size_t o = 0;
   L.hdr = o;   o += align_up(sizeof(int32_t) * MAX_CLASSES + sizeof(uint32_t) * 4);
   L.ordx = o;  o += align_up((size_t)nx_if);
@@ -207,7 +207,7 @@ ALayout alayout(const KProb& k) {
   ALayout L{};
   L.nItems = k.dim == 2 ? k.n1 * k.n2 : k.nIx;
   L.lmax = k.dim == 2 ? 4 * k.P * k.P : 2 * k.P;
-  const int64_t cblocks = (L.nItems + BLOCK - 1) / BLOCK;
+  const int64_t cblocks = class_tiles(k);
   size_t o = 0;
   L.hdr = o;   o += align_up(sizeof(int32_t) * MAX_CLASSES + sizeof(uint32_t) * 4);
   L.cls = o;   o += align_up((size_t)L.nItems);

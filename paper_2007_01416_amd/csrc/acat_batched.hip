@@ -293,7 +293,8 @@ hipError_t step_b_impl(const KBatch& bt, const KBStep& st, hipStream_t s) {
   ACAT_CHECK_LAUNCH();
   k_scan_hist<<<bt.Pmax, SCAN_T, 0, s>>>(st.hist, cblocks, st.offs, st.counts, bt.Pmax, CflReduce{});
   ACAT_CHECK_LAUNCH();
-  k_scatter<BATCH_PMAX><<<cblocks, BLOCK, 0, s>>>(st.ord, 1, bt.nif, cblocks, st.offs, st.counts, st.list);
+  k_scatter<BATCH_PMAX, false><<<cblocks, BLOCK, 0, s>>>(st.ord, 1, bt.nif, 1, cblocks, st.offs, st.counts,
+                                                         st.list);
   ACAT_CHECK_LAUNCH();
   hipError_t e;
   if ((e = launch_flux_b<FLUX, NV, 1>(bt, st, s)) != hipSuccess) return e;

@@ -27,6 +27,18 @@ struct KProb {
   double dx, dy, eps, theta;
 };
 
+// Tiles of the classification and of the class lists.  1D: 256 consecutive
+// interfaces.  2D: 16 x 16 corners, tiles numbered row by row; the class
+// lists are therefore tile-major (row-major inside a tile), so a block
+// walking a stretch of a list works on a compact patch of the grid whose
+// stencil cells stay in cache.
+constexpr int TILE_X = 16, TILE_Y = 16;
+static_assert(TILE_X * TILE_Y == BLOCK, "one classification thread per item of a tile");
+inline int64_t class_tiles(const KProb& k) {
+  if (k.dim == 2) return ((k.n1 + TILE_X - 1) / TILE_X) * ((k.n2 + TILE_Y - 1) / TILE_Y);
+  return (k.nIx + BLOCK - 1) / BLOCK;
+}
+
 // Everything one step's kernels read and write.
 struct KStep {
   const double* u;
@@ -45,7 +57,7 @@ struct KStep {
   int32_t* hist;          // per-tile class histograms of the classification kernel [tiles][MAX_CLASSES]
   int32_t* offs;          // per-class exclusive prefix of hist over tiles [MAX_CLASSES][tiles + 1]
   int32_t* counts;        // [MAX_CLASSES] items per order class
-  int32_t* list;          // item ids grouped by class, spatial order within a class [items]
+  int32_t* list;          // item ids grouped by class, tile order within a class [items]
   uint32_t* status;       // device status bits
   int replay;             // decisions given in ord/psi/al
   // CFL mode: the classification also reduces the cells' spectral radii into

@@ -260,15 +260,20 @@ __global__ __launch_bounds__(BLOCK) void k_update1d(KProb pb, KStep st) {
 }
 
 // ======================================================================= 2D
+// One block per 16 x 16 tile of corners, one thread per corner.
 template <int FLUX, int NV, int P>
 __global__ __launch_bounds__(BLOCK) void k_classify2d(KProb pb, KStep st) {
   constexpr int G = P > 2 ? P : 2;
-  const int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int64_t ntx = (pb.n1 + TILE_X - 1) / TILE_X;
+  const int64_t e1 = (blockIdx.x % ntx) * TILE_X + threadIdx.x % TILE_X;
+  const int64_t e2 = (blockIdx.x / ntx) * TILE_Y + threadIdx.x / TILE_X;
+  const bool inside = e1 < pb.n1 && e2 < pb.n2;
+  const int64_t e = e2 * pb.n1 + e1;
   const int64_t nx = pb.nx, ny = pb.ny;
-  const int64_t i1 = (e < pb.n1 * pb.n2) ? e % pb.n1 + pb.ioff : 0;
-  const int64_t i2 = (e < pb.n1 * pb.n2) ? e / pb.n1 + pb.ioff : 0;
+  const int64_t i1 = inside ? e1 + pb.ioff : 0;
+  const int64_t i2 = inside ? e2 + pb.ioff : 0;
   const bool needF = i2 >= 0, needG = i1 >= 0;
-  const bool valid = e < pb.n1 * pb.n2 && (needF || needG);
+  const bool valid = inside && (needF || needG);
   int q1 = 1, q2 = 1;
   double sx = 0.0, sy = 0.0;
   if (valid) {
@@ -350,7 +355,7 @@ __global__ __launch_bounds__(BLOCK) void k_classify2d(KProb pb, KStep st) {
     }
   }
   const int cls = (q1 - 1) * P + (q2 - 1);
-  if (e < pb.n1 * pb.n2) st.cls[e] = valid ? (int8_t)cls : (int8_t)-1;
+  if (inside) st.cls[e] = valid ? (int8_t)cls : (int8_t)-1;
   __shared__ int sh[MAX_CLASSES];
   block_hist(sh, valid, cls, st.hist);
   if (st.cfl_mode) {
@@ -702,7 +707,7 @@ hipError_t lists1d_impl(const KProb& pb, const KStep& st, hipStream_t s) {
     ProfScope ps("class_lists", s);
     k_scan_hist<<<P + (st.cfl_mode ? 1 : 0), SCAN_T, 0, s>>>(st.hist, cblocks, st.offs, st.counts, P,
                                                             cfl_reduce(pb, st, cblocks));
-    k_scatter<P><<<cblocks, BLOCK, 0, s>>>(st.cls, 0, nI, cblocks, st.offs, st.counts, st.list);
+    k_scatter<P, false><<<cblocks, BLOCK, 0, s>>>(st.cls, 0, nI, 1, cblocks, st.offs, st.counts, st.list);
   }
   ACAT_CHECK_LAUNCH();
   return hipSuccess;
@@ -747,8 +752,7 @@ hipError_t launch_class2d(const KProb& pb, const KStep& st, int cap, hipStream_t
 
 template <int FLUX, int NV, int P>
 hipError_t lists2d_impl(const KProb& pb, const KStep& st, hipStream_t s) {
-  const int64_t nc = pb.n1 * pb.n2;
-  const int cblocks = (int)((nc + BLOCK - 1) / BLOCK);
+  const int cblocks = (int)class_tiles(pb);
   {
     ProfScope ps("classify2d", s);
     k_classify2d<FLUX, NV, P><<<cblocks, BLOCK, 0, s>>>(pb, st);
@@ -758,7 +762,8 @@ hipError_t lists2d_impl(const KProb& pb, const KStep& st, hipStream_t s) {
     ProfScope ps("class_lists", s);
     k_scan_hist<<<P * P + (st.cfl_mode ? 1 : 0), SCAN_T, 0, s>>>(st.hist, cblocks, st.offs, st.counts, P * P,
                                                                 cfl_reduce(pb, st, cblocks));
-    k_scatter<P * P><<<cblocks, BLOCK, 0, s>>>(st.cls, 0, nc, cblocks, st.offs, st.counts, st.list);
+    k_scatter<P * P, true><<<cblocks, BLOCK, 0, s>>>(st.cls, 0, pb.n1, pb.n2, cblocks, st.offs, st.counts,
+                                                      st.list);
   }
   ACAT_CHECK_LAUNCH();
   return hipSuccess;

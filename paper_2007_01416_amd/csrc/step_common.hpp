@@ -269,13 +269,27 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_hist(const int32_t* hist, int n
 
 // list[base_c + offs[c][tile] + rank] = item, for the item of every thread
 // (rank among the tile's items of the same class, in thread order).  One
-// block per tile of the classification; no atomics, deterministic.
-template <int NCLS>
-__global__ __launch_bounds__(BLOCK) void k_scatter(const int8_t* map, int map_bias, int64_t nitems, int ntiles,
-                                                   const int32_t* offs, const int32_t* counts, int32_t* list) {
+// block per tile of the classification, with the same tiles: n1 consecutive
+// items (1D, n2 = 1), or a 16 x 16 patch of the n2 x n1 corner grid (TILED).
+// No atomics, deterministic.
+template <int NCLS, bool TILED>
+__global__ __launch_bounds__(BLOCK) void k_scatter(const int8_t* map, int map_bias, int64_t n1, int64_t n2,
+                                                   int ntiles, const int32_t* offs, const int32_t* counts,
+                                                   int32_t* list) {
   __shared__ int wc[NCLS][BLOCK / 64];
-  const int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  const int c = e < nitems ? map[e] - map_bias : -1;
+  int64_t e;
+  bool inside;
+  if constexpr (TILED) {
+    const int64_t ntx = (n1 + TILE_X - 1) / TILE_X;
+    const int64_t e1 = (blockIdx.x % ntx) * TILE_X + threadIdx.x % TILE_X;
+    const int64_t e2 = (blockIdx.x / ntx) * TILE_Y + threadIdx.x / TILE_X;
+    inside = e1 < n1 && e2 < n2;
+    e = e2 * n1 + e1;
+  } else {
+    e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    inside = e < n1;
+  }
+  const int c = inside ? map[e] - map_bias : -1;
   const int lane = __lane_id(), wid = threadIdx.x >> 6;
   unsigned long long mine = 0ull;
 #pragma unroll
