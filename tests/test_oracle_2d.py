@@ -206,3 +206,44 @@ def test_jvp_matches_central_difference_2d():
     up = oracle.step2d(pb, u + h * d, dt, maps=maps)["u"]
     um = oracle.step2d(pb, u - h * d, dt, maps=maps)["u"]
     assert np.abs((up - um) / (2 * h) - jv).max() < 1e-7 * np.abs(jv).max()
+
+
+@pytest.mark.parametrize("q1,q2", [(1, 2), (2, 1), (1, 3), (3, 1), (2, 3), (3, 2), (1, 4), (4, 2), (3, 4), (4, 3)])
+def test_rectangle_corners_linear_closed_form(q1, q2):
+    """Sec. 4 on the rectangle J_q1 x J_q2 with q1 != q2 (two recursions on one
+    rectangle, time nodes J_q1 for F and J_q2 for G), linear advection.  The
+    time-derivative formula on 2q points is exact on the Taylor predictions
+    (polynomials of degree < 2q in r), so Fh^k = a U^k, Gh^k = b U^k and
+    U^k = M^k u with M = -lam_x a Dx - lam_y b Dy, Dx and Dy the first-derivative
+    matrices of the rectangle's rows (nodes J_q1) and columns (nodes J_q2).
+    The fluxes are then F = a sum_{k=1}^{2 q1} 1/k! sum_l eta_l (M^{k-1} u)_(l,0)
+    and G = b sum_{k=1}^{2 q2} 1/k! sum_l eta_l (M^{k-1} u)_(0,l): matrix powers
+    in place of predictions, flux evaluations and time-derivative weights.
+    A direction of order 1 is taken with psi^1 = 1 (pure CAT2)."""
+    rng = np.random.default_rng(100 + 10 * q1 + q2)
+    nx, ny = 19, 17
+    a, b, dx, dy, dt = 0.7, -0.45, 0.1, 0.13, 0.02
+    P = max(q1, q2)
+    pb = prob2d(nx, ny, P, flux=ADV, dx=dx, dy=dy, ax=a, ay=b)
+    u = rng.standard_normal((1, ny, nx))
+    nIx, nIy = pb.n_interfaces
+    maps = (np.full((ny, nIx), q1, np.int8), np.full((nIy, nx), q2, np.int8),
+            np.ones((ny, nIx)), np.ones((nIy, nx)), np.ones((ny, nIx)), np.ones((nIy, nx)))
+    r = oracle.step2d(pb, u, dt, maps=maps)
+    n1, n2 = 2 * q1, 2 * q2
+    c1, c2 = oracle.coeffs(q1), oracle.coeffs(q2)
+    Dx = np.kron(np.eye(n2), c1["g1"])          # node index a2 * n1 + a1
+    Dy = np.kron(c2["g1"], np.eye(n1))
+    M = -(dt / dx) * a * Dx - (dt / dy) * b * Dy
+    fact = np.cumprod([1.0] + list(range(1, 2 * P + 1)))
+    for i2 in range(0, ny, 3):
+        for i1 in range(0, nx, 2):
+            rows = (i2 + np.arange(n2) - q2 + 1) % ny
+            cols = (i1 + np.arange(n1) - q1 + 1) % nx
+            U = [u[0][np.ix_(rows, cols)].ravel()]
+            for _ in range(2 * P):
+                U.append(M @ U[-1])
+            F = a * sum(c1["eta"] @ U[k - 1][(q2 - 1) * n1 + np.arange(n1)] / fact[k] for k in range(1, 2 * q1 + 1))
+            Gv = b * sum(c2["eta"] @ U[k - 1][np.arange(n2) * n1 + (q1 - 1)] / fact[k] for k in range(1, 2 * q2 + 1))
+            assert abs(r["F"][0, i2, i1] - F) <= 1e-13 * max(1.0, abs(F)), (i1, i2, r["F"][0, i2, i1], F)
+            assert abs(r["G"][0, i2, i1] - Gv) <= 1e-13 * max(1.0, abs(Gv)), (i1, i2, r["G"][0, i2, i1], Gv)
