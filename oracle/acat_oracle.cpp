@@ -43,6 +43,15 @@
 //     bit, which matters because the limiter and the admissibility test are
 //     discontinuous in the data.
 //
+// Pins (tests/test_oracle_*.py, tests/golden/): exact-rational coefficient
+// identities and tables, closed forms (CAT2 in 1D and 2D, the order-2p
+// Lax-Wendroff stencil and the q1 != q2 rectangles for linear flux), exact
+// shift at unit Courant number, convergence orders, conservation, symmetries,
+// reductions, and exact Riemann solutions of the paper's shock tubes.  Parity
+// unpinned: the values of nonlinear shocked states, and the nonlinear flux
+// evaluations on q1 != q2 rectangles, for which no closed form or printed
+// value exists.
+//
 // Build: g++ -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math).
 #include <cmath>
 #include <cstdint>
