@@ -182,8 +182,9 @@ acat_status acat_cfl_dt(const acat_problem* prob, const double* smax_dev, double
  *   States: SoA over the concatenated cells, u[var][coff_b + i] with
  *   coff_b = n[0] + ... + n[b-1] (total C cells: arrays of nvar * C).
  * The descriptor is a host struct of host arrays; acat_batch_init copies
- * it into the workspace once (synchronously); every later call takes the
- * same descriptor and workspace.
+ * it into the workspace once (synchronously), together with the problem
+ * index of every interface and of every cell (4 bytes each); every later
+ * call takes the same descriptor and workspace.
  * --------------------------------------------------------------------- */
 typedef struct {
   int32_t nvar;         /* as in acat_problem (1D)                             */

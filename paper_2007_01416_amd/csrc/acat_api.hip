@@ -259,7 +259,7 @@ acat_status check_batch(const acat_batch* bt) {
 }
 
 struct BLayout {
-  size_t hdr, coff, ioffs, N, P, bc, dx, smax, ord, psi, al, F, hist, offs, list, total;
+  size_t hdr, coff, ioffs, N, P, bc, dx, pif, pcell, smax, ord, psi, al, F, hist, offs, list, total;
   int64_t ncell, nif;
   int Pmax;
 };
@@ -282,6 +282,8 @@ BLayout blayout(const acat_batch* bt) {
   L.P = o;     o += align_up(sizeof(int32_t) * np);
   L.bc = o;    o += align_up(sizeof(int32_t) * np);
   L.dx = o;    o += align_up(sizeof(double) * np);
+  L.pif = o;   o += align_up(sizeof(int32_t) * L.nif);
+  L.pcell = o; o += align_up(sizeof(int32_t) * L.ncell);
   L.smax = o;  o += align_up(sizeof(double) * np);
   L.ord = o;   o += align_up((size_t)L.nif);
   L.psi = o;   o += align_up(sizeof(double) * L.nif);
@@ -314,6 +316,8 @@ KBatch make_kbatch(const acat_batch* bt, const BLayout& L, char* w) {
   k.P = reinterpret_cast<const int32_t*>(w + L.P);
   k.bc = reinterpret_cast<const int32_t*>(w + L.bc);
   k.dx = reinterpret_cast<const double*>(w + L.dx);
+  k.pif = reinterpret_cast<const int32_t*>(w + L.pif);
+  k.pcell = reinterpret_cast<const int32_t*>(w + L.pcell);
   for (int p = 1; p <= BATCH_PMAX; ++p) {
     k.waves[p] = bt->launch && bt->launch[2 * (p - 1)] > 0 ? bt->launch[2 * (p - 1)] : 4;
     k.per_cu[p] = bt->launch ? bt->launch[2 * (p - 1) + 1] : 0;
@@ -455,6 +459,13 @@ acat_status acat_batch_init(const acat_batch* batch, void* workspace, size_t wor
   put(L.P, P.data(), sizeof(int32_t) * np);
   put(L.bc, bc.data(), sizeof(int32_t) * np);
   put(L.dx, batch->dx, sizeof(double) * np);
+  // problem of every interface and of every cell (the layout is fixed for the batch)
+  int32_t* pif = reinterpret_cast<int32_t*>(host.data() + (L.pif - L.coff));
+  int32_t* pcell = reinterpret_cast<int32_t*>(host.data() + (L.pcell - L.coff));
+  for (int b = 0; b < np; ++b) {
+    for (int64_t k = ioffs[b]; k < ioffs[b + 1]; ++k) pif[k] = b;
+    for (int64_t e = coff[b]; e < coff[b + 1]; ++e) pcell[e] = b;
+  }
   char* w = static_cast<char*>(workspace);
   if (hipMemcpy(w + L.coff, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) return ACAT_ERR_DEVICE;
   return ACAT_OK;

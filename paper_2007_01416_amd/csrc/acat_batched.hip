@@ -19,17 +19,6 @@ namespace acat {
 
 namespace {
 
-// largest b with off[b] <= x (off nondecreasing, off[0] = 0 <= x)
-__device__ __forceinline__ int find_seg(const int64_t* off, int n, int64_t x) {
-  int a = 0, b = n;
-  while (b - a > 1) {
-    const int m = (a + b) >> 1;
-    if (off[m] <= x) a = m;
-    else b = m;
-  }
-  return a;
-}
-
 constexpr int GW = BATCH_PMAX;   // indicator window half-width for every problem (offsets -3 .. 4)
 
 template <int FLUX, int NV>
@@ -38,7 +27,7 @@ __global__ __launch_bounds__(BLOCK) void k_classify_b(KBatch bt, KBStep st) {
   const bool valid = kg < bt.nif;
   int ps = 1;
   if (valid) {
-    const int b = find_seg(bt.ioffs, bt.nprob, kg);
+    const int b = bt.pif[kg];
     const int n = bt.N[b], bc = bt.bc[b];
     const int i = (int)(kg - bt.ioffs[b]) - (bc == PERIODIC ? 0 : 1);
     const double* ub = st.u + bt.coff[b];
@@ -95,7 +84,7 @@ __global__ __launch_bounds__(BS) void k_flux_b(KBatch bt, KBStep st) {
   for (int64_t base = sl.lo; base < sl.hi; base += GPB) {
     const bool valid = inblk && base + g < sl.hi;
     const int64_t kg = valid ? sl.items[base + g] : 0;
-    const int b = find_seg(bt.ioffs, bt.nprob, kg);
+    const int b = bt.pif[kg];
     const int n = bt.N[b], bc = bt.bc[b];
     const int i = (int)(kg - bt.ioffs[b]) - (bc == PERIODIC ? 0 : 1);
     const double* ub = st.u + bt.coff[b];
@@ -204,7 +193,7 @@ template <int FLUX, int NV>
 __global__ __launch_bounds__(BLOCK) void k_update_b(KBatch bt, KBStep st) {
   const int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (e >= bt.ncell) return;
-  const int b = find_seg(bt.coff, bt.nprob, e);
+  const int b = bt.pcell[e];
   const int n = bt.N[b], bc = bt.bc[b];
   const int i = (int)(e - bt.coff[b]);
   const double lam = st.dt[b] / bt.dx[b];

@@ -106,6 +106,8 @@ struct KBatch {
   const int32_t* P;         // [nprob] largest half-width
   const int32_t* bc;        // [nprob] boundary
   const double* dx;         // [nprob]
+  const int32_t* pif;       // [nif] problem of each interface
+  const int32_t* pcell;     // [ncell] problem of each cell
   int waves[BATCH_PMAX + 1];    // per order class p: waves per block of the flux kernel (1, 2 or 4)
   int per_cu[BATCH_PMAX + 1];   // per order class p: persistent blocks per CU (0: occupancy limit)
 };
