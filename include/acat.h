@@ -144,7 +144,8 @@ acat_status acat_step_replay(const acat_problem* prob, const double* u_in, doubl
  * u_out = S(u_in) the map of acat_step_replay for the same `dec` and time
  * step, ubar_in = (dS/du_in)^T ubar_out: the conservative update's
  * transpose gives the interface flux adjoints Fbar = lambda (ubar_{i+1} -
- * ubar_i), and each interface (1D) or corner (2D) recomputes its Taylor
+ * ubar_i) (a transmissive edge flux enters one cell only: the missing
+ * term is dropped), and each interface (1D) or corner (2D) recomputes its Taylor
  * recursion (Sec. 2.2; Sec. 4) and runs it backwards, with the analytic
  * flux Jacobians and the transposed centred-difference and time-
  * extrapolation weights; the FL-CAT2 blend (Sec. 3.1) is differentiated at
@@ -154,8 +155,10 @@ acat_status acat_step_replay(const acat_problem* prob, const double* u_in, doubl
  *     the forward step's input state; dt / dt_dev as in acat_step.
  *   - ubar_out, ubar_in: state-shaped adjoints; ubar_in may equal ubar_out
  *     (in place) but may not partially overlap it or overlap u_in.
- *   - 1D: every flux and boundary, P <= 4; 2D: periodic only, P <= 3
- *     (else ACAT_ERR_UNSUPPORTED).  Recorded orders outside 1..P are taken as 1
+ *   - 1D: P <= 4; 2D: P <= 3; every flux and both boundaries (the
+ *     transposed clamp adds the contributions of ghost reads to the edge
+ *     cells); the HLL variant is not differentiated (else
+ *     ACAT_ERR_UNSUPPORTED).  Recorded orders outside 1..P are taken as 1
  *     and set ACAT_DEV_BAD_ORDER.
  * --------------------------------------------------------------------- */
 acat_status acat_adjoint_workspace_size(const acat_problem* prob, size_t* bytes /* host */);

@@ -461,9 +461,16 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
     double u[NV];
 #pragma unroll
     for (int c = 0; c < NV; ++c) u[c] = valid ? st.u[c * plane + (int64_t)y * nx + x] : 1.0;
-    // Fbar = lamx (ubar_{i+e1} - ubar_i), Gbar = lamy (ubar_{i+e2} - ubar_i)
+    // Fbar = lamx (ubar_{i+e1} - ubar_i), Gbar = lamy (ubar_{i+e2} - ubar_i), the
+    // terms of cells outside a transmissive grid dropped (an edge flux enters
+    // one cell only); corners on the ghost row carry no x-flux, those on the
+    // ghost column no y-flux
+    const bool per = pb.bc == PERIODIC;
+    const bool hasF = valid && i2 >= 0, hasG = valid && i1 >= 0;
     double Fb[NV], Gb[NV];
     {
+      const bool in1 = per || i1 >= 0, inr1 = per || i1 + 1 < nx32;
+      const bool in2 = per || i2 >= 0, inr2 = per || i2 + 1 < ny32;
       const int x0 = bc_index32(i1, nx32, pb.bc), y0 = bc_index32(i2, ny32, pb.bc);
       const int xr = bc_index32(i1 + 1, nx32, pb.bc), yr = bc_index32(i2 + 1, ny32, pb.bc);
 #pragma unroll
@@ -471,18 +478,18 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
         const double u0 = valid ? ubo[c * plane + (int64_t)y0 * nx + x0] : 0.0;
         const double ux = valid ? ubo[c * plane + (int64_t)y0 * nx + xr] : 0.0;
         const double uy = valid ? ubo[c * plane + (int64_t)yr * nx + x0] : 0.0;
-        Fb[c] = lamx * (ux - u0);
-        Gb[c] = lamy * (uy - u0);
+        Fb[c] = hasF ? lamx * ((inr1 ? ux : 0.0) - (in1 ? u0 : 0.0)) : 0.0;
+        Gb[c] = hasG ? lamy * ((inr2 ? uy : 0.0) - (in2 ? u0 : 0.0)) : 0.0;
       }
     }
     double psix = 1.0, alx = 0.0, psiy = 1.0, aly = 0.0;
     if (valid) {
-      if (Q1 == 1) {
+      if (Q1 == 1 && hasF) {
         const int64_t ex = (int64_t)i2 * pb.nIx + (i1 - ioff);
         psix = st.psix[ex];
         alx = st.alx[ex];
       }
-      if (Q2 == 1) {
+      if (Q2 == 1 && hasG) {
         const int64_t ey = (int64_t)(i2 - ioff) * nx + i1;
         psiy = st.psiy[ey];
         aly = st.aly[ey];
@@ -541,31 +548,57 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
   }
 }
 
-// periodic 2D gather: cell m collects node (j1, j2) of corner m - j for every
-// j in [-P+1, P]^2 inside that corner's rectangle (j2 outer, j1 inner).
+// Corners k whose node at offset j reads cell m along one direction of n
+// cells: k = m - j (wrapped when periodic); with the transmissive clamp, an
+// edge cell is also read by every corner whose node lies beyond it
+// (k + j <= 0 for m = 0, k + j >= n - 1 for m = n - 1); corners run over
+// [-1, n - 1] there.
+__device__ __forceinline__ void corners_reading(int m, int j, int n, bool per, int& lo, int& hi) {
+  lo = hi = m - j;
+  if (per) return;
+  if (m == 0) lo = -1;
+  if (m == n - 1) hi = n - 1;
+  lo = lo < -1 ? -1 : lo;
+  hi = hi > n - 1 ? n - 1 : hi;
+}
+
+// 2D gather: cell m collects node (j1, j2) of every corner whose rectangle
+// holds that node and whose node reads cell m (j2, corner row, j1, corner
+// column: one fixed order).
 template <int NV>
 __global__ __launch_bounds__(BLOCK) void k_gather2d(KProb pb, KStep st, const double* __restrict__ ubo,
                                                     const double* __restrict__ C, int LMAX, double* ubi) {
   const int64_t m = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  const int nx = (int)pb.nx, ny = (int)pb.ny, P = pb.P;
+  const int nx = (int)pb.nx, ny = (int)pb.ny, P = pb.P, ioff = (int)pb.ioff;
   if (m >= (int64_t)nx * ny) return;
+  const bool per = pb.bc == PERIODIC;
   const int m1 = (int)(m % nx), m2 = (int)(m / nx);
   const int64_t plane = (int64_t)nx * ny;
-  const int64_t cstride = pb.n1 * pb.n2 * LMAX;
+  const int64_t nitems = pb.n1 * pb.n2;
+  const int64_t cstride = nitems * LMAX;
   double acc[NV];
 #pragma unroll
   for (int c = 0; c < NV; ++c) acc[c] = ubo[c * plane + m];
   for (int j2 = -P + 1; j2 <= P; ++j2) {
-    const int k2 = bc_index32(m2 - j2, ny, PERIODIC);
-    for (int j1 = -P + 1; j1 <= P; ++j1) {
-      const int k1 = bc_index32(m1 - j1, nx, PERIODIC);
-      const int64_t e = (int64_t)k2 * nx + k1;
-      const int cl = st.cls[e];
-      const int q1 = cl / P + 1, q2 = cl % P + 1;
-      if (j1 < -q1 + 1 || j1 > q1 || j2 < -q2 + 1 || j2 > q2) continue;
-      const int64_t slot = (int64_t)(j2 + P - 1) * (2 * P) + (j1 + P - 1);
+    int lo2, hi2;
+    corners_reading(m2, j2, ny, per, lo2, hi2);
+    for (int k2 = lo2; k2 <= hi2; ++k2) {
+      const int r2 = per ? bc_index32(k2, ny, PERIODIC) : k2;
+      for (int j1 = -P + 1; j1 <= P; ++j1) {
+        int lo1, hi1;
+        corners_reading(m1, j1, nx, per, lo1, hi1);
+        for (int k1 = lo1; k1 <= hi1; ++k1) {
+          const int r1 = per ? bc_index32(k1, nx, PERIODIC) : k1;
+          const int64_t e = (int64_t)(r2 - ioff) * pb.n1 + (r1 - ioff);
+          const int cl = st.cls[e];
+          if (cl < 0) continue;
+          const int q1 = cl / P + 1, q2 = cl % P + 1;
+          if (j1 < -q1 + 1 || j1 > q1 || j2 < -q2 + 1 || j2 > q2) continue;
+          const int64_t slot = (int64_t)(j2 + P - 1) * (2 * P) + (j1 + P - 1);
 #pragma unroll
-      for (int c = 0; c < NV; ++c) acc[c] += C[c * cstride + slot * plane + e];
+          for (int c = 0; c < NV; ++c) acc[c] += C[c * cstride + slot * nitems + e];
+        }
+      }
     }
   }
 #pragma unroll

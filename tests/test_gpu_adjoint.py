@@ -110,6 +110,41 @@ def test_adjoint_2d_euler_matches_dense_oracle(acat, P):
     assert err <= TOL_DENSE * np.abs(want).max()
 
 
+@pytest.mark.parametrize("P", [1, 2, 3])
+def test_adjoint_2d_transmissive_matches_dense_oracle(acat, P):
+    """Transmissive 2D: the edge fluxes enter one cell each, ghost-row and
+    ghost-column corners carry one flux, and the clamped ghost reads add
+    their adjoints to the edge cells.  Non-square grid, every order class."""
+    nx, ny = 30, 27
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    rho = 1 + 0.2 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y) + 0.5 * ((X > 0.4) & (X < 0.7))
+    v, w = 0.3 + 0.1 * np.sin(2 * np.pi * Y), -0.2 + 0.1 * np.cos(2 * np.pi * X)
+    p = 1 + 0.1 * np.sin(2 * np.pi * (X + Y)) + 0.6 * (Y < 0.3)
+    u = np.stack([rho, rho * v, rho * w, p / 0.4 + 0.5 * rho * (v * v + w * w)])
+    po, pg = both_problems(2, 4, nx, "euler", P, "transmissive", 1.0 / nx, ny=ny, dy=1.0 / ny)
+    dt = oracle.dt_cfl(po, u, 0.4)
+    got, want, r = dense_case(acat, po, pg, u, dt, seed=40 + P)
+    # corner (i1, i2) takes the orders of x-interface (i1 + 1/2, i2) and y-interface (i1, i2 + 1/2)
+    corners = {(int(r["ordx"][i2, i1 + 1]), int(r["ordy"][i2 + 1, i1])) for i2 in range(ny) for i1 in range(nx)}
+    assert len(corners) == P * P, corners
+    err = np.abs(got - want).max()
+    print(f"2D euler transmissive P={P}: max err {err:.3e} (scale {np.abs(want).max():.3e})", flush=True)
+    assert err <= TOL_DENSE * np.abs(want).max()
+
+
+def test_adjoint_2d_transmissive_advection_lf(acat):
+    n = 14
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal((1, n, n + 3))
+    po, pg = both_problems(2, 1, n + 3, "advection", 2, "transmissive", 0.1, ny=n, dy=0.12, ax=0.8, ay=-0.5,
+                           flags=oracle.FLAG_FLO_LF)
+    dt = oracle.dt_cfl(po, u, 0.4)
+    got, want, _ = dense_case(acat, po, pg, u, dt, seed=9)
+    assert np.abs(got - want).max() <= TOL_DENSE * np.abs(want).max()
+
+
 def test_adjoint_2d_advection_matches_dense_oracle(acat):
     n = 16
     rng = np.random.default_rng(3)
