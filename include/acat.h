@@ -155,10 +155,9 @@ acat_status acat_step_replay(const acat_problem* prob, const double* u_in, doubl
  *     the forward step's input state; dt / dt_dev as in acat_step.
  *   - ubar_out, ubar_in: state-shaped adjoints; ubar_in may equal ubar_out
  *     (in place) but may not partially overlap it or overlap u_in.
- *   - 1D: P <= 4; 2D: P <= 3; every flux and both boundaries (the
- *     transposed clamp adds the contributions of ghost reads to the edge
- *     cells); the HLL variant is not differentiated (else
- *     ACAT_ERR_UNSUPPORTED).  Recorded orders outside 1..P are taken as 1
+ *   - Every order, flux and boundary of acat_step (the transposed clamp
+ *     adds the contributions of ghost reads to the edge cells); the HLL
+ *     variant is not differentiated (ACAT_ERR_UNSUPPORTED).  Recorded orders outside 1..P are taken as 1
  *     and set ACAT_DEV_BAD_ORDER.
  * --------------------------------------------------------------------- */
 acat_status acat_adjoint_workspace_size(const acat_problem* prob, size_t* bytes /* host */);

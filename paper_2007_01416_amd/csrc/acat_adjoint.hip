@@ -415,7 +415,9 @@ __device__ __forceinline__ void corner_adjoint(const Phys& ph, double lamx, doub
 // contribution buffer, slot-major: C[c][slot][e], slot = (j2 + P - 1) 2P + (j1 + P - 1)
 // for the node at offset (j1, j2) of corner e (a gather over one offset reads
 // consecutive corners)
-template <int FLUX, int NV, int Q1, int Q2>
+// PASSES (corners with q1 != q2): 1 = the F recursion only, 2 = the G recursion
+// only, added to the contributions the first launch wrote, 3 = both.
+template <int FLUX, int NV, int Q1, int Q2, int PASSES = 3>
 __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const double* __restrict__ ubo,
                                                  double* __restrict__ C, int LMAX) {
   constexpr int N1 = 2 * Q1, N2 = 2 * Q2, L = N1 * N2;
@@ -512,10 +514,12 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
       corner_adjoint<FLUX, NV, Q1, Q2, Q1>(pb.ph, lamx, lamy, u, f0, g0, gx, gy, xs[0], xs[1], STRIDE, buf, slot,
                                            g * L, a1, a2, sfb, sgb, ub, f0b, g0b);
     } else {
-      corner_adjoint<FLUX, NV, Q1, Q2, Q1>(pb.ph, lamx, lamy, u, f0, g0, gx, gy, xs[0], xs[1], STRIDE, buf, slot,
-                                           g * L, a1, a2, sfb, zero, ub, f0b, g0b);
-      corner_adjoint<FLUX, NV, Q1, Q2, Q2>(pb.ph, lamx, lamy, u, f0, g0, gx, gy, xs[0], xs[1], STRIDE, buf, slot,
-                                           g * L, a1, a2, zero, sgb, ub, f0b, g0b);
+      if constexpr ((PASSES & 1) != 0)
+        corner_adjoint<FLUX, NV, Q1, Q2, Q1>(pb.ph, lamx, lamy, u, f0, g0, gx, gy, xs[0], xs[1], STRIDE, buf, slot,
+                                             g * L, a1, a2, sfb, zero, ub, f0b, g0b);
+      if constexpr ((PASSES & 2) != 0)
+        corner_adjoint<FLUX, NV, Q1, Q2, Q2>(pb.ph, lamx, lamy, u, f0, g0, gx, gy, xs[0], xs[1], STRIDE, buf, slot,
+                                             g * L, a1, a2, zero, sgb, ub, f0b, g0b);
     }
     // first-order parts (Rusanov or Lax-Friedrichs) of the FL-CAT2 blends, on
     // the two nodes each one reads
@@ -523,7 +527,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
       alx = pb.dx / ((double)pb.dim * dt);
       aly = pb.dy / ((double)pb.dim * dt);
     }
-    if (Q1 == 1 && on_row && (a1 == Q1 - 1 || a1 == Q1)) {
+    if ((PASSES & 1) != 0 && Q1 == 1 && on_row && (a1 == Q1 - 1 || a1 == Q1)) {
 #pragma unroll
       for (int c = 0; c < NV; ++c) {
         const double lb = 0.5 * (1.0 - psix) * Fb[c];
@@ -531,7 +535,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
         ub[c] += (a1 == Q1 - 1 ? alx : -alx) * lb;
       }
     }
-    if (Q2 == 1 && on_col && (a2 == Q2 - 1 || a2 == Q2)) {
+    if ((PASSES & 2) != 0 && Q2 == 1 && on_col && (a2 == Q2 - 1 || a2 == Q2)) {
 #pragma unroll
       for (int c = 0; c < NV; ++c) {
         const double lb = 0.5 * (1.0 - psiy) * Gb[c];
@@ -543,7 +547,10 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
     const int cslot = (a2 - Q2 + pb.P) * (2 * pb.P) + (a1 - Q1 + pb.P);
     if (valid) {
 #pragma unroll
-      for (int c = 0; c < NV; ++c) C[c * cstride + (int64_t)cslot * nitems + e] = ub[c];
+      for (int c = 0; c < NV; ++c) {
+        double* dst = C + c * cstride + (int64_t)cslot * nitems + e;
+        *dst = PASSES == 2 ? *dst + ub[c] : ub[c];
+      }
     }
   }
 }
@@ -614,7 +621,8 @@ __global__ __launch_bounds__(BLOCK) void k_gather2d(KProb pb, KStep st, const do
 template <int FLUX, int NV, int P, int p>
 hipError_t launch_adj1d(const KProb& pb, const KStep& st, const double* ubo, double* C, hipStream_t s) {
   if constexpr (p <= P) {
-    static const char* names[5] = {"", "adjoint1d_p1", "adjoint1d_p2", "adjoint1d_p3", "adjoint1d_p4"};
+    static const char* names[7] = {"", "adjoint1d_p1", "adjoint1d_p2", "adjoint1d_p3", "adjoint1d_p4",
+                                   "adjoint1d_p5", "adjoint1d_p6"};
     auto kern = k_adj1d<FLUX, NV, p>;
     const int grid = persistent_grid(kern, pb.nIx, 0);
     {
@@ -633,6 +641,8 @@ hipError_t adj1d_impl(const KProb& pb, const KStep& st, const double* ubo, doubl
   if ((e = launch_adj1d<FLUX, NV, P, 2>(pb, st, ubo, C, s)) != hipSuccess) return e;
   if ((e = launch_adj1d<FLUX, NV, P, 3>(pb, st, ubo, C, s)) != hipSuccess) return e;
   if ((e = launch_adj1d<FLUX, NV, P, 4>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj1d<FLUX, NV, P, 5>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj1d<FLUX, NV, P, 6>(pb, st, ubo, C, s)) != hipSuccess) return e;
   {
     ProfScope ps("gather1d", s);
     k_gather1d<NV><<<(unsigned)((pb.nx + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st, ubo, C, 2 * P, ubi);
@@ -644,13 +654,23 @@ hipError_t adj1d_impl(const KProb& pb, const KStep& st, const double* ubo, doubl
 template <int FLUX, int NV, int P, int Q1, int Q2>
 hipError_t launch_adj2d(const KProb& pb, const KStep& st, const double* ubo, double* C, hipStream_t s) {
   if constexpr (Q1 <= P && Q2 <= P) {
-    static const char* names[4][4] = {{"", "", "", ""},
-                                      {"", "adjoint2d_q11", "adjoint2d_q12", "adjoint2d_q13"},
-                                      {"", "adjoint2d_q21", "adjoint2d_q22", "adjoint2d_q23"},
-                                      {"", "adjoint2d_q31", "adjoint2d_q32", "adjoint2d_q33"}};
-    auto kern = k_adj2d<FLUX, NV, Q1, Q2>;
-    const int grid = persistent_grid(kern, pb.n1 * pb.n2, 0);
-    {
+    static const char* names[5][5] = {{"", "", "", "", ""},
+                                      {"", "adjoint2d_q11", "adjoint2d_q12", "adjoint2d_q13", "adjoint2d_q14"},
+                                      {"", "adjoint2d_q21", "adjoint2d_q22", "adjoint2d_q23", "adjoint2d_q24"},
+                                      {"", "adjoint2d_q31", "adjoint2d_q32", "adjoint2d_q33", "adjoint2d_q34"},
+                                      {"", "adjoint2d_q41", "adjoint2d_q42", "adjoint2d_q43", "adjoint2d_q44"}};
+    // the rectangles with two recursions of orders 6 and 8 run them in two
+    // launches (one recursion each, in order on the stream)
+    constexpr bool SPLIT = Q1 != Q2 && Q1 >= 3 && Q2 >= 3;
+    if constexpr (SPLIT) {
+      auto k1 = k_adj2d<FLUX, NV, Q1, Q2, 1>;
+      auto k2 = k_adj2d<FLUX, NV, Q1, Q2, 2>;
+      ProfScope ps(names[Q1][Q2], s);
+      k1<<<persistent_grid(k1, pb.n1 * pb.n2, 0), BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P);
+      k2<<<persistent_grid(k2, pb.n1 * pb.n2, 0), BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P);
+    } else {
+      auto kern = k_adj2d<FLUX, NV, Q1, Q2>;
+      const int grid = persistent_grid(kern, pb.n1 * pb.n2, 0);
       ProfScope ps(names[Q1][Q2], s);
       kern<<<grid, BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P);
     }
@@ -671,6 +691,13 @@ hipError_t adj2d_impl(const KProb& pb, const KStep& st, const double* ubo, doubl
   if ((e = launch_adj2d<FLUX, NV, P, 2, 3>(pb, st, ubo, C, s)) != hipSuccess) return e;
   if ((e = launch_adj2d<FLUX, NV, P, 3, 2>(pb, st, ubo, C, s)) != hipSuccess) return e;
   if ((e = launch_adj2d<FLUX, NV, P, 3, 3>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj2d<FLUX, NV, P, 1, 4>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj2d<FLUX, NV, P, 4, 1>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj2d<FLUX, NV, P, 2, 4>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj2d<FLUX, NV, P, 4, 2>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj2d<FLUX, NV, P, 3, 4>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj2d<FLUX, NV, P, 4, 3>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adj2d<FLUX, NV, P, 4, 4>(pb, st, ubo, C, s)) != hipSuccess) return e;
   {
     ProfScope ps("gather2d", s);
     k_gather2d<NV><<<(unsigned)((pb.nx * pb.ny + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P,
@@ -691,6 +718,8 @@ hipError_t launch_adjoint(const KProb& pb, const KStep& st, const double* ubo, d
         case 2: return adj1d_impl<EUL, 3, 2>(pb, st, ubo, ubi, C, s);
         case 3: return adj1d_impl<EUL, 3, 3>(pb, st, ubo, ubi, C, s);
         case 4: return adj1d_impl<EUL, 3, 4>(pb, st, ubo, ubi, C, s);
+        case 5: return adj1d_impl<EUL, 3, 5>(pb, st, ubo, ubi, C, s);
+        case 6: return adj1d_impl<EUL, 3, 6>(pb, st, ubo, ubi, C, s);
       }
     } else if (pb.flux == BURG) {
       switch (pb.P) {
@@ -698,6 +727,8 @@ hipError_t launch_adjoint(const KProb& pb, const KStep& st, const double* ubo, d
         case 2: return adj1d_impl<BURG, 1, 2>(pb, st, ubo, ubi, C, s);
         case 3: return adj1d_impl<BURG, 1, 3>(pb, st, ubo, ubi, C, s);
         case 4: return adj1d_impl<BURG, 1, 4>(pb, st, ubo, ubi, C, s);
+        case 5: return adj1d_impl<BURG, 1, 5>(pb, st, ubo, ubi, C, s);
+        case 6: return adj1d_impl<BURG, 1, 6>(pb, st, ubo, ubi, C, s);
       }
     } else {
       switch (pb.P) {
@@ -705,6 +736,8 @@ hipError_t launch_adjoint(const KProb& pb, const KStep& st, const double* ubo, d
         case 2: return adj1d_impl<ADV, 1, 2>(pb, st, ubo, ubi, C, s);
         case 3: return adj1d_impl<ADV, 1, 3>(pb, st, ubo, ubi, C, s);
         case 4: return adj1d_impl<ADV, 1, 4>(pb, st, ubo, ubi, C, s);
+        case 5: return adj1d_impl<ADV, 1, 5>(pb, st, ubo, ubi, C, s);
+        case 6: return adj1d_impl<ADV, 1, 6>(pb, st, ubo, ubi, C, s);
       }
     }
   } else {
@@ -713,12 +746,14 @@ hipError_t launch_adjoint(const KProb& pb, const KStep& st, const double* ubo, d
         case 1: return adj2d_impl<EUL, 4, 1>(pb, st, ubo, ubi, C, s);
         case 2: return adj2d_impl<EUL, 4, 2>(pb, st, ubo, ubi, C, s);
         case 3: return adj2d_impl<EUL, 4, 3>(pb, st, ubo, ubi, C, s);
+        case 4: return adj2d_impl<EUL, 4, 4>(pb, st, ubo, ubi, C, s);
       }
     } else {
       switch (pb.P) {
         case 1: return adj2d_impl<ADV, 1, 1>(pb, st, ubo, ubi, C, s);
         case 2: return adj2d_impl<ADV, 1, 2>(pb, st, ubo, ubi, C, s);
         case 3: return adj2d_impl<ADV, 1, 3>(pb, st, ubo, ubi, C, s);
+        case 4: return adj2d_impl<ADV, 1, 4>(pb, st, ubo, ubi, C, s);
       }
     }
   }

@@ -223,7 +223,6 @@ acat_status check_adjoint(const acat_problem* prob) {
   acat_status rc = check_problem(prob);
   if (rc != ACAT_OK) return rc;
   if (prob->flags & ACAT_FLAG_FLO_HLL) return ACAT_ERR_UNSUPPORTED;
-  if (prob->P > (prob->dim == 1 ? 4 : 3)) return ACAT_ERR_UNSUPPORTED;   // adjoint kernels up to P = 4 (1D), 3 (2D)
   return ACAT_OK;
 }
 

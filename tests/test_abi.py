@@ -170,14 +170,14 @@ def test_adjoint_argument_errors_before_launch(lib):
     assert lib.acat_adjoint_workspace_size(ctypes.byref(pc), ctypes.byref(n)) == 0
     # the contribution buffer dominates: nvar * interfaces * 2P doubles
     assert n.value >= 8 * 3 * 64 * 4
-    # 2D transmissive has an adjoint; 2D P = 4 and the HLL variant have none
-    p2 = _prob(dim=2, nvar=4, ny=32, dy=0.1, bc="transmissive", P=3)
+    # every order and boundary of the forward step has an adjoint; the HLL variant has none
+    p2 = _prob(dim=2, nvar=4, ny=32, dy=0.1, bc="transmissive", P=4)
     assert lib.acat_adjoint_workspace_size(ctypes.byref(p2.c()), ctypes.byref(n)) == 0
-    p3 = _prob(dim=2, nvar=4, ny=32, dy=0.1, P=4)
-    assert lib.acat_adjoint_workspace_size(ctypes.byref(p3.c()), ctypes.byref(n)) == -4
+    assert lib.acat_adjoint_workspace_size(ctypes.byref(_prob(P=6, bc="transmissive").c()), ctypes.byref(n)) == 0
     assert lib.acat_adjoint_workspace_size(ctypes.byref(_prob(flags=2).c()), ctypes.byref(n)) == -4
     assert lib.acat_adjoint_workspace_size(ctypes.byref(_prob(P=7).c()), ctypes.byref(n)) == -2
-    assert lib.acat_adjoint_workspace_size(ctypes.byref(_prob(P=5).c()), ctypes.byref(n)) == -4
+    p5 = _prob(dim=2, nvar=4, ny=32, dy=0.1, P=5)
+    assert lib.acat_adjoint_workspace_size(ctypes.byref(p5.c()), ctypes.byref(n)) == -4
     ub = (ctypes.c_double * (3 * 64))()
     ub2 = (ctypes.c_double * (3 * 64))()
     u = (ctypes.c_double * (3 * 64))()

@@ -70,7 +70,7 @@ def orders_seen(po, r):
     return set(zip(r["ordx"].ravel().tolist(), r["ordy"].ravel().tolist()))
 
 
-@pytest.mark.parametrize("P", [2, 3, 4])
+@pytest.mark.parametrize("P", [2, 3, 4, 5, 6])
 @pytest.mark.parametrize("bc", ["periodic", "transmissive"])
 def test_adjoint_1d_euler_matches_dense_oracle(acat, P, bc):
     w = workloads.euler_1d(n=32, P=P)
@@ -96,7 +96,7 @@ def test_adjoint_1d_scalar_matches_dense_oracle(acat, flux, P, bc):
     assert np.abs(got - want).max() <= TOL_DENSE * np.abs(want).max()
 
 
-@pytest.mark.parametrize("P", [2, 3])
+@pytest.mark.parametrize("P", [2, 3, 4])
 def test_adjoint_2d_euler_matches_dense_oracle(acat, P):
     n = 24
     u = smooth_2d(n)
@@ -110,7 +110,7 @@ def test_adjoint_2d_euler_matches_dense_oracle(acat, P):
     assert err <= TOL_DENSE * np.abs(want).max()
 
 
-@pytest.mark.parametrize("P", [1, 2, 3])
+@pytest.mark.parametrize("P", [1, 2, 3, 4])
 def test_adjoint_2d_transmissive_matches_dense_oracle(acat, P):
     """Transmissive 2D: the edge fluxes enter one cell each, ghost-row and
     ghost-column corners carry one flux, and the clamped ghost reads add
@@ -295,3 +295,35 @@ def test_graph_captured_segments_match_eager(acat):
         assert torch.equal(uT, uT2) and torch.equal(g, g2)
         res.append((uT, g))
     assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
+
+
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+@pytest.mark.parametrize("q1,q2", [(a, b) for a in range(1, 5) for b in range(1, 5)])
+def test_adjoint_every_corner_class_forced(acat, q1, q2, bc):
+    """Every 2D corner class of P = 4, forced through replay maps on smooth
+    data (psi^1 = 0.6 and alpha = 2 where an order is 1), on a non-square
+    grid with both boundaries: the GPU adjoint against the oracle's dense
+    adjoint of the same frozen step."""
+    nx, ny = 10, 9
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    rho = 1 + 0.1 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)
+    v, w = 0.3 + 0.05 * np.sin(2 * np.pi * Y), -0.2 + 0.05 * np.cos(2 * np.pi * X)
+    p = 1 + 0.05 * np.sin(2 * np.pi * (X + Y))
+    u = np.stack([rho, rho * v, rho * w, p / 0.4 + 0.5 * rho * (v * v + w * w)])
+    po, pg = both_problems(2, 4, nx, "euler", 4, bc, 1.0 / nx, ny=ny, dy=1.0 / ny)
+    nIx, nIy = po.n_interfaces
+    r = dict(ordx=np.full((ny, nIx), q1, np.int8), ordy=np.full((nIy, nx), q2, np.int8),
+             psix=np.full((ny, nIx), 0.6), psiy=np.full((nIy, nx), 0.6),
+             alx=np.full((ny, nIx), 2.0), aly=np.full((nIy, nx), 2.0))
+    maps = (r["ordx"], r["ordy"], r["psix"], r["psiy"], r["alx"], r["aly"])
+    dt = 0.2 * oracle.dt_cfl(po, u, 0.4)
+    ub = np.random.default_rng(10 * q1 + q2).standard_normal(u.shape)
+    want = oracle.vjp_dense(po, u, ub, dt, maps)
+    dec = gpu_decisions(acat, pg, po, r)
+    got = acat.step_adjoint(pg, torch.from_numpy(u).cuda(), dt, dec, torch.from_numpy(ub).cuda()).cpu().numpy()
+    bad = np.argwhere(~np.isfinite(got))
+    err = np.abs(got - want).max()
+    print(f"class ({q1},{q2}) {bc}: max err {err:.3e}, non-finite {len(bad)} first {bad[:3].tolist()}", flush=True)
+    assert np.all(np.isfinite(got)) and err <= TOL_DENSE * np.abs(want).max()
