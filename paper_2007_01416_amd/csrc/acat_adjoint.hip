@@ -572,13 +572,13 @@ __device__ __forceinline__ void corners_reading(int m, int j, int n, bool per, i
 // 2D gather: cell m collects node (j1, j2) of every corner whose rectangle
 // holds that node and whose node reads cell m (j2, corner row, j1, corner
 // column: one fixed order).
-template <int NV>
+template <int NV, bool PER>
 __global__ __launch_bounds__(BLOCK) void k_gather2d(KProb pb, KStep st, const double* __restrict__ ubo,
                                                     const double* __restrict__ C, int LMAX, double* ubi) {
   const int64_t m = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int nx = (int)pb.nx, ny = (int)pb.ny, P = pb.P, ioff = (int)pb.ioff;
   if (m >= (int64_t)nx * ny) return;
-  const bool per = pb.bc == PERIODIC;
+  constexpr bool per = PER;
   const int m1 = (int)(m % nx), m2 = (int)(m / nx);
   const int64_t plane = (int64_t)nx * ny;
   const int64_t nitems = pb.n1 * pb.n2;
@@ -700,8 +700,9 @@ hipError_t adj2d_impl(const KProb& pb, const KStep& st, const double* ubo, doubl
   if ((e = launch_adj2d<FLUX, NV, P, 4, 4>(pb, st, ubo, C, s)) != hipSuccess) return e;
   {
     ProfScope ps("gather2d", s);
-    k_gather2d<NV><<<(unsigned)((pb.nx * pb.ny + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P,
-                                                                                       ubi);
+    const unsigned gb = (unsigned)((pb.nx * pb.ny + BLOCK - 1) / BLOCK);
+    if (pb.bc == PERIODIC) k_gather2d<NV, true><<<gb, BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P, ubi);
+    else k_gather2d<NV, false><<<gb, BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P, ubi);
   }
   ACAT_CHECK_LAUNCH();
   return hipSuccess;
