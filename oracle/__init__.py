@@ -27,7 +27,7 @@ FLUX_ADVECTION, FLUX_BURGERS, FLUX_EULER = 0, 1, 2
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
 # variants (Problem.flags): first-order flux Lax-Friedrichs / HLL instead of
 # Rusanov, modified p = 2 indicator, Roe-speed upwind psi^1 (scalar laws)
-FLAG_FLO_LF, FLAG_FLO_HLL, FLAG_PSI2_MODIFIED, FLAG_PSI1_ROE = 1, 2, 4, 8
+FLAG_FLO_LF, FLAG_FLO_HLL, FLAG_PSI2_MODIFIED, FLAG_PSI1_ROE, FLAG_SQUARE_2D = 1, 2, 4, 8, 16
 
 
 def build(force: bool = True) -> str:

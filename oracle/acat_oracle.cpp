@@ -35,6 +35,8 @@
 //     x-interface i+e1/2 and q2 the order of the y-interface i+e2/2 (Sec. 4,
 //     rectangular stencils); F is computed with Taylor order 2 q1 and time
 //     nodes J_{q1}, G with 2 q2 and J_{q2}; one recursion when q1 = q2.
+//     Variant FLAG_SQUARE_2D: F on the square J_{q1} x J_{q1}, G on
+//     J_{q2} x J_{q2} (the square algorithm of Sec. 4 per direction);
 //   * boundaries: periodic wrap or transmissive zeroth-order extrapolation.
 //   * rounding: the paper fixes none.  Sums run in the index order the paper
 //     writes them; the weighted sums of the recursion use fused multiply-add
@@ -341,7 +343,7 @@ int64_t bc_index(int64_t i, int64_t n, int bc) {
 // Rusanov (Sec. 5 lists LF and HLL as the first-order schemes), the p = 2
 // indicator is the modified one of Sec. 3.2, and for scalar laws psi^1 may
 // use the upwind ratio chosen by the sign of Roe's speed (Sec. 3.1).
-enum { FLAG_FLO_LF = 1, FLAG_FLO_HLL = 2, FLAG_PSI2_MODIFIED = 4, FLAG_PSI1_ROE = 8 };
+enum { FLAG_FLO_LF = 1, FLAG_FLO_HLL = 2, FLAG_PSI2_MODIFIED = 4, FLAG_PSI1_ROE = 8, FLAG_SQUARE_2D = 16 };
 
 // Modified p = 2 indicator (Sec. 3.2): two pairs of lateral weights, each
 // joining the central sub-interval to one side; the larger ratio.
@@ -759,16 +761,33 @@ struct Step2D {
     }
     return ps;
   }
+  // States of the stencil J_{s1} x J_{s2} around corner (i1, i2).
+  void gather(int64_t i1, int64_t i2, int s1, int s2, T (*us)[NMAX][VMAX]) const {
+    for (int j1 = -s1 + 1; j1 <= s1; ++j1)
+      for (int j2 = -s2 + 1; j2 <= s2; ++j2)
+        for (int c = 0; c < pb.nvar; ++c) us[j1 + s1 - 1][j2 + s2 - 1][c] = at(c, i1 + j1, i2 + j2);
+  }
   // Fluxes of corner (i1, i2).  q/psi/alpha for both directions are given.
+  // Default: both fluxes on the rectangle J_{q1} x J_{q2}.  FLAG_SQUARE_2D
+  // (q1 != q2): F on the square J_{q1} x J_{q1} and G on J_{q2} x J_{q2},
+  // each the square algorithm of Sec. 4 with its own half-width.
   void corner(int64_t i1, int64_t i2, int q1, int q2, double ps1x, double ps1y, double alx, double aly,
               double lamx, double lamy, T* F, T* G_) const {
     T us[NMAX][NMAX][VMAX];
-    for (int j1 = -q1 + 1; j1 <= q1; ++j1)
-      for (int j2 = -q2 + 1; j2 <= q2; ++j2)
-        for (int c = 0; c < pb.nvar; ++c) us[j1 + q1 - 1][j2 + q2 - 1][c] = at(c, i1 + j1, i2 + j2);
     if (q1 == q2) {
+      gather(i1, i2, q1, q2, us);
       cat_corner_2d(pb, q1, q2, q1, us, lamx, lamy, F, G_);
+    } else if (pb.flags & FLAG_SQUARE_2D) {
+      if (F) {
+        gather(i1, i2, q1, q1, us);
+        cat_corner_2d<T>(pb, q1, q1, q1, us, lamx, lamy, F, nullptr);
+      }
+      if (G_) {
+        gather(i1, i2, q2, q2, us);
+        cat_corner_2d<T>(pb, q2, q2, q2, us, lamx, lamy, nullptr, G_);
+      }
     } else {
+      gather(i1, i2, q1, q2, us);
       if (F) cat_corner_2d<T>(pb, q1, q2, q1, us, lamx, lamy, F, nullptr);
       if (G_) cat_corner_2d<T>(pb, q1, q2, q2, us, lamx, lamy, nullptr, G_);
     }
@@ -873,7 +892,8 @@ int check_problem(const oracle_problem* pb) {
   if (pb->flux == FLUX_BURGERS && (pb->nvar != 1 || pb->dim != 1)) return -2;
   if (pb->flux == FLUX_EULER && pb->nvar != (pb->dim == 1 ? 3 : 4)) return -2;
   if (pb->nx < 2 * std::max(pb->P, 2) || (pb->dim == 2 && pb->ny < 2 * std::max(pb->P, 2))) return -2;
-  if (pb->flags & ~(FLAG_FLO_LF | FLAG_FLO_HLL | FLAG_PSI2_MODIFIED | FLAG_PSI1_ROE)) return -2;
+  if (pb->flags & ~(FLAG_FLO_LF | FLAG_FLO_HLL | FLAG_PSI2_MODIFIED | FLAG_PSI1_ROE | FLAG_SQUARE_2D)) return -2;
+  if ((pb->flags & FLAG_SQUARE_2D) && pb->dim != 2) return -2;
   if ((pb->flags & FLAG_FLO_LF) && (pb->flags & FLAG_FLO_HLL)) return -2;
   if ((pb->flags & FLAG_PSI1_ROE) && pb->flux == FLUX_EULER) return -2;   // scalar laws only
   return 0;

@@ -208,8 +208,9 @@ def test_jvp_matches_central_difference_2d():
     assert np.abs((up - um) / (2 * h) - jv).max() < 1e-7 * np.abs(jv).max()
 
 
+@pytest.mark.parametrize("square", [False, True])
 @pytest.mark.parametrize("q1,q2", [(1, 2), (2, 1), (1, 3), (3, 1), (2, 3), (3, 2), (1, 4), (4, 2), (3, 4), (4, 3)])
-def test_rectangle_corners_linear_closed_form(q1, q2):
+def test_rectangle_corners_linear_closed_form(q1, q2, square):
     """Sec. 4 on the rectangle J_q1 x J_q2 with q1 != q2 (two recursions on one
     rectangle, time nodes J_q1 for F and J_q2 for G), linear advection.  The
     time-derivative formula on 2q points is exact on the Taylor predictions
@@ -219,31 +220,81 @@ def test_rectangle_corners_linear_closed_form(q1, q2):
     The fluxes are then F = a sum_{k=1}^{2 q1} 1/k! sum_l eta_l (M^{k-1} u)_(l,0)
     and G = b sum_{k=1}^{2 q2} 1/k! sum_l eta_l (M^{k-1} u)_(0,l): matrix powers
     in place of predictions, flux evaluations and time-derivative weights.
-    A direction of order 1 is taken with psi^1 = 1 (pure CAT2)."""
+    A direction of order 1 is taken with psi^1 = 1 (pure CAT2).  With the
+    square-stencil variant (FLAG_SQUARE_2D) F comes from the square
+    J_q1 x J_q1 and G from J_q2 x J_q2: the same closed form on those squares."""
     rng = np.random.default_rng(100 + 10 * q1 + q2)
     nx, ny = 19, 17
     a, b, dx, dy, dt = 0.7, -0.45, 0.1, 0.13, 0.02
     P = max(q1, q2)
     pb = prob2d(nx, ny, P, flux=ADV, dx=dx, dy=dy, ax=a, ay=b)
+    if square:
+        pb.flags = oracle.FLAG_SQUARE_2D
     u = rng.standard_normal((1, ny, nx))
     nIx, nIy = pb.n_interfaces
     maps = (np.full((ny, nIx), q1, np.int8), np.full((nIy, nx), q2, np.int8),
             np.ones((ny, nIx)), np.ones((nIy, nx)), np.ones((ny, nIx)), np.ones((nIy, nx)))
     r = oracle.step2d(pb, u, dt, maps=maps)
-    n1, n2 = 2 * q1, 2 * q2
-    c1, c2 = oracle.coeffs(q1), oracle.coeffs(q2)
-    Dx = np.kron(np.eye(n2), c1["g1"])          # node index a2 * n1 + a1
-    Dy = np.kron(c2["g1"], np.eye(n1))
-    M = -(dt / dx) * a * Dx - (dt / dy) * b * Dy
     fact = np.cumprod([1.0] + list(range(1, 2 * P + 1)))
+
+    def powers(i1, i2, s1, s2):
+        """M^k u on the stencil J_s1 x J_s2 around corner (i1, i2), k = 0..2P."""
+        n1, n2 = 2 * s1, 2 * s2
+        Dx = np.kron(np.eye(n2), oracle.coeffs(s1)["g1"])          # node index a2 * n1 + a1
+        Dy = np.kron(oracle.coeffs(s2)["g1"], np.eye(n1))
+        M = -(dt / dx) * a * Dx - (dt / dy) * b * Dy
+        rows = (i2 + np.arange(n2) - s2 + 1) % ny
+        cols = (i1 + np.arange(n1) - s1 + 1) % nx
+        U = [u[0][np.ix_(rows, cols)].ravel()]
+        for _ in range(2 * P):
+            U.append(M @ U[-1])
+        return U
+
+    c1, c2 = oracle.coeffs(q1), oracle.coeffs(q2)
     for i2 in range(0, ny, 3):
         for i1 in range(0, nx, 2):
-            rows = (i2 + np.arange(n2) - q2 + 1) % ny
-            cols = (i1 + np.arange(n1) - q1 + 1) % nx
-            U = [u[0][np.ix_(rows, cols)].ravel()]
-            for _ in range(2 * P):
-                U.append(M @ U[-1])
-            F = a * sum(c1["eta"] @ U[k - 1][(q2 - 1) * n1 + np.arange(n1)] / fact[k] for k in range(1, 2 * q1 + 1))
-            Gv = b * sum(c2["eta"] @ U[k - 1][np.arange(n2) * n1 + (q1 - 1)] / fact[k] for k in range(1, 2 * q2 + 1))
+            sF = (q1, q1) if square else (q1, q2)
+            sG = (q2, q2) if square else (q1, q2)
+            U = powers(i1, i2, *sF)
+            n1 = 2 * sF[0]
+            F = a * sum(c1["eta"] @ U[k - 1][(sF[1] - 1) * n1 + np.arange(n1)] / fact[k] for k in range(1, 2 * q1 + 1))
+            U = powers(i1, i2, *sG)
+            n1, n2 = 2 * sG[0], 2 * sG[1]
+            Gv = b * sum(c2["eta"] @ U[k - 1][np.arange(n2) * n1 + (sG[0] - 1)] / fact[k] for k in range(1, 2 * q2 + 1))
             assert abs(r["F"][0, i2, i1] - F) <= 1e-13 * max(1.0, abs(F)), (i1, i2, r["F"][0, i2, i1], F)
             assert abs(r["G"][0, i2, i1] - Gv) <= 1e-13 * max(1.0, abs(Gv)), (i1, i2, r["G"][0, i2, i1], Gv)
+
+
+@pytest.mark.parametrize("P", [2, 3, 4])
+def test_square_variant_equals_default_when_orders_agree(P):
+    """FLAG_SQUARE_2D changes only corners with q1 != q2: on data whose
+    corners all have q1 = q2 (forced) the two are identical, bit for bit;
+    on natural shocked data they differ exactly at the corners with
+    q1 != q2 (their fluxes) and agree elsewhere."""
+    rng = np.random.default_rng(30 + P)
+    n = 20
+    u = smooth_state(rng, n, n)
+    pb = prob2d(n, n, P)
+    ps = prob2d(n, n, P)
+    ps.flags = oracle.FLAG_SQUARE_2D
+    for q in range(1, P + 1):
+        m = maps_forced(pb, q)
+        a = oracle.step2d(pb, u, 1e-3, maps=m)
+        b = oracle.step2d(ps, u, 1e-3, maps=m)
+        assert np.array_equal(a["u"], b["u"])
+    dt = oracle.dt_cfl(pb, u, 0.4)
+    a = oracle.step2d(pb, u, dt)
+    b = oracle.step2d(ps, u, dt)
+    qx = a["ordx"]                     # periodic: corner (i1, i2) takes ordx[i2, i1] and ordy[i2, i1]
+    qy = a["ordy"]
+    differ = qx != qy
+    assert differ.any()
+    assert np.array_equal(a["F"][:, ~differ], b["F"][:, ~differ])
+    assert np.array_equal(a["G"][:, ~differ], b["G"][:, ~differ])
+    assert not np.array_equal(a["F"][:, differ], b["F"][:, differ])
+
+
+def test_square_variant_is_rejected_in_1d():
+    pb = oracle.Problem(dim=1, nvar=3, nx=16, flux=EUL, P=2, bc=0, dx=0.1, flags=oracle.FLAG_SQUARE_2D)
+    with pytest.raises(Exception):
+        oracle.step1d(pb, np.ones((3, 16)), 0.01)
