@@ -72,8 +72,15 @@ enum { ACAT_BC_PERIODIC = 0, ACAT_BC_TRANSMISSIVE = 1 };
  *     of a lateral sub-interval.
  *   PSI1_ROE: scalar laws only; psi^1 from the upwind ratio chosen by the
  *     sign of Roe's speed (Sec. 3.1) instead of the min form.
- * The batched step has no variants; acat_step_adjoint rejects FLO_HLL. */
-enum { ACAT_FLAG_FLO_LF = 1, ACAT_FLAG_FLO_HLL = 2, ACAT_FLAG_PSI2_MODIFIED = 4, ACAT_FLAG_PSI1_ROE = 8 };
+ *   SQUARE_2D: 2D only; a corner whose x- and y-interface orders differ
+ *     (q1 != q2) computes F on the square stencil J_q1 x J_q1 and G on
+ *     J_q2 x J_q2 (the square algorithm of Sec. 4 per direction) instead of
+ *     both on the rectangle J_q1 x J_q2 of the default method.  Grids of at
+ *     most 2^29 corners.
+ * The batched step has no variants; acat_step_adjoint rejects FLO_HLL and
+ * SQUARE_2D. */
+enum { ACAT_FLAG_FLO_LF = 1, ACAT_FLAG_FLO_HLL = 2, ACAT_FLAG_PSI2_MODIFIED = 4, ACAT_FLAG_PSI1_ROE = 8,
+       ACAT_FLAG_SQUARE_2D = 16 };
 
 /* Device status bits (acat_device_status): non-finite output state,
  * non-positive density or pressure (Euler), and (replay) a recorded order

@@ -25,7 +25,7 @@ DEV_NONFINITE, DEV_NONPHYSICAL = 1, 2
 
 
 # variants (Problem.flags), as ACAT_FLAG_* in acat.h
-FLAG_FLO_LF, FLAG_FLO_HLL, FLAG_PSI2_MODIFIED, FLAG_PSI1_ROE = 1, 2, 4, 8
+FLAG_FLO_LF, FLAG_FLO_HLL, FLAG_PSI2_MODIFIED, FLAG_PSI1_ROE, FLAG_SQUARE_2D = 1, 2, 4, 8, 16
 
 
 class AcatError(RuntimeError):

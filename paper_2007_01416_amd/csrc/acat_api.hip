@@ -18,8 +18,10 @@ inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 acat_status check_problem(const acat_problem* pb) {
   if (!pb) return ACAT_ERR_NULL;
   if (pb->dim != 1 && pb->dim != 2) return ACAT_ERR_ARG;
-  if (pb->flags & ~(ACAT_FLAG_FLO_LF | ACAT_FLAG_FLO_HLL | ACAT_FLAG_PSI2_MODIFIED | ACAT_FLAG_PSI1_ROE))
+  if (pb->flags & ~(ACAT_FLAG_FLO_LF | ACAT_FLAG_FLO_HLL | ACAT_FLAG_PSI2_MODIFIED | ACAT_FLAG_PSI1_ROE |
+                    ACAT_FLAG_SQUARE_2D))
     return ACAT_ERR_ARG;
+  if ((pb->flags & ACAT_FLAG_SQUARE_2D) && pb->dim != 2) return ACAT_ERR_ARG;
   if ((pb->flags & ACAT_FLAG_FLO_LF) && (pb->flags & ACAT_FLAG_FLO_HLL)) return ACAT_ERR_ARG;
   if ((pb->flags & ACAT_FLAG_PSI1_ROE) && pb->flux == ACAT_FLUX_EULER) return ACAT_ERR_UNSUPPORTED;
   if (pb->bc != ACAT_BC_PERIODIC && pb->bc != ACAT_BC_TRANSMISSIVE) return ACAT_ERR_ARG;
@@ -40,6 +42,8 @@ acat_status check_problem(const acat_problem* pb) {
   const int64_t cells = pb->nx * (pb->dim == 2 ? pb->ny : 1);
   const int64_t items = (pb->dim == 2) ? (pb->nx + 1) * (pb->ny + 1) : pb->nx + 1;
   if (cells * pb->nvar >= ((int64_t)1 << 40) || items >= ((int64_t)1 << 31) - 1) return ACAT_ERR_UNSUPPORTED;
+  // the square-stencil variant tags list entries in bits 29 and 30
+  if ((pb->flags & ACAT_FLAG_SQUARE_2D) && items >= ((int64_t)1 << LIST_TAG_SHIFT)) return ACAT_ERR_UNSUPPORTED;
   return ACAT_OK;
 }
 
@@ -105,7 +109,8 @@ Layout layout(const KProb& k) {
   L.cls = o;   o += align_up((size_t)L.nItems);
   L.hist = o;  o += align_up(sizeof(int32_t) * MAX_CLASSES * (size_t)cblocks);
   L.offs = o;  o += align_up(sizeof(int32_t) * MAX_CLASSES * (size_t)(cblocks + 1));
-  L.list = o;  o += align_up(sizeof(int32_t) * (size_t)L.nItems);
+  // a corner with q1 != q2 has two entries under the square-stencil variant
+  L.list = o;  o += align_up(sizeof(int32_t) * (size_t)L.nItems * ((k.flags & FLAG_SQUARE_2D) ? 2 : 1));
   L.part = o;  o += align_up(sizeof(double) * 2 * (size_t)cblocks);
   L.total = o;
   return L;
@@ -222,7 +227,7 @@ ALayout alayout(const KProb& k) {
 acat_status check_adjoint(const acat_problem* prob) {
   acat_status rc = check_problem(prob);
   if (rc != ACAT_OK) return rc;
-  if (prob->flags & ACAT_FLAG_FLO_HLL) return ACAT_ERR_UNSUPPORTED;
+  if (prob->flags & (ACAT_FLAG_FLO_HLL | ACAT_FLAG_SQUARE_2D)) return ACAT_ERR_UNSUPPORTED;
   return ACAT_OK;
 }
 

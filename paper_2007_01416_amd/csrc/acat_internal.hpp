@@ -34,6 +34,9 @@ struct KProb {
 // stencil cells stay in cache.
 constexpr int TILE_X = 16, TILE_Y = 16;
 static_assert(TILE_X * TILE_Y == BLOCK, "one classification thread per item of a tile");
+// List entries under the square-stencil variant: item | tag << LIST_TAG_SHIFT,
+// tag 1 = store F only, 2 = store G only, 0 = both.
+constexpr int LIST_TAG_SHIFT = 29;
 inline int64_t class_tiles(const KProb& k) {
   if (k.dim == 2) return ((k.n1 + TILE_X - 1) / TILE_X) * ((k.n2 + TILE_Y - 1) / TILE_Y);
   return (k.nIx + BLOCK - 1) / BLOCK;

@@ -356,8 +356,10 @@ __global__ __launch_bounds__(BLOCK) void k_classify2d(KProb pb, KStep st) {
   }
   const int cls = (q1 - 1) * P + (q2 - 1);
   if (inside) st.cls[e] = valid ? (int8_t)cls : (int8_t)-1;
+  // square-stencil variant: F in class (q1, q1), G in (q2, q2)
+  const bool split = (pb.flags & FLAG_SQUARE_2D) && q1 != q2;
   __shared__ int sh[MAX_CLASSES];
-  block_hist(sh, valid, cls, st.hist);
+  block_hist(sh, valid, split ? (q1 - 1) * P + (q1 - 1) : cls, st.hist, split ? (q2 - 1) * P + (q2 - 1) : -1);
   if (st.cfl_mode) {
     block_max2(sx, sy);
     if (threadIdx.x == 0) {
@@ -493,7 +495,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
   for (int64_t base = sl.lo; base < sl.hi; base += CPB) {
     {
       const bool valid = inblk && base + g < sl.hi;
-      const int32_t e = valid ? sl.items[base + g] : 0;
+      const int32_t raw = valid ? sl.items[base + g] : 0;
+      // square-stencil variant: entries carry which flux to store (1 F, 2 G, 0 both)
+      const bool tagged = (pb.flags & FLAG_SQUARE_2D) != 0;
+      const int32_t e = tagged ? (raw & ((1 << LIST_TAG_SHIFT) - 1)) : raw;
+      const int tag = tagged ? (raw >> LIST_TAG_SHIFT) : 0;
       const uint32_t eq = (uint32_t)e / n1u;
       const int i2 = (int)eq + ioff, i1 = (int)((uint32_t)e - eq * n1u) + ioff;
       const int x = bc_index32(i1 + (a1 - Q1 + 1), nx32, pb.bc);
@@ -547,7 +553,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
         if (!valid || task >= 2 * NV) continue;
         const bool isG = task >= NV;
         const int c = isG ? task - NV : task;
-        const bool need = isG ? (i1 >= 0) : (i2 >= 0);   // transmissive ghost corners need one flux only
+        // transmissive ghost corners need one flux only; tagged entries one flux each
+        const bool need = isG ? (i1 >= 0 && tag != 1) : (i2 >= 0 && tag != 2);
         if (!need) continue;
         double v = acc[tk];
         if ((!isG && Q1 == 1) || (isG && Q2 == 1)) {
@@ -763,7 +770,7 @@ hipError_t lists2d_impl(const KProb& pb, const KStep& st, hipStream_t s) {
     k_scan_hist<<<P * P + (st.cfl_mode ? 1 : 0), SCAN_T, 0, s>>>(st.hist, cblocks, st.offs, st.counts, P * P,
                                                                 cfl_reduce(pb, st, cblocks));
     k_scatter<P * P, true><<<cblocks, BLOCK, 0, s>>>(st.cls, 0, pb.n1, pb.n2, cblocks, st.offs, st.counts,
-                                                      st.list);
+                                                      st.list, (pb.flags & FLAG_SQUARE_2D) ? P : 0);
   }
   ACAT_CHECK_LAUNCH();
   return hipSuccess;

@@ -206,7 +206,7 @@ __device__ __forceinline__ int bc_index32(int i, int n, int bc) {
 }
 
 // Variants of the method (acat_problem.flags; ACAT_FLAG_* in acat.h).
-enum { FLAG_FLO_LF = 1, FLAG_FLO_HLL = 2, FLAG_PSI2_MODIFIED = 4, FLAG_PSI1_ROE = 8 };
+enum { FLAG_FLO_LF = 1, FLAG_FLO_HLL = 2, FLAG_PSI2_MODIFIED = 4, FLAG_PSI1_ROE = 8, FLAG_SQUARE_2D = 16 };
 
 // Smallest and largest characteristic speed along direction d (the Davis
 // estimates of HLL): Euler v -+ c, Burgers u, advection a.

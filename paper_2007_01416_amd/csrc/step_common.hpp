@@ -169,10 +169,11 @@ __device__ __forceinline__ void block_max2(double& m0, double& m1) {
   }
 }
 
-__device__ __forceinline__ void block_hist(int* sh, bool valid, int cls, int32_t* out) {
+__device__ __forceinline__ void block_hist(int* sh, bool valid, int cls, int32_t* out, int cls2 = -1) {
   if (threadIdx.x < MAX_CLASSES) sh[threadIdx.x] = 0;
   __syncthreads();
   if (valid) atomicAdd(&sh[cls], 1);
+  if (valid && cls2 >= 0) atomicAdd(&sh[cls2], 1);
   __syncthreads();
   if (threadIdx.x < MAX_CLASSES) out[(int64_t)blockIdx.x * MAX_CLASSES + threadIdx.x] = sh[threadIdx.x];
 }
@@ -271,11 +272,13 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_hist(const int32_t* hist, int n
 // (rank among the tile's items of the same class, in thread order).  One
 // block per tile of the classification, with the same tiles: n1 consecutive
 // items (1D, n2 = 1), or a 16 x 16 patch of the n2 x n1 corner grid (TILED).
-// No atomics, deterministic.
+// With square_P > 0 (2D square-stencil variant, map = pair class of order
+// P), a corner with q1 != q2 is listed in the square classes (q1, q1),
+// tagged F only, and (q2, q2), tagged G only.  No atomics, deterministic.
 template <int NCLS, bool TILED>
 __global__ __launch_bounds__(BLOCK) void k_scatter(const int8_t* map, int map_bias, int64_t n1, int64_t n2,
                                                    int ntiles, const int32_t* offs, const int32_t* counts,
-                                                   int32_t* list) {
+                                                   int32_t* list, int square_P = 0) {
   __shared__ int wc[NCLS][BLOCK / 64];
   int64_t e;
   bool inside;
@@ -289,23 +292,39 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const int8_t* map, int map_bi
     e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     inside = e < n1;
   }
-  const int c = inside ? map[e] - map_bias : -1;
+  int c1 = inside ? map[e] - map_bias : -1;
+  int c2 = -1, t1 = 0, t2 = 0;
+  if (TILED && square_P > 0 && c1 >= 0) {
+    const int a = c1 / square_P, b = c1 % square_P;   // q1 - 1, q2 - 1
+    if (a != b) {
+      c1 = a * square_P + a;
+      t1 = 1;
+      c2 = b * square_P + b;
+      t2 = 2;
+    }
+  }
   const int lane = __lane_id(), wid = threadIdx.x >> 6;
-  unsigned long long mine = 0ull;
+  unsigned long long m1 = 0ull, m2 = 0ull;
 #pragma unroll
   for (int k = 0; k < NCLS; ++k) {
-    const unsigned long long m = __ballot(c == k);
-    if (c == k) mine = m;
+    const unsigned long long m = __ballot(c1 == k || c2 == k);
+    if (c1 == k) m1 = m;
+    if (c2 == k) m2 = m;
     if (lane == 0) wc[k][wid] = __popcll(m);
   }
   __syncthreads();
-  if (c >= 0 && c < NCLS) {
+  const int cs[2] = {c1, c2}, ts[2] = {t1, t2};
+  const unsigned long long ms[2] = {m1, m2};
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int c = cs[s];
+    if (c < 0 || c >= NCLS) continue;
     int64_t pos = 0;
     for (int k = 0; k < c; ++k) pos += counts[k];
     pos += offs[(int64_t)c * (ntiles + 1) + blockIdx.x];
     for (int w = 0; w < wid; ++w) pos += wc[c][w];
-    pos += __popcll(mine & ((1ull << lane) - 1ull));
-    list[pos] = (int32_t)e;
+    pos += __popcll(ms[s] & ((1ull << lane) - 1ull));
+    list[pos] = (int32_t)(e | ((int64_t)ts[s] << LIST_TAG_SHIFT));
   }
 }
 

@@ -63,6 +63,7 @@ def _prob(**kw):
     (dict(flux="burgers", nvar=1, dim=2, ny=16, dy=0.1), -2),
     (dict(flux="advection", nvar=2), -4), (dict(dim=2, nvar=4, ny=64, dy=0.1, P=5), -4),
     (dict(gamma=1.0), -2),
+    (dict(flags=16), -2),    # the square-stencil variant is 2D only
     # smallest grid: 2 max(P, 2) cells per direction
     (dict(nx=7, P=4), -2), (dict(nx=11, P=6), -2), (dict(dim=2, nvar=4, nx=64, ny=5, dy=0.1, P=3), -2),
     # largest: item indices are 32-bit
@@ -175,6 +176,9 @@ def test_adjoint_argument_errors_before_launch(lib):
     assert lib.acat_adjoint_workspace_size(ctypes.byref(p2.c()), ctypes.byref(n)) == 0
     assert lib.acat_adjoint_workspace_size(ctypes.byref(_prob(P=6, bc="transmissive").c()), ctypes.byref(n)) == 0
     assert lib.acat_adjoint_workspace_size(ctypes.byref(_prob(flags=2).c()), ctypes.byref(n)) == -4
+    psq = _prob(dim=2, nvar=4, ny=32, dy=0.1, P=3, flags=16)
+    assert lib.acat_workspace_size(ctypes.byref(psq.c()), ctypes.byref(n)) == 0
+    assert lib.acat_adjoint_workspace_size(ctypes.byref(psq.c()), ctypes.byref(n)) == -4
     assert lib.acat_adjoint_workspace_size(ctypes.byref(_prob(P=7).c()), ctypes.byref(n)) == -2
     p5 = _prob(dim=2, nvar=4, ny=32, dy=0.1, P=5)
     assert lib.acat_adjoint_workspace_size(ctypes.byref(p5.c()), ctypes.byref(n)) == -4

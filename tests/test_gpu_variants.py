@@ -1,6 +1,7 @@
 """GPU parity of the variants (acat_problem.flags) against the oracle:
 Lax-Friedrichs or HLL as the first-order flux, the modified p = 2
-indicator, the Roe-speed limiter ratio for scalar laws.  Lockstep, bit for
+indicator, the Roe-speed limiter ratio for scalar laws, the square-stencil
+2D corners.  Lockstep, bit for
 bit, on shocked data where the fallback and all orders occur; the adjoint
 with Lax-Friedrichs against the dense oracle adjoint."""
 import numpy as np
@@ -14,7 +15,7 @@ from test_gpu_parity import lockstep
 
 pytestmark = pytest.mark.gpu
 
-LF, HLL, PSI2M, ROE = 1, 2, 4, 8
+LF, HLL, PSI2M, ROE, SQUARE = 1, 2, 4, 8, 16
 
 
 @pytest.mark.parametrize("flags", [LF, HLL, PSI2M, PSI2M | LF, PSI2M | HLL])
@@ -46,6 +47,42 @@ def test_variants_lockstep_euler2d(acat, flags, bc):
     w = workloads.euler_2d(n=64, P=3)
     po, pg = from_workload(w, bc=bc, flags=flags)
     lockstep(acat, po, pg, w["u"], 0.4, 4, label=f"euler2d flags={flags} {bc}")
+
+
+@pytest.mark.parametrize("P,flags", [(3, SQUARE), (4, SQUARE), (3, SQUARE | LF)])
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+def test_square_variant_lockstep_euler2d(acat, P, flags, bc):
+    """Corners with q1 != q2 computed on two squares: their entries are
+    listed twice (F only in class (q1, q1), G only in (q2, q2))."""
+    w = workloads.euler_2d(n=64, P=P)
+    po, pg = from_workload(w, bc=bc, flags=flags)
+    r = oracle.step2d(po, w["u"], oracle.dt_cfl(po, w["u"], 0.4))
+    assert (r["ordx"][:, :64] != r["ordy"][:64, :]).any()      # mixed corners occur
+    lockstep(acat, po, pg, w["u"], 0.4, 4, label=f"euler2d square P={P} flags={flags} {bc}")
+
+
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+@pytest.mark.parametrize("q1,q2", [(a, b) for a in range(1, 5) for b in range(1, 5) if a != b])
+def test_square_variant_every_class_forced(acat, q1, q2, bc):
+    from test_gpu_adjoint import gpu_decisions
+    nx, ny = 21, 17
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    rho = 1 + 0.1 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)
+    v, wv = 0.3 + 0.05 * np.sin(2 * np.pi * Y), -0.2 + 0.05 * np.cos(2 * np.pi * X)
+    p = 1 + 0.05 * np.sin(2 * np.pi * (X + Y))
+    u = np.stack([rho, rho * v, rho * wv, p / 0.4 + 0.5 * rho * (v * v + wv * wv)])
+    po, pg = both_problems(2, 4, nx, "euler", 4, bc, 1.0 / nx, ny=ny, dy=1.0 / ny, flags=SQUARE)
+    nIx, nIy = po.n_interfaces
+    r = dict(ordx=np.full((ny, nIx), q1, np.int8), ordy=np.full((nIy, nx), q2, np.int8),
+             psix=np.full((ny, nIx), 0.6), psiy=np.full((nIy, nx), 0.6),
+             alx=np.full((ny, nIx), 2.0), aly=np.full((nIy, nx), 2.0))
+    maps = (r["ordx"], r["ordy"], r["psix"], r["psiy"], r["alx"], r["aly"])
+    dt = oracle.dt_cfl(po, u, 0.4)
+    want = oracle.step2d(po, u, dt, maps=maps)["u"]
+    got = acat.step_replay(pg, torch.from_numpy(u).cuda(), dt, gpu_decisions(acat, pg, po, r)).cpu().numpy()
+    assert np.array_equal(got, want), (q1, q2, bc, np.abs(got - want).max())
 
 
 def test_variants_lockstep_advection2d_roe(acat):
