@@ -64,6 +64,8 @@ def _prob(**kw):
     (dict(flux="advection", nvar=2), -4), (dict(dim=2, nvar=4, ny=64, dy=0.1, P=5), -4),
     (dict(gamma=1.0), -2),
     (dict(flags=16), -2),    # the square-stencil variant is 2D only
+    # empty grids
+    (dict(nx=0), -2), (dict(dim=2, nvar=4, nx=64, ny=0, dy=0.1), -2), (dict(nx=-5), -2),
     # smallest grid: 2 max(P, 2) cells per direction
     (dict(nx=7, P=4), -2), (dict(nx=11, P=6), -2), (dict(dim=2, nvar=4, nx=64, ny=5, dy=0.1, P=3), -2),
     # largest: item indices are 32-bit
@@ -242,3 +244,13 @@ def test_fma_rate_argument_errors(lib):
     assert lib.acat_fp64_fma_rate(0, 1, p, 256, None) == -2
     assert lib.acat_fp64_fma_rate(1, 0, p, 256, None) == -2
     assert lib.acat_fp64_fma_rate(2, 1, p, 256, None) == -2
+
+
+def test_empty_batch_is_rejected(lib):
+    import paper_2007_01416_amd as acat
+    n = np.zeros(0, np.int64); P = np.zeros(0, np.int32); bc = np.zeros(0, np.int32); dx = np.zeros(0)
+    b = acat._Batch(3, 2, 1.4, 1.0, 1e-12, 0.5, 0, n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                    P.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), bc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                    dx.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    nb = ctypes.c_size_t(0)
+    assert lib.acat_batch_workspace_size(ctypes.byref(b), ctypes.byref(nb)) == -2
