@@ -459,7 +459,8 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, double lamx, double 
 }
 
 // Fluxes of the corners of order class (Q1, Q2) (Sec. 4; rectangle J_Q1 x J_Q2).
-template <int FLUX, int NV, int Q1, int Q2>
+// SQUARE: list entries carry the square-stencil variant's tags (square classes only).
+template <int FLUX, int NV, int Q1, int Q2, bool SQUARE = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_flux2d(KProb pb, KStep st) {
   constexpr int N1 = 2 * Q1, N2 = 2 * Q2, L = N1 * N2;
   using Grp = Groups<L>;
@@ -497,9 +498,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
       const bool valid = inblk && base + g < sl.hi;
       const int32_t raw = valid ? sl.items[base + g] : 0;
       // square-stencil variant: entries carry which flux to store (1 F, 2 G, 0 both)
-      const bool tagged = (pb.flags & FLAG_SQUARE_2D) != 0;
-      const int32_t e = tagged ? (raw & ((1 << LIST_TAG_SHIFT) - 1)) : raw;
-      const int tag = tagged ? (raw >> LIST_TAG_SHIFT) : 0;
+      const int32_t e = SQUARE ? (raw & ((1 << LIST_TAG_SHIFT) - 1)) : raw;
+      const int tag = SQUARE ? (raw >> LIST_TAG_SHIFT) : 0;
       const uint32_t eq = (uint32_t)e / n1u;
       const int i2 = (int)eq + ioff, i1 = (int)((uint32_t)e - eq * n1u) + ioff;
       const int x = bc_index32(i1 + (a1 - Q1 + 1), nx32, pb.bc);
@@ -746,7 +746,11 @@ hipError_t launch_class2d(const KProb& pb, const KStep& st, int cap, hipStream_t
                                       {"", "flux2d_q21", "flux2d_q22", "flux2d_q23", "flux2d_q24"},
                                       {"", "flux2d_q31", "flux2d_q32", "flux2d_q33", "flux2d_q34"},
                                       {"", "flux2d_q41", "flux2d_q42", "flux2d_q43", "flux2d_q44"}};
+    // under the square-stencil variant only the square classes have items
     auto kern = k_flux2d<FLUX, NV, Q1, Q2>;
+    if constexpr (Q1 == Q2) {
+      if (pb.flags & FLAG_SQUARE_2D) kern = k_flux2d<FLUX, NV, Q1, Q2, true>;
+    }
     const int grid = persistent_grid(kern, pb.n1 * pb.n2, cap);
     {
       ProfScope ps(names[Q1][Q2], s);
@@ -769,8 +773,12 @@ hipError_t lists2d_impl(const KProb& pb, const KStep& st, hipStream_t s) {
     ProfScope ps("class_lists", s);
     k_scan_hist<<<P * P + (st.cfl_mode ? 1 : 0), SCAN_T, 0, s>>>(st.hist, cblocks, st.offs, st.counts, P * P,
                                                                 cfl_reduce(pb, st, cblocks));
-    k_scatter<P * P, true><<<cblocks, BLOCK, 0, s>>>(st.cls, 0, pb.n1, pb.n2, cblocks, st.offs, st.counts,
-                                                      st.list, (pb.flags & FLAG_SQUARE_2D) ? P : 0);
+    if (pb.flags & FLAG_SQUARE_2D)
+      k_scatter<P * P, true, true><<<cblocks, BLOCK, 0, s>>>(st.cls, 0, pb.n1, pb.n2, cblocks, st.offs, st.counts,
+                                                              st.list, P);
+    else
+      k_scatter<P * P, true><<<cblocks, BLOCK, 0, s>>>(st.cls, 0, pb.n1, pb.n2, cblocks, st.offs, st.counts,
+                                                        st.list);
   }
   ACAT_CHECK_LAUNCH();
   return hipSuccess;

@@ -272,10 +272,10 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_hist(const int32_t* hist, int n
 // (rank among the tile's items of the same class, in thread order).  One
 // block per tile of the classification, with the same tiles: n1 consecutive
 // items (1D, n2 = 1), or a 16 x 16 patch of the n2 x n1 corner grid (TILED).
-// With square_P > 0 (2D square-stencil variant, map = pair class of order
-// P), a corner with q1 != q2 is listed in the square classes (q1, q1),
-// tagged F only, and (q2, q2), tagged G only.  No atomics, deterministic.
-template <int NCLS, bool TILED>
+// SQUARE (2D square-stencil variant, map = pair class of order square_P): a
+// corner with q1 != q2 is listed in the square classes (q1, q1), tagged F
+// only, and (q2, q2), tagged G only.  No atomics, deterministic.
+template <int NCLS, bool TILED, bool SQUARE = false>
 __global__ __launch_bounds__(BLOCK) void k_scatter(const int8_t* map, int map_bias, int64_t n1, int64_t n2,
                                                    int ntiles, const int32_t* offs, const int32_t* counts,
                                                    int32_t* list, int square_P = 0) {
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const int8_t* map, int map_bi
   }
   int c1 = inside ? map[e] - map_bias : -1;
   int c2 = -1, t1 = 0, t2 = 0;
-  if (TILED && square_P > 0 && c1 >= 0) {
+  if (SQUARE && c1 >= 0) {
     const int a = c1 / square_P, b = c1 % square_P;   // q1 - 1, q2 - 1
     if (a != b) {
       c1 = a * square_P + a;
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const int8_t* map, int map_bi
   const int cs[2] = {c1, c2}, ts[2] = {t1, t2};
   const unsigned long long ms[2] = {m1, m2};
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
+  for (int s = 0; s < (SQUARE ? 2 : 1); ++s) {
     const int c = cs[s];
     if (c < 0 || c >= NCLS) continue;
     int64_t pos = 0;
