@@ -423,7 +423,7 @@ def main():
                     help="also run one 1 GiB device-to-device copy (reference dispatch for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        sys.exit("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus must be 1)")
+        sys.exit("bench.py runs on one GPU only: the library has no multi-GPU path (--gpus must be 1)")
 
     import numpy as np
     import torch
