@@ -227,12 +227,14 @@ def misfit_grad(w, u_T, rho_star):
     return g
 
 
-@pytest.mark.parametrize("n,nsteps,k", [(64, 12, 5), (64, 10, 10)])
-def test_checkpointed_run_matches_oracle_tangent(acat, n, nsteps, k):
+@pytest.mark.parametrize("n,nsteps,k,bc,P", [(64, 12, 5, "periodic", 2), (64, 10, 10, "periodic", 2),
+                                             (48, 8, 3, "transmissive", 2), (40, 6, 4, "transmissive", 4)])
+def test_checkpointed_run_matches_oracle_tangent(acat, n, nsteps, k, bc, P):
     """Gradient of a misfit after nsteps through ACATRun (checkpoint every k)
-    against the oracle's tangent run along two directions."""
+    against the oracle's tangent run along two directions; both boundaries,
+    orders 4 and 8."""
     w = workloads.adjoint_2d(n=n)
-    po, pg = from_workload(w)
+    po, pg = from_workload(w, bc=bc, P=P)
     uT_o, _, _, hist = oracle.run(po, w["u"], w["cfl"], nsteps=nsteps, nthreads=16, record=True)
     star = oracle.run(po, w["target_u0"], w["cfl"], nsteps=nsteps, nthreads=16)[0][0]
     run = acat.AdjointRun(pg, w["cfl"], nsteps, checkpoint_every=k)
