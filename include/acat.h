@@ -218,6 +218,14 @@ acat_status acat_batch_init(const acat_batch* batch, void* workspace, size_t wor
 /* u_out = one ACAT step of every problem with dt_dev[b] (device [nprob]). */
 acat_status acat_step_batched(const acat_batch* batch, const double* u_in, double* u_out, const double* dt_dev,
                               void* workspace, size_t workspace_bytes, void* stream);
+/* The same step, and then dt_dev[b] = the time step that acat_batched_cfl_dt
+ * (cfl) gives for u_out, bit for bit: the update pass reduces each problem's
+ * maximum wave speed of the new state (atomic maxima on the bit patterns,
+ * exact in any order), so no extra pass over u_out is made.  dt_dev is read
+ * as this step's time steps before it is overwritten; cfl > 0.  The first
+ * dt_dev comes from acat_batched_cfl_dt. */
+acat_status acat_step_batched_cfl(const acat_batch* batch, const double* u_in, double* u_out, double* dt_dev,
+                                  double cfl, void* workspace, size_t workspace_bytes, void* stream);
 /* dt_dev[b] = cfl dx[b] / (max spectral radius over problem b of u). */
 acat_status acat_batched_cfl_dt(const acat_batch* batch, const double* u, double cfl, double* dt_dev,
                                 void* workspace, size_t workspace_bytes, void* stream);

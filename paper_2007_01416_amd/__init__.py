@@ -73,6 +73,8 @@ _SIGS = {
     "acat_batch_init": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t],
     "acat_step_batched": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                           ctypes.c_size_t, ctypes.c_void_p],
+    "acat_step_batched_cfl": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                              ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "acat_batched_cfl_dt": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                             ctypes.c_size_t, ctypes.c_void_p],
     "acat_profile_enable": [ctypes.c_int32],
@@ -369,6 +371,16 @@ class Batch:
         out = torch.empty_like(u) if out is None else out
         _check(load().acat_step_batched(ctypes.byref(self._c), _ptr(u), _ptr(out), _ptr(dt), _ptr(self.ws),
                                         self.ws.numel(), _stream(stream)), "acat_step_batched")
+        return out
+
+    def step_cfl(self, u: torch.Tensor, dt: torch.Tensor, cfl: float, out: torch.Tensor = None,
+                 stream=None) -> torch.Tensor:
+        """One step with the time steps in `dt`, after which `dt` holds the CFL
+        time steps of the result (as `cfl_dt(out, cfl, dt)` would give)."""
+        out = torch.empty_like(u) if out is None else out
+        _check(load().acat_step_batched_cfl(ctypes.byref(self._c), _ptr(u), _ptr(out), _ptr(dt), cfl,
+                                            _ptr(self.ws), self.ws.numel(), _stream(stream)),
+               "acat_step_batched_cfl")
         return out
 
     def cfl_dt(self, u: torch.Tensor, cfl: float, dt: torch.Tensor, stream=None) -> torch.Tensor:

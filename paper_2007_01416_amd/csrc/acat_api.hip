@@ -262,7 +262,7 @@ acat_status check_batch(const acat_batch* bt) {
 }
 
 struct BLayout {
-  size_t hdr, coff, ioffs, N, P, bc, dx, pif, pcell, smax, ord, psi, al, F, hist, offs, list, total;
+  size_t hdr, coff, ioffs, N, P, bc, dx, pif, pcell, smax, ord, psi, al, wmax, F, hist, offs, list, total;
   int64_t ncell, nif;
   int Pmax;
 };
@@ -291,6 +291,7 @@ BLayout blayout(const acat_batch* bt) {
   L.ord = o;   o += align_up((size_t)L.nif);
   L.psi = o;   o += align_up(sizeof(double) * L.nif);
   L.al = o;    o += align_up(sizeof(double) * L.nif);
+  L.wmax = o;  o += align_up(sizeof(double) * ((L.ncell + 63) / 64));
   L.F = o;     o += align_up(sizeof(double) * bt->nvar * L.nif);
   L.hist = o;  o += align_up(sizeof(int32_t) * MAX_CLASSES * tiles);
   L.offs = o;  o += align_up(sizeof(int32_t) * MAX_CLASSES * (tiles + 1));
@@ -445,7 +446,7 @@ acat_status acat_batch_init(const acat_batch* batch, void* workspace, size_t wor
   const BLayout L = blayout(batch);
   if (!workspace || workspace_bytes < L.total) return ACAT_ERR_WORKSPACE;
   const int np = batch->nprob;
-  std::vector<char> host(L.smax - L.coff, 0);
+  std::vector<char> host(L.ord - L.coff, 0);   // the static tables, and smax cleared
   auto put = [&](size_t off, const void* src, size_t n) { std::memcpy(host.data() + (off - L.coff), src, n); };
   std::vector<int64_t> coff(np + 1, 0), ioffs(np + 1, 0);
   std::vector<int32_t> N(np), P(np), bc(np);
@@ -474,11 +475,14 @@ acat_status acat_batch_init(const acat_batch* batch, void* workspace, size_t wor
   return ACAT_OK;
 }
 
-acat_status acat_step_batched(const acat_batch* batch, const double* u_in, double* u_out, const double* dt_dev,
-                              void* workspace, size_t workspace_bytes, void* stream) {
+namespace acat {
+namespace {
+acat_status step_batched(const acat_batch* batch, const double* u_in, double* u_out, double* dt_dev, double cfl,
+                         bool fused_cfl, void* workspace, size_t workspace_bytes, void* stream) {
   acat_status rc = check_batch(batch);
   if (rc != ACAT_OK) return rc;
   if (!u_in || !u_out || !dt_dev) return ACAT_ERR_NULL;
+  if (fused_cfl && !(cfl > 0.0)) return ACAT_ERR_ARG;
   const BLayout L = blayout(batch);
   if (!workspace || workspace_bytes < L.total) return ACAT_ERR_WORKSPACE;
   if (overlaps(u_in, u_out, sizeof(double) * batch->nvar * (size_t)L.ncell)) return ACAT_ERR_ALIAS;
@@ -498,8 +502,27 @@ acat_status acat_step_batched(const acat_batch* batch, const double* u_in, doubl
   st.list = reinterpret_cast<int32_t*>(w + L.list);
   st.status = status_ptr();
   if (!st.status) return ACAT_ERR_DEVICE;
+  if (fused_cfl) {
+    st.smax = reinterpret_cast<unsigned long long*>(w + L.smax);
+    st.wmax = reinterpret_cast<double*>(w + L.wmax);
+    st.dt_next = dt_dev;
+    st.cfl = cfl;
+  }
   hipError_t e = launch_step_batched(bt, st, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? ACAT_OK : ACAT_ERR_DEVICE;
+}
+}  // namespace
+}  // namespace acat
+
+acat_status acat_step_batched(const acat_batch* batch, const double* u_in, double* u_out, const double* dt_dev,
+                              void* workspace, size_t workspace_bytes, void* stream) {
+  return step_batched(batch, u_in, u_out, const_cast<double*>(dt_dev), 0.0, false, workspace, workspace_bytes,
+                      stream);
+}
+
+acat_status acat_step_batched_cfl(const acat_batch* batch, const double* u_in, double* u_out, double* dt_dev,
+                                  double cfl, void* workspace, size_t workspace_bytes, void* stream) {
+  return step_batched(batch, u_in, u_out, dt_dev, cfl, true, workspace, workspace_bytes, stream);
 }
 
 acat_status acat_batched_cfl_dt(const acat_batch* batch, const double* u, double cfl, double* dt_dev,
@@ -512,7 +535,7 @@ acat_status acat_batched_cfl_dt(const acat_batch* batch, const double* u, double
   if (!workspace || workspace_bytes < L.total) return ACAT_ERR_WORKSPACE;
   char* w = static_cast<char*>(workspace);
   const KBatch bt = make_kbatch(batch, L, w);
-  hipError_t e = launch_cfl_batched(bt, u, cfl, reinterpret_cast<double*>(w + L.smax), dt_dev,
+  hipError_t e = launch_cfl_batched(bt, u, cfl, reinterpret_cast<unsigned long long*>(w + L.smax), dt_dev,
                                     static_cast<hipStream_t>(stream));
   return e == hipSuccess ? ACAT_OK : ACAT_ERR_DEVICE;
 }

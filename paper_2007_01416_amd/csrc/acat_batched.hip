@@ -189,33 +189,66 @@ __global__ __launch_bounds__(BS) void k_flux_b(KBatch bt, KBStep st) {
   }
 }
 
-template <int FLUX, int NV>
+// A wave speed as a maximum candidate: NaN and -0 become +0, so that the bit
+// pattern orders like the value under an unsigned integer maximum.
+__device__ __forceinline__ double speed_floor(double m) { return m > 0.0 ? m : 0.0; }
+
+template <int FLUX, int NV, bool CFL>
 __global__ __launch_bounds__(BLOCK) void k_update_b(KBatch bt, KBStep st) {
   const int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (e >= bt.ncell) return;
-  const int b = bt.pcell[e];
-  const int n = bt.N[b], bc = bt.bc[b];
-  const int i = (int)(e - bt.coff[b]);
-  const double lam = st.dt[b] / bt.dx[b];
-  const int64_t kr = bt.ioffs[b] + i + (bc == PERIODIC ? 0 : 1);
-  const int64_t kl = bt.ioffs[b] + ((bc == PERIODIC) ? (i == 0 ? n - 1 : i - 1) : i);
+  const bool valid = e < bt.ncell;
+  const int b = valid ? bt.pcell[e] : 0;
   double w[NV];
-  bool finite = true;
+  if (valid) {
+    const int n = bt.N[b], bc = bt.bc[b];
+    const int i = (int)(e - bt.coff[b]);
+    const double lam = st.dt[b] / bt.dx[b];
+    const int64_t kr = bt.ioffs[b] + i + (bc == PERIODIC ? 0 : 1);
+    const int64_t kl = bt.ioffs[b] + ((bc == PERIODIC) ? (i == 0 ? n - 1 : i - 1) : i);
+    bool finite = true;
 #pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    w[c] = st.u[c * bt.ncell + e] + lam * (st.F[c * bt.nif + kl] - st.F[c * bt.nif + kr]);
-    st.uout[c * bt.ncell + e] = w[c];
-    finite = finite && isfinite(w[c]);
+    for (int c = 0; c < NV; ++c) {
+      w[c] = st.u[c * bt.ncell + e] + lam * (st.F[c * bt.nif + kl] - st.F[c * bt.nif + kr]);
+      st.uout[c * bt.ncell + e] = w[c];
+      finite = finite && isfinite(w[c]);
+    }
+    const uint32_t bad = (finite ? 0u : 1u) | (physical<FLUX, 1, NV>(bt.ph, w) ? 0u : 2u);
+    if (bad) atomicOr(st.status, bad);
   }
-  const uint32_t bad = (finite ? 0u : 1u) | (physical<FLUX, 1, NV>(bt.ph, w) ? 0u : 2u);
-  if (bad) atomicOr(st.status, bad);
+  if constexpr (CFL) {
+    // per-problem maximum of the new state's spectral radius (NaN and -0
+    // count as +0, as in k_max_speed_b).  The lanes of a wave hold runs of
+    // equal problem index: a segmented maximum over the runs, then the last
+    // lane of each run stores it, with a plain store when the run is the
+    // whole wave (most waves; folded per problem by k_dt_fold_b) and as an
+    // atomic maximum on the bit patterns otherwise (only waves that straddle
+    // problems; non-negative doubles order like their bit patterns, and max
+    // is exact in any order).
+    double m = valid ? speed_floor(spectral_radius<FLUX, 1, NV>(bt.ph, w, 0)) : 0.0;
+    const int key = valid ? b : -1;
+    const int lane = __lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double mo = __shfl_up(m, off);
+      const int ko = __shfl_up(key, off);
+      if (lane >= off && ko == key) m = fmax(m, mo);
+    }
+    const int key0 = __shfl(key, 0);
+    const bool whole = __all(key == key0) && key0 >= 0;
+    const int knext = __shfl_down(key, 1);
+    if (valid && (lane == 63 || knext != key)) {
+      if (whole) st.wmax[e >> 6] = m;
+      else atomicMax(&st.smax[key], (unsigned long long)__double_as_longlong(m));
+    }
+  }
 }
 
 // smax[b] = max spectral radius over problem b: one 1024-thread block per
 // problem (a few cells per thread even for the largest problems), no atomics.
 constexpr int MSB_T = 1024;
 template <int FLUX, int NV>
-__global__ __launch_bounds__(MSB_T) void k_max_speed_b(KBatch bt, const double* __restrict__ u, double* smax) {
+__global__ __launch_bounds__(MSB_T) void k_max_speed_b(KBatch bt, const double* __restrict__ u,
+                                                      unsigned long long* smax) {
   const int b = blockIdx.x;
   const int64_t c0 = bt.coff[b], c1 = bt.coff[b + 1];
   double m = 0.0;
@@ -233,13 +266,34 @@ __global__ __launch_bounds__(MSB_T) void k_max_speed_b(KBatch bt, const double* 
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int w = 1; w < MSB_T / 64; ++w) m = fmax(m, red[w]);
-    smax[b] = m;
+    smax[b] = (unsigned long long)__double_as_longlong(speed_floor(m));
   }
 }
 
-__global__ void k_dt_b(KBatch bt, const double* smax, double cfl, double* dt) {
+// dt[b] = cfl dx[b] / smax[b]; smax is cleared for the next reduction
+// One wave per problem: the maximum of the partial maxima of the waves whole
+// inside problem b (cells coff[b] .. coff[b+1]-1) and of smax[b].
+__global__ __launch_bounds__(64) void k_dt_fold_b(KBatch bt, unsigned long long* smax, const double* wmax,
+                                                  double cfl, double* dt) {
+  const int b = blockIdx.x;
+  const int64_t w0 = (bt.coff[b] + 63) >> 6, w1 = bt.coff[b + 1] >> 6;
+  double m = 0.0;
+  for (int64_t v = w0 + threadIdx.x; v < w1; v += 64) m = fmax(m, wmax[v]);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  if (threadIdx.x == 0) {
+    m = fmax(m, __longlong_as_double((long long)smax[b]));
+    dt[b] = cfl * bt.dx[b] / m;
+    smax[b] = 0ull;
+  }
+}
+
+__global__ void k_dt_b(KBatch bt, unsigned long long* smax, double cfl, double* dt) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < bt.nprob) dt[b] = cfl * bt.dx[b] / smax[b];
+  if (b < bt.nprob) {
+    dt[b] = cfl * bt.dx[b] / __longlong_as_double((long long)smax[b]);
+    smax[b] = 0ull;
+  }
 }
 
 #define ACAT_CHECK_LAUNCH()                  \
@@ -292,14 +346,21 @@ hipError_t step_b_impl(const KBatch& bt, const KBStep& st, hipStream_t s) {
   if ((e = launch_flux_b<FLUX, NV, 4>(bt, st, s)) != hipSuccess) return e;
   {
     ProfScope ps("update_b", s);
-    k_update_b<FLUX, NV><<<(unsigned)((bt.ncell + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(bt, st);
+    const unsigned grid = (unsigned)((bt.ncell + BLOCK - 1) / BLOCK);
+    if (st.smax) k_update_b<FLUX, NV, true><<<grid, BLOCK, 0, s>>>(bt, st);
+    else k_update_b<FLUX, NV, false><<<grid, BLOCK, 0, s>>>(bt, st);
   }
   ACAT_CHECK_LAUNCH();
+  if (st.smax) {
+    k_dt_fold_b<<<bt.nprob, 64, 0, s>>>(bt, st.smax, st.wmax, st.cfl, st.dt_next);
+    ACAT_CHECK_LAUNCH();
+  }
   return hipSuccess;
 }
 
 template <int FLUX, int NV>
-hipError_t cfl_b_impl(const KBatch& bt, const double* u, double cfl, double* smax, double* dt, hipStream_t s) {
+hipError_t cfl_b_impl(const KBatch& bt, const double* u, double cfl, unsigned long long* smax, double* dt,
+                      hipStream_t s) {
   {
     ProfScope ps("max_speed_b", s);
     k_max_speed_b<FLUX, NV><<<bt.nprob, MSB_T, 0, s>>>(bt, u, smax);
@@ -318,7 +379,7 @@ hipError_t launch_step_batched(const KBatch& bt, const KBStep& st, hipStream_t s
   return step_b_impl<ADV, 1>(bt, st, s);
 }
 
-hipError_t launch_cfl_batched(const KBatch& bt, const double* u, double cfl, double* smax, double* dt,
+hipError_t launch_cfl_batched(const KBatch& bt, const double* u, double cfl, unsigned long long* smax, double* dt,
                               hipStream_t s) {
   if (bt.flux == EUL) return cfl_b_impl<EUL, 3>(bt, u, cfl, smax, dt, s);
   if (bt.flux == BURG) return cfl_b_impl<BURG, 1>(bt, u, cfl, smax, dt, s);

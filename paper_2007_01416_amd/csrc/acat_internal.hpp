@@ -128,10 +128,19 @@ struct KBStep {
   int32_t* counts;
   int32_t* list;
   uint32_t* status;
+  // with smax set: the update also reduces the spectral radius of the new
+  // state, one maximum per wave that lies whole inside one problem into
+  // wmax[wave] and the rest into smax[problem] (bit patterns of non-negative
+  // doubles, atomic maxima; zero on entry); a last kernel folds both into
+  // the next time steps dt_next[b] = cfl dx[b] / max and clears smax
+  unsigned long long* smax;
+  double* wmax;             // [ceil(ncell / 64)]
+  double* dt_next;
+  double cfl;
 };
 
 hipError_t launch_step_batched(const KBatch& bt, const KBStep& st, hipStream_t stream);
-hipError_t launch_cfl_batched(const KBatch& bt, const double* u, double cfl, double* smax, double* dt,
+hipError_t launch_cfl_batched(const KBatch& bt, const double* u, double cfl, unsigned long long* smax, double* dt,
                               hipStream_t stream);
 
 }  // namespace acat

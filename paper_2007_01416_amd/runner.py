@@ -101,7 +101,9 @@ class Solver:
 
 class BatchSolver:
     """Fixed-step time loop of a Batch: per step, per-problem CFL time steps
-    and one batched step; `capture(k)` records k steps into one HIP graph."""
+    and one batched step; `capture(k)` records k steps into one HIP graph.
+    After the first step the time steps of step n+1 are reduced inside step n
+    (acat_step_batched_cfl)."""
 
     def __init__(self, batch: Batch, u0, cfl: float, device="cuda"):
         self.batch = batch
@@ -112,6 +114,7 @@ class BatchSolver:
         self.buf = [u0.clone(), torch.empty_like(u0)]
         self.cur = 0
         self.dt = torch.zeros(batch.nprob, dtype=torch.float64, device=device)
+        self.dt_valid = False   # dt holds the CFL time steps of the current state
         self.nsteps = 0
         self.graph = None
         self.graph_steps = 0
@@ -121,8 +124,10 @@ class BatchSolver:
         return self.buf[self.cur]
 
     def step(self):
-        self.batch.cfl_dt(self.u, self.cfl, self.dt)
-        self.batch.step(self.u, self.dt, out=self.buf[1 - self.cur])
+        if not self.dt_valid:
+            self.batch.cfl_dt(self.u, self.cfl, self.dt)
+            self.dt_valid = True
+        self.batch.step_cfl(self.u, self.dt, self.cfl, out=self.buf[1 - self.cur])
         self.cur ^= 1
         self.nsteps += 1
 

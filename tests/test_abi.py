@@ -148,6 +148,11 @@ def test_batch_validation(lib, n, P, bc, dx, code):
         ws = ctypes.create_string_buffer(nb.value)
         assert lib.acat_step_batched(ctypes.byref(b), None, None, None, ws, nb.value, None) == -1
         assert lib.acat_step_batched(ctypes.byref(b), ws, ws, ws, ws, 16, None) == -6
+        # the fused-CFL step also needs cfl > 0
+        assert lib.acat_step_batched_cfl(ctypes.byref(b), None, None, None, 0.5, ws, nb.value, None) == -1
+        assert lib.acat_step_batched_cfl(ctypes.byref(b), ws, ws, ws, 0.0, ws, nb.value, None) == -2
+        assert lib.acat_step_batched_cfl(ctypes.byref(b), ws, ws, ws, float("nan"), ws, nb.value, None) == -2
+        assert lib.acat_step_batched_cfl(ctypes.byref(b), ws, ws, ws, 0.5, ws, 16, None) == -6
 
 
 @pytest.mark.parametrize("table,code", [

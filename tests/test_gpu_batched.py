@@ -42,13 +42,19 @@ def test_batched_c4_equals_per_instance_steps(acat):
         pg = acat.Problem(dim=1, nvar=3, nx=p["u"].shape[1], flux="euler", P=p["P"], bc=p["bc"], dx=p["dx"])
         singles.append(acat.Solver(pg, p["u"], w["cfl"]))
     for n in range(3):
+        # the time steps this step uses, by the separate reduction; after the
+        # first step the solver holds them already (reduced inside the last step)
+        used = torch.empty_like(bs.dt)
+        batch.cfl_dt(bs.u, w["cfl"], used)
+        if bs.dt_valid:
+            assert torch.equal(used, bs.dt), f"fused time steps before step {n}"
         bs.step()
         for s in singles:
             s.step()
         torch.cuda.synchronize()
         got = bs.u.cpu().numpy()
         parts = batch.split(got)
-        dts = bs.dt.cpu().numpy()
+        dts = used.cpu().numpy()
         for b, s in enumerate(singles):
             assert float(s.dt.item()) == dts[b], f"dt problem {b} step {n}"
             assert np.array_equal(parts[b], s.u.cpu().numpy()), f"state problem {b} step {n}"
@@ -90,6 +96,46 @@ def test_batched_lockstep_oracle(acat, flux):
             assert dts[b] == oracle.dt_cfl(po, us[b], 0.6)
             us[b] = oracle.step1d(po, us[b], dts[b])["u"]
             assert np.array_equal(parts[b], us[b]), f"problem {b} step {step}"
+
+
+@pytest.mark.parametrize("flux", ["euler", "burgers"])
+def test_batched_fused_cfl_equals_separate_reduction(acat, flux):
+    """acat_step_batched_cfl: the same states as acat_step_batched, and the time
+    steps it leaves equal acat_batched_cfl_dt of the new state, over several
+    steps (ragged sizes, problems shorter than a wave, periodic and
+    transmissive, every P)."""
+    import torch
+    rng = np.random.default_rng(11)
+    sizes = [8, 9, 40, 63, 64, 65, 130, 777, 2049, 16]
+    probs = []
+    for b, n in enumerate(sizes):
+        P = 1 + b % 4
+        n = max(n, 2 * max(P, 2))
+        if flux == "euler":
+            p = workloads.euler_1d(n=n, P=P, stream=(100 + b,))
+        else:
+            x = np.arange(n) / n
+            p = dict(u=(np.sin(2 * np.pi * x + b) - 0.3 * (x > 0.4))[None].copy(), dx=1.0 / n, flux="burgers",
+                     P=P, nvar=1)
+        p["bc"] = "periodic" if b % 2 else "transmissive"
+        p["P"] = P
+        probs.append(p)
+    batch = make_batch(acat, probs)
+    u0 = T(concat([p["u"] for p in probs]))
+    cfl = 0.55
+    ua, dta = u0.clone(), torch.zeros(batch.nprob, dtype=torch.float64, device="cuda")
+    ub, dtb = u0.clone(), torch.zeros_like(dta)
+    batch.cfl_dt(ua, cfl, dta)
+    for step in range(6):
+        batch.cfl_dt(ub, cfl, dtb)
+        assert torch.equal(dta, dtb), f"dt before step {step}"
+        ua = batch.step_cfl(ua, dta, cfl)
+        ub = batch.step(ub, dtb)
+        torch.cuda.synchronize()
+        assert torch.equal(ua, ub), f"state after step {step}"
+    batch.cfl_dt(ub, cfl, dtb)
+    assert torch.equal(dta, dtb)
+    say(f"[batched fused CFL] {flux}: 6 steps, states and time steps bitwise equal to the separate reduction")
 
 
 def test_batched_graph_replay_matches_eager(acat):
