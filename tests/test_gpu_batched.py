@@ -98,6 +98,42 @@ def test_batched_lockstep_oracle(acat, flux):
             assert np.array_equal(parts[b], us[b]), f"problem {b} step {step}"
 
 
+def test_batched_c4_full_size_sampled_oracle(acat):
+    """The full batched workload (256 Euler problems, 1.2 M cells) through
+    BatchSolver, as the benchmark runs it (the second step's time steps come
+    from the fused reduction): sampled problems (the largest, the smallest,
+    and two more at each P) against the oracle's own time steps and steps,
+    bitwise."""
+    import torch
+    w = workloads.batch_1d()
+    probs = w["problems"]
+    batch = make_batch(acat, probs)
+    bs = acat.BatchSolver(batch, concat([p["u"] for p in probs]), w["cfl"])
+    Ns = np.array([p["u"].shape[1] for p in probs])
+    Ps = np.array([p["P"] for p in probs])
+    pick = {int(np.argmax(Ns)), int(np.argmin(Ns))}
+    for P in (2, 3, 4):
+        pick.update(int(b) for b in np.flatnonzero(Ps == P)[:2])
+    pick = sorted(pick)
+    us = {b: probs[b]["u"].copy() for b in pick}
+    po = {b: oracle.Problem(dim=1, nvar=3, nx=int(Ns[b]), flux=oracle.FLUX_EULER, P=int(Ps[b]),
+                            bc=oracle.BC_TRANSMISSIVE if probs[b]["bc"] == "transmissive" else oracle.BC_PERIODIC,
+                            dx=probs[b]["dx"]) for b in pick}
+    for step in range(2):
+        dts = {b: oracle.dt_cfl(po[b], us[b], w["cfl"]) for b in pick}
+        if bs.dt_valid:
+            got_dt = bs.dt.cpu().numpy()
+            for b in pick:
+                assert got_dt[b] == dts[b], f"fused time step, problem {b} before step {step}"
+        bs.step()
+        torch.cuda.synchronize()
+        parts = batch.split(bs.u.cpu().numpy())
+        for b in pick:
+            us[b] = oracle.step1d(po[b], us[b], dts[b])["u"]
+            assert np.array_equal(parts[b], us[b]), f"problem {b} (N={Ns[b]}, P={Ps[b]}) step {step}"
+    say(f"[batched C4 full size] problems {pick}: 2 steps bitwise equal to the oracle")
+
+
 @pytest.mark.parametrize("flux", ["euler", "burgers"])
 def test_batched_fused_cfl_equals_separate_reduction(acat, flux):
     """acat_step_batched_cfl: the same states as acat_step_batched, and the time
