@@ -234,10 +234,15 @@ inline double val(const Dual& x) { return x.v; }
 // a*b + c with one rounding.  Every weighted sum of the recursion (the
 // differentiation formulas in space and time, the Taylor predictions and
 // the final flux sum) accumulates in index order with this fused
-// multiply-add; all other arithmetic is plain IEEE operations, so the
-// rounding of every operation is fixed.
+// multiply-add, and so do U^k's two directional terms and the 2D Euler
+// flux's product-sums (m v + n w, E - (m v + n w)/2, m v + p, n w + p); all
+// other arithmetic is plain IEEE operations, so the rounding of every
+// operation is fixed.
 inline double mad(double a, double b, double c) { return std::fma(a, b, c); }
 inline Dual mad(double a, const Dual& b, const Dual& c) { return Dual(std::fma(a, b.v, c.v), std::fma(a, b.d, c.d)); }
+inline Dual mad(const Dual& a, const Dual& b, const Dual& c) {
+  return Dual(std::fma(a.v, b.v, c.v), a.d * b.v + a.v * b.d + c.d);
+}
 
 // ---------------------------------------------------------------------------
 // Physics: fluxes and spectral radii.
@@ -280,9 +285,9 @@ void flux_f(const oracle_problem& pb, const T* u, T* f) {
     T rho = u[0], mx = u[1], my = u[2], E = u[3];
     T ir = 1.0 / rho;
     T v = mx * ir, w = my * ir;
-    T p = (pb.gamma - 1.0) * (E - 0.5 * (mx * v + my * w));
+    T p = (pb.gamma - 1.0) * mad(-0.5, mad(mx, v, my * w), E);
     f[0] = mx;
-    f[1] = mx * v + p;
+    f[1] = mad(mx, v, p);
     f[2] = my * v;
     f[3] = v * (E + p);
   }
@@ -297,10 +302,10 @@ void flux_g(const oracle_problem& pb, const T* u, T* g) {
     T rho = u[0], mx = u[1], my = u[2], E = u[3];
     T ir = 1.0 / rho;
     T v = mx * ir, w = my * ir;
-    T p = (pb.gamma - 1.0) * (E - 0.5 * (mx * v + my * w));
+    T p = (pb.gamma - 1.0) * mad(-0.5, mad(mx, v, my * w), E);
     g[0] = my;
     g[1] = mx * w;
-    g[2] = my * w + p;
+    g[2] = mad(my, w, p);
     g[3] = w * (E + p);
   }
 }
@@ -662,7 +667,7 @@ void cat_corner_2d(const oracle_problem& pb, int q1, int q2, int qt, const T (*u
           T sx = 0.0, sy = 0.0;
           for (int l = 0; l < n1; ++l) sx = mad(Tb.g1[q1][a1][l], Fh[k - 2][l][a2][c], sx);
           for (int l = 0; l < n2; ++l) sy = mad(Tb.g1[q2][a2][l], Gh[k - 2][a1][l][c], sy);
-          U[k - 1][a1][a2][c] = -lamx * sx - lamy * sy;
+          U[k - 1][a1][a2][c] = mad(-lamy, sy, -lamx * sx);
         }
     // (b), (c): f and g at the predicted states, time derivative at r = 0
     for (int a1 = 0; a1 < n1; ++a1)

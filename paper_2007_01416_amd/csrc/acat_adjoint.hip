@@ -296,7 +296,7 @@ __device__ __forceinline__ void corner_adjoint(const Phys& ph, double lamx, doub
 #pragma unroll
       for (int l = 0; l < N2; ++l)
         sy = fma(gy[a2 * N2 + l], Xch<NV>::get(xr, stride, gbase + l * N1 + a1, c, true), sy);
-      U[kk - 1][c] = -lamx * sx - lamy * sy;
+      U[kk - 1][c] = fma(-lamy, sy, -lamx * sx);
     }
     buf ^= 1;
     if (kk == T) break;
@@ -659,9 +659,10 @@ hipError_t launch_adj2d(const KProb& pb, const KStep& st, const double* ubo, dou
                                       {"", "adjoint2d_q21", "adjoint2d_q22", "adjoint2d_q23", "adjoint2d_q24"},
                                       {"", "adjoint2d_q31", "adjoint2d_q32", "adjoint2d_q33", "adjoint2d_q34"},
                                       {"", "adjoint2d_q41", "adjoint2d_q42", "adjoint2d_q43", "adjoint2d_q44"}};
-    // the rectangles with two recursions of orders 6 and 8 run them in two
-    // launches (one recursion each, in order on the stream)
-    constexpr bool SPLIT = Q1 != Q2 && Q1 >= 3 && Q2 >= 3;
+    // the rectangles with two recursions of orders 4 and 8 or 6 and 8 run
+    // them in two launches (one recursion each, in order on the stream):
+    // together in one kernel they exceed the register file several times
+    constexpr bool SPLIT = Q1 != Q2 && Q1 >= 2 && Q2 >= 2 && Q1 + Q2 >= 6;
     if constexpr (SPLIT) {
       auto k1 = k_adj2d<FLUX, NV, Q1, Q2, 1>;
       auto k2 = k_adj2d<FLUX, NV, Q1, Q2, 2>;

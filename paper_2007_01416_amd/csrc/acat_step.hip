@@ -413,7 +413,7 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, double lamx, double 
       for (int l = 0; l < N1; ++l) sx = fma(g1x[l], Xch<NV>::get(xr, stride, gbase + a2 * N1 + l, c, false), sx);
 #pragma unroll
       for (int l = 0; l < N2; ++l) sy = fma(g1y[l], Xch<NV>::get(xr, stride, gbase + l * N1 + a1, c, true), sy);
-      Uk[c] = -lamx * sx - lamy * sy;
+      Uk[c] = fma(-lamy, sy, -lamx * sx);
     }
     buf ^= 1;
 #pragma unroll

@@ -45,9 +45,12 @@ __device__ __forceinline__ void flux1d(const Phys& ph, const double (&u)[NV], do
   } else {
     static_assert(NV == 3, "1D Euler has 3 conserved variables");
     const double v = div_rn(u[1], u[0]);
-    const double p = ph.gm1 * (u[2] - 0.5 * (u[1] * v));
+    const double mv = u[1] * v;
+    // E - mv/2 in one fused operation: halving is exact, so this is the
+    // same value as the subtraction of the halved product
+    const double p = ph.gm1 * fma(-0.5, mv, u[2]);
     f[0] = u[1];
-    f[1] = u[1] * v + p;
+    f[1] = mv + p;
     f[2] = v * (u[2] + p);
   }
 }
@@ -81,15 +84,18 @@ __device__ __forceinline__ void flux2d(const Phys& ph, const double (&u)[NV], do
     const double ir = recip(u[0]);
     const double v = u[1] * ir;
     const double w = u[2] * ir;
-    const double p = ph.gm1 * (u[3] - 0.5 * (u[1] * v + u[2] * w));
+    // the product-sums are fused multiply-adds: m v + n w, E - (m v + n w)/2,
+    // m v + p and n w + p, each rounded once
+    const double s = fma(u[1], v, u[2] * w);
+    const double p = ph.gm1 * fma(-0.5, s, u[3]);
     const double ep = u[3] + p;
     f[0] = u[1];
-    f[1] = u[1] * v + p;
+    f[1] = fma(u[1], v, p);
     f[2] = u[2] * v;
     f[3] = v * ep;
     g[0] = u[2];
     g[1] = u[1] * w;
-    g[2] = u[2] * w + p;
+    g[2] = fma(u[2], w, p);
     g[3] = w * ep;
   }
 }
@@ -107,7 +113,7 @@ __device__ __forceinline__ void flux1d_vjp(const Phys& ph, const double (&u)[NV]
     // f = (m, m v + p, v (E + p)), v = m / rho, p = (gamma-1)(E - m v / 2)
     const double rho = u[0], m = u[1], E = u[2];
     const double v = div_rn(m, rho);
-    const double p = ph.gm1 * (E - 0.5 * (m * v));
+    const double p = ph.gm1 * fma(-0.5, m * v, E);
     double mb = fb[0] + fb[1] * v, vb = fb[1] * m + fb[2] * (E + p);
     const double epb = fb[2] * v;
     double Eb = epb;
@@ -134,7 +140,7 @@ __device__ __forceinline__ void flux2d_vjp(const Phys& ph, const double (&u)[NV]
     const double rho = u[0], m = u[1], n = u[2], E = u[3];
     const double ir = recip(rho);
     const double v = m * ir, w = n * ir;
-    const double p = ph.gm1 * (E - 0.5 * (m * v + n * w));
+    const double p = ph.gm1 * fma(-0.5, fma(m, v, n * w), E);
     const double ep = E + p;
     // f = (m, m v + p, n v, v ep), g = (n, m w, n w + p, w ep)
     double mb = fb[0] + fb[1] * v + gb[1] * w;
