@@ -234,8 +234,9 @@ inline double val(const Dual& x) { return x.v; }
 // a*b + c with one rounding.  Every weighted sum of the recursion (the
 // differentiation formulas in space and time, the Taylor predictions and
 // the final flux sum) accumulates in index order with this fused
-// multiply-add, and so do U^k's two directional terms and the 2D Euler
-// flux's product-sums (m v + n w, E - (m v + n w)/2, m v + p, n w + p); all
+// multiply-add, and so do the 2D Euler flux's product-sums (m v + n w,
+// E - (m v + n w)/2, m v + p, n w + p); the 2D U^k is one such chain over the
+// row and then the column, with the weights -lamx gamma and -lamy gamma; all
 // other arithmetic is plain IEEE operations, so the rounding of every
 // operation is fixed.
 inline double mad(double a, double b, double c) { return std::fma(a, b, c); }
@@ -661,13 +662,15 @@ void cat_corner_2d(const oracle_problem& pb, int q1, int q2, int qt, const T (*u
   for (int k = 2; k <= nt; ++k) {
     // (a) U^{k-1}_j = -lamx sum_l gamma^{1,j1}_{q1,l} Fh^{k-2}_{(l,j2)}
     //                 -lamy sum_l gamma^{1,j2}_{q2,l} Gh^{k-2}_{(j1,l)}
+    //     summed as one chain, row terms then column terms, with the
+    //     weights -lamx gamma and -lamy gamma
     for (int a1 = 0; a1 < n1; ++a1)
       for (int a2 = 0; a2 < n2; ++a2)
         for (int c = 0; c < nv; ++c) {
-          T sx = 0.0, sy = 0.0;
-          for (int l = 0; l < n1; ++l) sx = mad(Tb.g1[q1][a1][l], Fh[k - 2][l][a2][c], sx);
-          for (int l = 0; l < n2; ++l) sy = mad(Tb.g1[q2][a2][l], Gh[k - 2][a1][l][c], sy);
-          U[k - 1][a1][a2][c] = mad(-lamy, sy, -lamx * sx);
+          T s = 0.0;
+          for (int l = 0; l < n1; ++l) s = mad(-lamx * Tb.g1[q1][a1][l], Fh[k - 2][l][a2][c], s);
+          for (int l = 0; l < n2; ++l) s = mad(-lamy * Tb.g1[q2][a2][l], Gh[k - 2][a1][l][c], s);
+          U[k - 1][a1][a2][c] = s;
         }
     // (b), (c): f and g at the predicted states, time derivative at r = 0
     for (int a1 = 0; a1 < n1; ++a1)

@@ -374,8 +374,9 @@ __global__ __launch_bounds__(BLOCK) void k_classify2d(KProb pb, KStep st) {
 // series SF = sum_k Fh^{k-1} / k! (DOF) and SG = sum_k Gh^{k-1} / k! (DOG)
 // of its node; the fluxes are the eta-weighted sums of SF over row j2 = 0
 // and of SG over column j1 = 0.  Same fixed rounding as the 1D kernel.
+// g1x, g1y: this node's derivative weights times -lamx and -lamy.
 template <int FLUX, int NV, int Q1, int Q2, int QT, bool DOF, bool DOG>
-__device__ __forceinline__ void corner_pass(const Phys& ph, double lamx, double lamy, const double (&u)[NV],
+__device__ __forceinline__ void corner_pass(const Phys& ph, const double (&u)[NV],
                                             const double (&f0)[NV], const double (&g0)[NV],
                                             const double* g1x, const double* g1y,
                                             double2* xsb0, double2* xsb1, int stride, int& buf, int slot,
@@ -404,16 +405,17 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, double lamx, double 
     Xch<NV>::put(xsw, stride, slot, fc, gc);
     Groups<(2 * Q1) * (2 * Q2)>::sync();
     const double* xr = reinterpret_cast<const double*>(xsw);
-    // U^{kk-1} = -lamx d_x Fh^{kk-2} - lamy d_y Gh^{kk-2} at this node
+    // U^{kk-1} = -lamx d_x Fh^{kk-2} - lamy d_y Gh^{kk-2} at this node: one
+    // chain of fused multiply-adds over the row (x) and then the column (y)
     double Uk[NV];
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
-      double sx = 0.0, sy = 0.0;
+      double s = 0.0;
 #pragma unroll
-      for (int l = 0; l < N1; ++l) sx = fma(g1x[l], Xch<NV>::get(xr, stride, gbase + a2 * N1 + l, c, false), sx);
+      for (int l = 0; l < N1; ++l) s = fma(g1x[l], Xch<NV>::get(xr, stride, gbase + a2 * N1 + l, c, false), s);
 #pragma unroll
-      for (int l = 0; l < N2; ++l) sy = fma(g1y[l], Xch<NV>::get(xr, stride, gbase + l * N1 + a1, c, true), sy);
-      Uk[c] = fma(-lamy, sy, -lamx * sx);
+      for (int l = 0; l < N2; ++l) s = fma(g1y[l], Xch<NV>::get(xr, stride, gbase + l * N1 + a1, c, true), s);
+      Uk[c] = s;
     }
     buf ^= 1;
 #pragma unroll
@@ -483,10 +485,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
   const int nx32 = (int)pb.nx, ny32 = (int)pb.ny, ioff = (int)pb.ioff;
   const uint32_t n1u = (uint32_t)pb.n1;
 
-  // derivative weights in LDS (read at each use rather than held in registers)
+  // derivative weights times -lamx (rows) and -lamy (columns), in LDS (read
+  // at each use rather than held in registers)
   __shared__ double g1s[N1 * N1 + N2 * N2];
   for (int i = tid; i < N1 * N1 + N2 * N2; i += BLOCK)
-    g1s[i] = i < N1 * N1 ? TB.G1[Q1][i / N1][i % N1] : TB.G1[Q2][(i - N1 * N1) / N2][(i - N1 * N1) % N2];
+    g1s[i] = i < N1 * N1 ? -lamx * TB.G1[Q1][i / N1][i % N1]
+                         : -lamy * TB.G1[Q2][(i - N1 * N1) / N2][(i - N1 * N1) % N2];
   __syncthreads();
   const double* g1x = g1s + a1 * N1;
   const double* g1y = g1s + N1 * N1 + a2 * N2;
@@ -513,12 +517,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
       double SF[NV], SG[NV];
       const int slot = g * L + nd;
       if constexpr (Q1 == Q2) {
-        corner_pass<FLUX, NV, Q1, Q2, Q1, true, true>(pb.ph, lamx, lamy, u, f0, g0, g1x, g1y, xs[0], xs[1],
+        corner_pass<FLUX, NV, Q1, Q2, Q1, true, true>(pb.ph, u, f0, g0, g1x, g1y, xs[0], xs[1],
                                                       STRIDE, buf, slot, g * L, a1, a2, SF, SG);
       } else {
-        corner_pass<FLUX, NV, Q1, Q2, Q1, true, false>(pb.ph, lamx, lamy, u, f0, g0, g1x, g1y, xs[0], xs[1],
+        corner_pass<FLUX, NV, Q1, Q2, Q1, true, false>(pb.ph, u, f0, g0, g1x, g1y, xs[0], xs[1],
                                                        STRIDE, buf, slot, g * L, a1, a2, SF, SG);
-        corner_pass<FLUX, NV, Q1, Q2, Q2, false, true>(pb.ph, lamx, lamy, u, f0, g0, g1x, g1y, xs[0], xs[1],
+        corner_pass<FLUX, NV, Q1, Q2, Q2, false, true>(pb.ph, u, f0, g0, g1x, g1y, xs[0], xs[1],
                                                        STRIDE, buf, slot, g * L, a1, a2, SF, SG);
       }
       // F_c = sum_l eta_l SF_(l,0),c and G_c = sum_l eta_l SG_(0,l),c on 2 NV lanes
