@@ -260,13 +260,19 @@ __global__ __launch_bounds__(BLOCK) void k_update1d(KProb pb, KStep st) {
 }
 
 // ======================================================================= 2D
-// One block per 16 x 16 tile of corners, one thread per corner.
+// One block per 16 x 16 tile of corners, one thread per corner.  The cells
+// the tile's x- and y-stencils read (the tile and a halo of G - 1 below and
+// G beyond it in each direction) are staged in LDS once per block.
 template <int FLUX, int NV, int P>
 __global__ __launch_bounds__(BLOCK) void k_classify2d(KProb pb, KStep st) {
   constexpr int G = P > 2 ? P : 2;
+  constexpr int TW = TILE_X + 2 * G - 1, TH = TILE_Y + 2 * G - 1;
+  static_assert(TILE_X * TILE_Y == BLOCK, "one thread per corner of the tile");
+  __shared__ double tile[NV][TH][TW];
   const int64_t ntx = (pb.n1 + TILE_X - 1) / TILE_X;
-  const int64_t e1 = (blockIdx.x % ntx) * TILE_X + threadIdx.x % TILE_X;
-  const int64_t e2 = (blockIdx.x / ntx) * TILE_Y + threadIdx.x / TILE_X;
+  const int tx = threadIdx.x % TILE_X, ty = threadIdx.x / TILE_X;
+  const int64_t e1 = (blockIdx.x % ntx) * TILE_X + tx;
+  const int64_t e2 = (blockIdx.x / ntx) * TILE_Y + ty;
   const bool inside = e1 < pb.n1 && e2 < pb.n2;
   const int64_t e = e2 * pb.n1 + e1;
   const int64_t nx = pb.nx, ny = pb.ny;
@@ -274,6 +280,23 @@ __global__ __launch_bounds__(BLOCK) void k_classify2d(KProb pb, KStep st) {
   const int64_t i2 = inside ? e2 + pb.ioff : 0;
   const bool needF = i2 >= 0, needG = i1 >= 0;
   const bool valid = inside && (needF || needG);
+  if (!st.replay) {
+    // tile cell (a, b) is cell (Y0 + a, X0 + b) before the boundary mapping;
+    // cells beyond what the grid's last corner reads are not loaded (so the
+    // periodic wrap stays within one period)
+    const int64_t X0 = (blockIdx.x % ntx) * TILE_X + pb.ioff - G + 1;
+    const int64_t Y0 = (blockIdx.x / ntx) * TILE_Y + pb.ioff - G + 1;
+    const int64_t Xmax = pb.n1 - 1 + pb.ioff + G, Ymax = pb.n2 - 1 + pb.ioff + G;
+    for (int t = threadIdx.x; t < TH * TW; t += BLOCK) {
+      const int a = t / TW, b = t - a * TW;
+      if (X0 + b <= Xmax && Y0 + a <= Ymax) {
+        const int64_t x = bc_index(X0 + b, nx, pb.bc), y = bc_index(Y0 + a, ny, pb.bc);
+#pragma unroll
+        for (int c = 0; c < NV; ++c) tile[c][a][b] = st.u[(c * ny + y) * nx + x];
+      }
+    }
+    __syncthreads();
+  }
   int q1 = 1, q2 = 1;
   double sx = 0.0, sy = 0.0;
   if (valid) {
@@ -289,13 +312,11 @@ __global__ __launch_bounds__(BLOCK) void k_classify2d(KProb pb, KStep st) {
       }
     } else {
       double v[NV][2 * G];
-      // x-interface (i1 + 1/2, i2)
+      // x-interface (i1 + 1/2, i2): cells (i2, i1 - G + 1 .. i1 + G)
 #pragma unroll
-      for (int a = 0; a < 2 * G; ++a) {
-        const int64_t x = bc_index(i1 - G + 1 + a, nx, pb.bc);
+      for (int a = 0; a < 2 * G; ++a)
 #pragma unroll
-        for (int c = 0; c < NV; ++c) v[c][a] = st.u[(c * ny + r2) * nx + x];
-      }
+        for (int c = 0; c < NV; ++c) v[c][a] = tile[c][ty + G - 1][tx + a];
       if (st.cfl_mode) {   // the corner's own cell (every cell is the cell of one corner)
         double uc[NV];
 #pragma unroll
@@ -324,13 +345,11 @@ __global__ __launch_bounds__(BLOCK) void k_classify2d(KProb pb, KStep st) {
         st.psix[ex] = psi1;
         st.alx[ex] = al;
       }
-      // y-interface (i1, i2 + 1/2)
+      // y-interface (i1, i2 + 1/2): cells (i2 - G + 1 .. i2 + G, i1)
 #pragma unroll
-      for (int a = 0; a < 2 * G; ++a) {
-        const int64_t y = bc_index(i2 - G + 1 + a, ny, pb.bc);
+      for (int a = 0; a < 2 * G; ++a)
 #pragma unroll
-        for (int c = 0; c < NV; ++c) v[c][a] = st.u[(c * ny + y) * nx + r1];
-      }
+        for (int c = 0; c < NV; ++c) v[c][a] = tile[c][ty + a][tx + G - 1];
       q2 = Select<NV, G, P>::run(v, pb.eps, pb.theta, (pb.flags & FLAG_PSI2_MODIFIED) != 0);
       if (needG) {
         double psi1 = -1.0, al = -1.0;
