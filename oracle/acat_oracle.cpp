@@ -235,9 +235,8 @@ inline double val(const Dual& x) { return x.v; }
 // differentiation formulas in space and time, the Taylor predictions and
 // the final flux sum) accumulates in index order with this fused
 // multiply-add, and so do the 2D Euler flux's product-sums (m v + n w,
-// E - (m v + n w)/2, m v + p, n w + p); U^k is one such chain with the
-// weights -lam gamma (in 2D over the row and then the column, with -lamx gamma
-// and -lamy gamma); all
+// E - (m v + n w)/2, m v + p, n w + p); the 2D U^k is one such chain over the
+// row and then the column, with the weights -lamx gamma and -lamy gamma; all
 // other arithmetic is plain IEEE operations, so the rounding of every
 // operation is fixed.
 inline double mad(double a, double b, double c) { return std::fma(a, b, c); }
@@ -460,13 +459,12 @@ void cat_flux_1d(const oracle_problem& pb, int p, const T (*u)[VMAX], double lam
   T U[NMAX][NMAX][VMAX];    // U[l][a][c]  = dt^l u~^(l) at node a
   for (int a = 0; a < nn; ++a) flux_f(pb, u[a], Fh[0][a]);
   for (int k = 2; k <= 2 * p; ++k) {
-    // (a) U^{k-1}_j = -lam * sum_l gamma^{1,j}_{p,l} Fh^{k-2}_l, summed with
-    //     the weights -lam gamma
+    // (a) U^{k-1}_j = -lam * sum_l gamma^{1,j}_{p,l} Fh^{k-2}_l
     for (int a = 0; a < nn; ++a)
       for (int c = 0; c < nv; ++c) {
         T s = 0.0;
-        for (int l = 0; l < nn; ++l) s = mad(-lam * Tb.g1[p][a][l], Fh[k - 2][l][c], s);
-        U[k - 1][a][c] = s;
+        for (int l = 0; l < nn; ++l) s = mad(Tb.g1[p][a][l], Fh[k - 2][l][c], s);
+        U[k - 1][a][c] = -lam * s;
       }
     // (b) flux at the Taylor-predicted states at the time nodes r, and
     // (c) its (k-1)-th time derivative at r = 0.

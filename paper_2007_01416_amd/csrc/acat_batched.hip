@@ -93,9 +93,6 @@ __global__ __launch_bounds__(BS) void k_flux_b(KBatch bt, KBStep st) {
     double u[NV];
 #pragma unroll
     for (int c = 0; c < NV; ++c) u[c] = valid ? ub[c * bt.ncell + node] : 1.0;
-    double w1[L];   // the derivative weights times this problem's -lam
-#pragma unroll
-    for (int l = 0; l < L; ++l) w1[l] = -lam * g1[l];
 
     double fh0[NV], cur[NV], S[NV];
     flux1d<FLUX, NV>(bt.ph, u, fh0);
@@ -119,8 +116,8 @@ __global__ __launch_bounds__(BS) void k_flux_b(KBatch bt, KBStep st) {
       for (int c = 0; c < NV; ++c) {
         double sacc = 0.0;
 #pragma unroll
-        for (int l = 0; l < L; ++l) sacc = fma(w1[l], xs[buf][c][g * SL + l], sacc);
-        Uk[c] = sacc;
+        for (int l = 0; l < L; ++l) sacc = fma(g1[l], xs[buf][c][g * SL + l], sacc);
+        Uk[c] = -lam * sacc;
       }
       buf ^= 1;
 #pragma unroll

@@ -116,9 +116,9 @@ __global__ __launch_bounds__(BLOCK) void k_flux1d(KProb pb, KStep st) {
   const double lam = step_dt(st) / pb.dx;
   const int64_t nx = pb.nx, nI = pb.nIx;
 
-  double g1[L];   // this node's derivative weights times -lam
+  double g1[L];
 #pragma unroll
-  for (int l = 0; l < L; ++l) g1[l] = -lam * TB.G1[p][a][l];
+  for (int l = 0; l < L; ++l) g1[l] = TB.G1[p][a][l];
 
   int buf = 0;
   const Slice sl(st.counts, st.list, p - 1);
@@ -153,15 +153,14 @@ __global__ __launch_bounds__(BLOCK) void k_flux1d(KProb pb, KStep st) {
 #pragma unroll
         for (int c = 0; c < NV; ++c) xs[buf][c][slot] = cur[c];
         Grp::sync();
-        // U^{kk-1} = -lambda * (spatial derivative of Fh^{kk-2} at this node),
-        // one chain with the weights -lambda gamma
+        // U^{kk-1} = -lambda * (spatial derivative of Fh^{kk-2} at this node)
         double Uk[NV];
 #pragma unroll
         for (int c = 0; c < NV; ++c) {
           double sacc = 0.0;
 #pragma unroll
           for (int l = 0; l < L; ++l) sacc = fma(g1[l], xs[buf][c][g * SL + l], sacc);
-          Uk[c] = sacc;
+          Uk[c] = -lam * sacc;
         }
         buf ^= 1;
 #pragma unroll
