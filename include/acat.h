@@ -219,11 +219,14 @@ acat_status acat_batch_init(const acat_batch* batch, void* workspace, size_t wor
 acat_status acat_step_batched(const acat_batch* batch, const double* u_in, double* u_out, const double* dt_dev,
                               void* workspace, size_t workspace_bytes, void* stream);
 /* The same step, and then dt_dev[b] = the time step that acat_batched_cfl_dt
- * (cfl) gives for u_out, bit for bit: the update pass reduces each problem's
- * maximum wave speed of the new state (atomic maxima on the bit patterns,
- * exact in any order), so no extra pass over u_out is made.  dt_dev is read
- * as this step's time steps before it is overwritten; cfl > 0.  The first
- * dt_dev comes from acat_batched_cfl_dt. */
+ * (cfl) gives for u_out, bit for bit: the update pass reduces the new
+ * state's wave speeds (one partial maximum per wavefront that lies inside
+ * one problem, atomic maxima on the bit patterns for wavefronts that
+ * straddle problems; max is exact in any order) and a last small launch
+ * folds them per problem, so no extra pass over u_out is made.  dt_dev is
+ * read as this step's time steps before it is overwritten; cfl > 0.  The
+ * first dt_dev comes from acat_batched_cfl_dt.  Errors as acat_step_batched,
+ * and ACAT_ERR_ARG for cfl <= 0 or NaN. */
 acat_status acat_step_batched_cfl(const acat_batch* batch, const double* u_in, double* u_out, double* dt_dev,
                                   double cfl, void* workspace, size_t workspace_bytes, void* stream);
 /* dt_dev[b] = cfl dx[b] / (max spectral radius over problem b of u). */
