@@ -39,8 +39,10 @@
 //     J_{q2} x J_{q2} (the square algorithm of Sec. 4 per direction);
 //   * boundaries: periodic wrap or transmissive zeroth-order extrapolation.
 //   * rounding: the paper fixes none.  Sums run in the index order the paper
-//     writes them; the weighted sums of the recursion use fused multiply-add
-//     (see mad below); nothing else is contracted.  With one fixed rounding,
+//     writes them; the weighted sums of the recursion, the 2D U^k (one chain
+//     with the weights -lamx gamma and -lamy gamma) and the 2D Euler flux's
+//     product-sums use fused multiply-add (see mad below); nothing else is
+//     contracted.  With one fixed rounding,
 //     an implementation that follows it reproduces these results bit for
 //     bit, which matters because the limiter and the admissibility test are
 //     discontinuous in the data.
