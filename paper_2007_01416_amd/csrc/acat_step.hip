@@ -569,6 +569,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
         acc[tk] = t;
       }
       buf ^= 1;   // the assembly may still read this buffer
+      if constexpr (Q1 == 1 && Q2 == 1) {
+        // the FL-CAT2 blends of a (1,1) corner read the corner's own nodes:
+        // states and point fluxes pass through both buffers, (u, f) and (g, g)
+        Grp::sync();   // the assembly has read its buffer
+        Xch<NV>::put(xs[0], STRIDE, slot, u, f0);
+        Xch<NV>::put(xs[1], STRIDE, slot, g0, g0);
+        Grp::sync();
+      }
       // finish and store the assembled components
 #pragma unroll
       for (int tk = 0; tk < 2; ++tk) {
@@ -589,13 +597,29 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
           const double psi = isG ? st.psiy[ei] : st.psix[ei];
           const double al = isG ? st.aly[ei] : st.alx[ei];
           double uL[NV], uR[NV], fL[NV], gL[NV], fR[NV], gR[NV];
+          if constexpr (Q1 == 1 && Q2 == 1) {
+            // nodes (0,0) and (1,0) (x) or (0,1) (y) of this corner
+            const double* p0 = reinterpret_cast<const double*>(xs[0]);
+            const double* p1 = reinterpret_cast<const double*>(xs[1]);
+            const int sl0 = g * L, slr = g * L + (isG ? N1 : 1);
 #pragma unroll
-          for (int cc = 0; cc < NV; ++cc) {
-            uL[cc] = st.u[(cc * ny + y0) * nx + x0];
-            uR[cc] = st.u[(cc * ny + yr) * nx + xr];
+            for (int cc = 0; cc < NV; ++cc) {
+              uL[cc] = Xch<NV>::get(p0, STRIDE, sl0, cc, false);
+              uR[cc] = Xch<NV>::get(p0, STRIDE, slr, cc, false);
+              fL[cc] = Xch<NV>::get(p0, STRIDE, sl0, cc, true);
+              fR[cc] = Xch<NV>::get(p0, STRIDE, slr, cc, true);
+              gL[cc] = Xch<NV>::get(p1, STRIDE, sl0, cc, false);
+              gR[cc] = Xch<NV>::get(p1, STRIDE, slr, cc, false);
+            }
+          } else {
+#pragma unroll
+            for (int cc = 0; cc < NV; ++cc) {
+              uL[cc] = st.u[(cc * ny + y0) * nx + x0];
+              uR[cc] = st.u[(cc * ny + yr) * nx + xr];
+            }
+            flux2d<FLUX, NV>(pb.ph, uL, fL, gL);
+            flux2d<FLUX, NV>(pb.ph, uR, fR, gR);
           }
-          flux2d<FLUX, NV>(pb.ph, uL, fL, gL);
-          flux2d<FLUX, NV>(pb.ph, uR, fR, gR);
           double ul = 0.0, ur = 0.0, hl = 0.0, hr = 0.0;
 #pragma unroll
           for (int cc = 0; cc < NV; ++cc)
@@ -612,6 +636,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
         if (isG) st.Gy[((int64_t)c * pb.nIy + (i2 - ioff)) * nx + i1] = v;
         else st.Fx[((int64_t)c * ny + i2) * pb.nIx + (i1 - ioff)] = v;
       }
+      if constexpr (Q1 == 1 && Q2 == 1) Grp::sync();   // the blends have read both buffers
     }
   }
 }
