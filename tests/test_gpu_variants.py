@@ -87,11 +87,13 @@ def test_square_variant_every_class_forced(acat, q1, q2, bc):
 
 @pytest.mark.parametrize("bc", ["periodic", "transmissive"])
 @pytest.mark.parametrize("flags", [0, LF, HLL])
-def test_order1_corners_forced_every_first_order_flux(acat, flags, bc):
-    """Every corner of class (1,1) with blend weights in (0,1), so that both
-    the CAT2 part and the first-order flux enter (the (1,1) kernel takes the
-    blend's states and point fluxes from its own node lanes); Rusanov,
-    Lax-Friedrichs and HLL, both boundaries, bitwise against the oracle."""
+@pytest.mark.parametrize("q1,q2", [(1, 1), (1, 2), (2, 1), (1, 3), (3, 1)])
+def test_order1_corners_forced_every_first_order_flux(acat, q1, q2, flags, bc):
+    """Every corner of class (q1, q2) with an order-1 direction and blend
+    weights in (0,1), so that both the CAT2 part and the first-order flux
+    enter (the small classes take the blend's states and point fluxes from
+    their own node lanes, the others reload them); Rusanov, Lax-Friedrichs
+    and HLL, both boundaries, bitwise against the oracle."""
     from test_gpu_adjoint import gpu_decisions
     nx, ny = 23, 19
     x = (np.arange(nx) + 0.5) / nx
@@ -101,17 +103,17 @@ def test_order1_corners_forced_every_first_order_flux(acat, flags, bc):
     v, wv = 0.3 + 0.1 * np.sin(2 * np.pi * Y), -0.2 + 0.1 * np.cos(2 * np.pi * X)
     p = 1 + 0.1 * np.sin(2 * np.pi * (X + Y)) + 0.5 * (Y > 0.4)
     u = np.stack([rho, rho * v, rho * wv, p / 0.4 + 0.5 * rho * (v * v + wv * wv)])
-    po, pg = both_problems(2, 4, nx, "euler", 2, bc, 1.0 / nx, ny=ny, dy=1.0 / ny, flags=flags)
+    po, pg = both_problems(2, 4, nx, "euler", 3, bc, 1.0 / nx, ny=ny, dy=1.0 / ny, flags=flags)
     nIx, nIy = po.n_interfaces
     rng = np.random.default_rng(31 + flags)
-    r = dict(ordx=np.ones((ny, nIx), np.int8), ordy=np.ones((nIy, nx), np.int8),
+    r = dict(ordx=np.full((ny, nIx), q1, np.int8), ordy=np.full((nIy, nx), q2, np.int8),
              psix=rng.uniform(0.1, 0.9, (ny, nIx)), psiy=rng.uniform(0.1, 0.9, (nIy, nx)),
              alx=rng.uniform(1.5, 3.0, (ny, nIx)), aly=rng.uniform(1.5, 3.0, (nIy, nx)))
     maps = (r["ordx"], r["ordy"], r["psix"], r["psiy"], r["alx"], r["aly"])
     dt = oracle.dt_cfl(po, u, 0.4)
     want = oracle.step2d(po, u, dt, maps=maps)["u"]
     got = acat.step_replay(pg, torch.from_numpy(u).cuda(), dt, gpu_decisions(acat, pg, po, r)).cpu().numpy()
-    assert np.array_equal(got, want), (flags, bc, np.abs(got - want).max())
+    assert np.array_equal(got, want), (q1, q2, flags, bc, np.abs(got - want).max())
 
 
 def test_variants_lockstep_advection2d_roe(acat):
