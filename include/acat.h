@@ -139,6 +139,27 @@ acat_status acat_step_cfl(const acat_problem* prob, const double* u_in, double* 
                           double* t_dev, double* dt_dev, void* workspace, size_t workspace_bytes,
                           const acat_decisions* dec, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Allocation-free step, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  The same step as acat_step (same kernels, same results bit
+ * for bit), with the workspace taken from one fixed array of
+ * ACAT_NOALLOC_SCRATCH_BYTES in the library's static device memory, one per
+ * GPU, held until the process ends.  The caller still owns u_in, u_out, the
+ * optional decision maps and dt_dev; the call allocates and frees nothing.
+ *   - ACAT_ERR_WORKSPACE when acat_workspace_size(prob) exceeds
+ *     ACAT_NOALLOC_SCRATCH_BYTES (64 MiB: e.g. 2D Euler up to about 800^2
+ *     cells, 1D Euler up to about 1.4 million cells); other errors as
+ *     acat_step.
+ *   - Every call on one GPU shares that GPU's array, which keeps the last
+ *     call's contents (nothing in it needs to start at zero).  Calls that
+ *     overlap on one GPU (concurrent streams, or threads) race on it: the
+ *     caller serialises them.
+ * --------------------------------------------------------------------- */
+#define ACAT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+acat_status acat_step_noalloc(const acat_problem* prob, const double* u_in, double* u_out, double dt,
+                              const double* dt_dev, const acat_decisions* dec, void* stream);
+
 /* The same step with the decisions frozen to `dec` (orders, psi1, alpha):
  * a smooth function of u_in, the forward map differentiated by
  * acat_step_adjoint. */

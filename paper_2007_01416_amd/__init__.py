@@ -55,6 +55,8 @@ _SIGS = {
     "acat_workspace_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
     "acat_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p],
+    "acat_step_noalloc": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                          ctypes.c_void_p, ctypes.c_void_p],
     "acat_step_replay": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p],
     "acat_step_cfl": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
@@ -211,6 +213,23 @@ def step(prob: Problem, u: torch.Tensor, dt, out: torch.Tensor = None, ws: torch
     dc = ctypes.byref(dec.c()) if dec is not None else None
     _check(load().acat_step(ctypes.byref(prob.c()), _ptr(u), _ptr(out), dtv, dtp, _ptr(ws), ws.numel(), dc,
                             _stream(stream)), "acat_step")
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # ACAT_NOALLOC_SCRATCH_BYTES
+
+
+def step_noalloc(prob: Problem, u: torch.Tensor, dt, out: torch.Tensor, dec: Decisions = None,
+                 stream=None) -> torch.Tensor:
+    """acat_step with the library's static per-device workspace: the call
+    allocates nothing (out is the caller's).  Calls on one device share that
+    workspace, so overlapping calls race."""
+    _check_state(prob, u, "u")
+    _check_state(prob, out, "out")
+    dtv, dtp = (float(dt), None) if not torch.is_tensor(dt) else (0.0, _ptr(dt))
+    dc = ctypes.byref(dec.c()) if dec is not None else None
+    _check(load().acat_step_noalloc(ctypes.byref(prob.c()), _ptr(u), _ptr(out), dtv, dtp, dc, _stream(stream)),
+           "acat_step_noalloc")
     return out
 
 

@@ -1,6 +1,7 @@
 // C ABI of the ACAT library: argument checks, workspace layout, launches.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstring>
 #include <vector>
 
@@ -129,6 +130,23 @@ uint32_t* status_ptr() {
     ptrs[dev] = static_cast<uint32_t*>(p);
   }
   return ptrs[dev];
+}
+
+// Workspace of acat_step_noalloc: one fixed array per device, in the
+// library's own static memory, held until the process ends.  Host code uses
+// the device address obtained from the runtime, never the array's name.
+__device__ __align__(256) unsigned char scratch[ACAT_NOALLOC_SCRATCH_BYTES];
+
+void* noalloc_scratch_ptr() {
+  static std::atomic<void*> ptrs[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  void* p = ptrs[dev].load(std::memory_order_acquire);
+  if (!p) {
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    ptrs[dev].store(p, std::memory_order_release);
+  }
+  return p;
 }
 
 bool overlaps(const void* a, const void* b, size_t n) {
@@ -350,6 +368,16 @@ acat_status acat_step(const acat_problem* prob, const double* u_in, double* u_ou
                       const double* dt_dev, void* workspace, size_t workspace_bytes, const acat_decisions* dec,
                       void* stream) {
   return do_step(prob, u_in, u_out, dt, dt_dev, workspace, workspace_bytes, dec, false, stream);
+}
+
+acat_status acat_step_noalloc(const acat_problem* prob, const double* u_in, double* u_out, double dt,
+                              const double* dt_dev, const acat_decisions* dec, void* stream) {
+  acat_status rc = check_problem(prob);
+  if (rc != ACAT_OK) return rc;
+  if (layout(make_kprob(prob)).total > ACAT_NOALLOC_SCRATCH_BYTES) return ACAT_ERR_WORKSPACE;
+  void* ws = noalloc_scratch_ptr();
+  if (!ws) return ACAT_ERR_DEVICE;
+  return do_step(prob, u_in, u_out, dt, dt_dev, ws, ACAT_NOALLOC_SCRATCH_BYTES, dec, false, stream);
 }
 
 acat_status acat_step_cfl(const acat_problem* prob, const double* u_in, double* u_out, double cfl, double t_final,

@@ -259,3 +259,14 @@ def test_empty_batch_is_rejected(lib):
                     dx.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     nb = ctypes.c_size_t(0)
     assert lib.acat_batch_workspace_size(ctypes.byref(b), ctypes.byref(nb)) == -2
+
+
+def test_noalloc_rejects_problems_beyond_its_static_workspace(lib):
+    """acat_step_noalloc refuses, before any launch, a problem whose
+    workspace exceeds the static array (2048^2 2D Euler: 262 MB)."""
+    big = _prob(dim=2, nvar=4, nx=2048, ny=2048, dy=0.01, P=3)
+    n = ctypes.c_size_t(0)
+    assert lib.acat_workspace_size(ctypes.byref(big.c()), ctypes.byref(n)) == 0
+    assert n.value > 64 << 20
+    assert lib.acat_step_noalloc(ctypes.byref(big.c()), None, None, 1e-3, None, None, None) == -6
+    assert lib.acat_step_noalloc(ctypes.byref(_prob(P=0).c()), None, None, 1e-3, None, None, None) == -2
