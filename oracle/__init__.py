@@ -3,8 +3,18 @@
 TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
 with the HIP library in ``paper_2007_01416_amd``: its arithmetic lives in
-``acat_oracle.cpp`` (plain C++ loops, fp64, no FMA contraction) and in
-``rational.py`` (exact rationals for tiny scalar grids).
+``acat_oracle.cpp`` (plain C++ loops, fp64, built with -ffp-contract=off so
+the compiler fuses nothing) and in ``rational.py`` (exact rationals for tiny
+scalar grids).
+
+Two frozen rounding modes (``Problem.rounding``): "fixed" (default) writes
+the recursion's weighted sums, the 2D U^k and the 2D Euler flux's
+product-sums as explicit fused multiply-adds in index order and sums the
+final flux node by node; "plain" rounds every product and every sum
+separately, in the order the paper writes the formulas (final flux k-outer,
+U^k as -lamx sum - lamy sum, velocities m / rho).  The two agree to rounding;
+parity at a tolerance against "plain" checks arithmetic whose rounding no
+implementation chose.
 
 Functions here marshal numpy arrays to the C++ oracle and implement the time
 step rules (1D: dt = CFL dx / max spectral radius; 2D: Sec. 5.5,
@@ -28,10 +38,11 @@ BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
 # variants (Problem.flags): first-order flux Lax-Friedrichs / HLL instead of
 # Rusanov, modified p = 2 indicator, Roe-speed upwind psi^1 (scalar laws)
 FLAG_FLO_LF, FLAG_FLO_HLL, FLAG_PSI2_MODIFIED, FLAG_PSI1_ROE, FLAG_SQUARE_2D = 1, 2, 4, 8, 16
+_FLAG_PLAIN_ROUNDING = 256      # set from Problem.rounding == "plain"
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with g++ (-O2, no FMA contraction, OpenMP)."""
+    """Compile the oracle with g++ (-O2, no implicit FMA contraction, OpenMP)."""
     if force or not os.path.exists(_LIB):
         cmd = ["g++", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared", "-fPIC",
                "-o", _LIB + ".tmp", _SRC]
@@ -67,9 +78,13 @@ class Problem:
     eps: float = 1e-12
     theta: float = 0.5
     flags: int = 0      # FLAG_* variants (default method: 0)
+    rounding: str = "fixed"   # "fixed" or "plain" (see the module docstring)
 
     def c(self) -> _Problem:
-        return _Problem(self.dim, self.nvar, self.nx, self.ny, self.flux, self.P, self.bc, self.flags,
+        if self.rounding not in ("fixed", "plain"):
+            raise ValueError(f"rounding {self.rounding!r}")
+        flags = self.flags | (_FLAG_PLAIN_ROUNDING if self.rounding == "plain" else 0)
+        return _Problem(self.dim, self.nvar, self.nx, self.ny, self.flux, self.P, self.bc, flags,
                         self.gamma, self.ax, self.ay, self.dx, self.dy, self.eps, self.theta)
 
     @property
@@ -102,6 +117,8 @@ def lib():
         L.oracle_step2d.argtypes = [P(_Problem), d, d, ctypes.c_double, ctypes.c_int, i8, i8, d, d, d, d, d, d,
                                     ctypes.c_int]
         L.oracle_step2d_jvp.argtypes = [P(_Problem), d, d, d, d, ctypes.c_double, i8, i8, d, d, d, d, ctypes.c_int]
+        L.oracle_step2d_jvp2.argtypes = [P(_Problem), d, d, d, d, ctypes.c_double, i8, i8, d, d, d, d, ctypes.c_int,
+                                         ctypes.c_int]
         L.oracle_update_cells.argtypes = [P(_Problem), d, ctypes.c_double, ctypes.c_int64, i64, d, i8, ctypes.c_int]
         L.oracle_max_speed.argtypes = [P(_Problem), d, d]
         _lib = L
@@ -217,6 +234,31 @@ def jvp(prob: Problem, u, du, dt: float, maps, nthreads: int = 0):
         i8 = ctypes.c_int8
         _chk(lib().oracle_step2d_jvp(ctypes.byref(pc), _p(u), _p(du), _p(out), _p(dout), dt, _p(ox, i8),
                                      _p(oy, i8), _p(px), _p(py), _p(ax), _p(ay), nthreads))
+    return out, dout
+
+
+def jvp2(prob: Problem, u, du2, dt: float, maps=None, nthreads: int = 0):
+    """2D tangent of the frozen replay step along two directions at once
+    (du2 of shape (2, nvar, ny, nx)): returns (u_out, du_out of the same
+    shape).  maps=None: the step's own decisions (taken from the values)."""
+    u = _state(prob, u)
+    if prob.dim != 2:
+        raise ValueError("jvp2 is 2D only")
+    du2 = np.ascontiguousarray(du2, dtype=np.float64)
+    if du2.shape != (2,) + u.shape:
+        raise ValueError(f"directions {du2.shape} != {(2,) + u.shape}")
+    out = np.empty_like(u); dout = np.empty_like(du2)
+    pc = prob.c()
+    decide = maps is None
+    if decide:
+        nIx, nIy = prob.n_interfaces
+        maps = (np.zeros((prob.ny, nIx), np.int8), np.zeros((nIy, prob.nx), np.int8), np.zeros((prob.ny, nIx)),
+                np.zeros((nIy, prob.nx)), np.zeros((prob.ny, nIx)), np.zeros((nIy, prob.nx)))
+    ox, oy, px, py, ax, ay = [np.ascontiguousarray(m, dtype=t) for m, t in
+                              zip(maps, (np.int8, np.int8) + (np.float64,) * 4)]
+    i8 = ctypes.c_int8
+    _chk(lib().oracle_step2d_jvp2(ctypes.byref(pc), _p(u), _p(du2), _p(out), _p(dout), dt, _p(ox, i8), _p(oy, i8),
+                                  _p(px), _p(py), _p(ax), _p(ay), nthreads, 1 if decide else 0))
     return out, dout
 
 

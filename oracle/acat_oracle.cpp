@@ -38,14 +38,16 @@
 //     Variant FLAG_SQUARE_2D: F on the square J_{q1} x J_{q1}, G on
 //     J_{q2} x J_{q2} (the square algorithm of Sec. 4 per direction);
 //   * boundaries: periodic wrap or transmissive zeroth-order extrapolation.
-//   * rounding: the paper fixes none.  Sums run in the index order the paper
-//     writes them; the weighted sums of the recursion, the 2D U^k (one chain
-//     with the weights -lamx gamma and -lamy gamma) and the 2D Euler flux's
-//     product-sums use fused multiply-add (see mad below); nothing else is
-//     contracted.  With one fixed rounding,
-//     an implementation that follows it reproduces these results bit for
-//     bit, which matters because the limiter and the admissibility test are
-//     discontinuous in the data.
+//   * rounding: the paper fixes none.  Two frozen modes (see mad below):
+//     "fixed" (default) writes the weighted sums of the recursion, the 2D U^k
+//     (one chain with the weights -lamx gamma and -lamy gamma) and the 2D
+//     Euler flux's product-sums as fused multiply-adds in index order;
+//     "plain" rounds every operation on its own in the order the paper writes
+//     the formulas.  Nothing is contracted implicitly (-ffp-contract=off).
+//     An implementation that follows the fixed mode reproduces its results
+//     bit for bit, which matters because the limiter and the admissibility
+//     test are discontinuous in the data; the plain mode checks an
+//     implementation at a tolerance against a rounding it did not choose.
 //
 // Pins (tests/test_oracle_*.py, tests/golden/): exact-rational coefficient
 // identities and tables, closed forms (CAT2 in 1D and 2D, the order-2p
@@ -149,8 +151,9 @@ struct Tables {
   double d1[PMAX + 1][2 * PMAX + 1];
   // taylor[r+PMAX-1][l] = r^l / l! for the local time nodes r.
   double taylor[NMAX][NMAX];
-  // inverse factorials 1/k!
+  // inverse factorials 1/k! and factorials k! (exact in binary64 for k <= 12)
   double invfact[NMAX + 1];
+  double fact[NMAX + 1];
   // (2p-1)!
   double fact2pm1[PMAX + 1];
 };
@@ -201,6 +204,7 @@ Tables build_tables() {
   for (int k = 0; k <= NMAX; ++k) {
     if (k > 0) f *= k;
     T.invfact[k] = Rat(1, f).to_double();
+    T.fact[k] = Rat(f).to_double();
   }
   return T;
 }
@@ -211,40 +215,112 @@ const Tables& tables() {
 }
 
 // ---------------------------------------------------------------------------
-// Dual numbers (value + one tangent) for the forward-mode JVP oracle.
-// ---------------------------------------------------------------------------
-struct Dual {
-  double v, d;
-  Dual(double v_ = 0, double d_ = 0) : v(v_), d(d_) {}
+// Dual numbers (value + K tangents) for the forward-mode JVP oracle: each
+// tangent follows the derivative rules of the operations on the value.
+template <int K>
+struct DualN {
+  double v, d[K];
+  DualN(double v_ = 0) : v(v_) {
+    for (int k = 0; k < K; ++k) d[k] = 0.0;
+  }
 };
-inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
-inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
-inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
-inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
-inline Dual operator/(Dual a, Dual b) {
-  double q = a.v / b.v;
-  return Dual(q, (a.d - q * b.d) / b.v);
+template <int K>
+inline DualN<K> operator+(const DualN<K>& a, const DualN<K>& b) {
+  DualN<K> r(a.v + b.v);
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] + b.d[k];
+  return r;
 }
-inline Dual operator*(double s, Dual b) { return Dual(s * b.v, s * b.d); }
-inline Dual operator/(double s, Dual b) { return Dual(s, 0.0) / b; }
-inline Dual operator*(Dual b, double s) { return Dual(b.v * s, b.d * s); }
-inline Dual operator+(Dual a, double s) { return Dual(a.v + s, a.d); }
-inline Dual operator-(double s, Dual a) { return Dual(s - a.v, -a.d); }
+template <int K>
+inline DualN<K> operator-(const DualN<K>& a, const DualN<K>& b) {
+  DualN<K> r(a.v - b.v);
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] - b.d[k];
+  return r;
+}
+template <int K>
+inline DualN<K> operator-(const DualN<K>& a) {
+  DualN<K> r(-a.v);
+  for (int k = 0; k < K; ++k) r.d[k] = -a.d[k];
+  return r;
+}
+template <int K>
+inline DualN<K> operator*(const DualN<K>& a, const DualN<K>& b) {
+  DualN<K> r(a.v * b.v);
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  return r;
+}
+template <int K>
+inline DualN<K> operator/(const DualN<K>& a, const DualN<K>& b) {
+  const double q = a.v / b.v;
+  DualN<K> r(q);
+  for (int k = 0; k < K; ++k) r.d[k] = (a.d[k] - q * b.d[k]) / b.v;
+  return r;
+}
+template <int K>
+inline DualN<K> operator*(double s, const DualN<K>& b) {
+  DualN<K> r(s * b.v);
+  for (int k = 0; k < K; ++k) r.d[k] = s * b.d[k];
+  return r;
+}
+template <int K>
+inline DualN<K> operator/(double s, const DualN<K>& b) { return DualN<K>(s) / b; }
+template <int K>
+inline DualN<K> operator/(const DualN<K>& a, double s) { return a / DualN<K>(s); }
+template <int K>
+inline DualN<K> operator*(const DualN<K>& b, double s) {
+  DualN<K> r(b.v * s);
+  for (int k = 0; k < K; ++k) r.d[k] = b.d[k] * s;
+  return r;
+}
+template <int K>
+inline DualN<K> operator+(const DualN<K>& a, double s) {
+  DualN<K> r(a);
+  r.v = a.v + s;
+  return r;
+}
+template <int K>
+inline DualN<K> operator-(double s, const DualN<K>& a) {
+  DualN<K> r(s - a.v);
+  for (int k = 0; k < K; ++k) r.d[k] = -a.d[k];
+  return r;
+}
+typedef DualN<1> Dual;
+typedef DualN<2> Dual2;
 inline double val(double x) { return x; }
-inline double val(const Dual& x) { return x.v; }
+template <int K>
+inline double val(const DualN<K>& x) { return x.v; }
 
-// a*b + c with one rounding.  Every weighted sum of the recursion (the
-// differentiation formulas in space and time, the Taylor predictions and
-// the final flux sum) accumulates in index order with this fused
-// multiply-add, and so do the 2D Euler flux's product-sums (m v + n w,
-// E - (m v + n w)/2, m v + p, n w + p); the 2D U^k is one such chain over the
-// row and then the column, with the weights -lamx gamma and -lamy gamma; all
-// other arithmetic is plain IEEE operations, so the rounding of every
-// operation is fixed.
-inline double mad(double a, double b, double c) { return std::fma(a, b, c); }
-inline Dual mad(double a, const Dual& b, const Dual& c) { return Dual(std::fma(a, b.v, c.v), std::fma(a, b.d, c.d)); }
-inline Dual mad(const Dual& a, const Dual& b, const Dual& c) {
-  return Dual(std::fma(a.v, b.v, c.v), a.d * b.v + a.v * b.d + c.d);
+// a*b + c.  Two rounding modes, chosen per problem (FLAG_PLAIN_ROUNDING):
+//   fixed (default): one rounding, a fused multiply-add.  Every weighted sum
+//     of the recursion (the differentiation formulas in space and time, the
+//     Taylor predictions and the final flux sum) accumulates in index order
+//     with it, and so do the 2D Euler flux's product-sums (m v + n w,
+//     E - (m v + n w)/2, m v + p, n w + p); the 2D U^k is one such chain over
+//     the row and then the column, with the weights -lamx gamma and
+//     -lamy gamma; the final flux is summed node by node.
+//   plain: the product and the sum each rounded (no fused operation
+//     anywhere), the sums in the order the paper writes them: U^k as
+//     -lamx (sum) - lamy (sum), the final flux k-outer with 1/k! as a
+//     division, velocities as m / rho.
+// All other arithmetic is plain IEEE operations in both modes.  Both modes
+// are frozen: each is a fixed reading of the paper's formulas, and neither
+// is changed to follow an implementation.
+inline double fmad(double a, double b, double c) { return std::fma(a, b, c); }
+template <int K>
+inline DualN<K> fmad(double a, const DualN<K>& b, const DualN<K>& c) {
+  DualN<K> r(std::fma(a, b.v, c.v));
+  for (int k = 0; k < K; ++k) r.d[k] = std::fma(a, b.d[k], c.d[k]);
+  return r;
+}
+template <int K>
+inline DualN<K> fmad(const DualN<K>& a, const DualN<K>& b, const DualN<K>& c) {
+  DualN<K> r(std::fma(a.v, b.v, c.v));
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k] + c.d[k];
+  return r;
+}
+template <class A, class B, class C>
+inline auto mad(bool plain, const A& a, const B& b, const C& c) -> decltype(fmad(a, b, c)) {
+  if (plain) return a * b + c;
+  return fmad(a, b, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -252,6 +328,15 @@ inline Dual mad(const Dual& a, const Dual& b, const Dual& c) {
 // ---------------------------------------------------------------------------
 enum { FLUX_ADVECTION = 0, FLUX_BURGERS = 1, FLUX_EULER = 2 };
 enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1 };
+// Variants the paper describes beside the default method (bits of flags):
+// the first-order flux F^lo of the blend is Lax-Friedrichs or HLL instead of
+// Rusanov (Sec. 5 lists LF and HLL as the first-order schemes), the p = 2
+// indicator is the modified one of Sec. 3.2, for scalar laws psi^1 may use
+// the upwind ratio chosen by the sign of Roe's speed (Sec. 3.1), and 2D
+// corners may use square stencils per direction.  FLAG_PLAIN_ROUNDING
+// selects the plain rounding mode (see mad).
+enum { FLAG_FLO_LF = 1, FLAG_FLO_HLL = 2, FLAG_PSI2_MODIFIED = 4, FLAG_PSI1_ROE = 8, FLAG_SQUARE_2D = 16,
+       FLAG_PLAIN_ROUNDING = 256 };
 
 }  // namespace
 
@@ -266,6 +351,22 @@ typedef struct {
 }
 
 namespace {
+
+inline bool plain(const oracle_problem& pb) { return (pb.flags & FLAG_PLAIN_ROUNDING) != 0; }
+
+// 2D velocities v = m / rho, w = n / rho: fixed rounding through one
+// reciprocal, plain rounding by division
+template <class T>
+void velocities(bool pl, const T& rho, const T& mx, const T& my, T& v, T& w) {
+  if (pl) {
+    v = mx / rho;
+    w = my / rho;
+  } else {
+    T ir = 1.0 / rho;
+    v = mx * ir;
+    w = my * ir;
+  }
+}
 
 // x-direction flux f(u) (1D flux, or the x-flux in 2D)
 template <class T>
@@ -283,14 +384,15 @@ void flux_f(const oracle_problem& pb, const T* u, T* f) {
     f[1] = m * v + p;
     f[2] = v * (E + p);
   } else {
-    // 2D Euler (Sec. 5.5): u = (rho, rho v, rho w, E); both velocity
-    // components use one reciprocal of the density
+    // 2D Euler (Sec. 5.5): u = (rho, rho v, rho w, E); fixed rounding: both
+    // velocity components use one reciprocal of the density
+    const bool pl = plain(pb);
     T rho = u[0], mx = u[1], my = u[2], E = u[3];
-    T ir = 1.0 / rho;
-    T v = mx * ir, w = my * ir;
-    T p = (pb.gamma - 1.0) * mad(-0.5, mad(mx, v, my * w), E);
+    T v, w;
+    velocities(pl, rho, mx, my, v, w);
+    T p = (pb.gamma - 1.0) * mad(pl, -0.5, mad(pl, mx, v, my * w), E);
     f[0] = mx;
-    f[1] = mad(mx, v, p);
+    f[1] = mad(pl, mx, v, p);
     f[2] = my * v;
     f[3] = v * (E + p);
   }
@@ -302,13 +404,14 @@ void flux_g(const oracle_problem& pb, const T* u, T* g) {
   if (pb.flux == FLUX_ADVECTION) {
     for (int c = 0; c < pb.nvar; ++c) g[c] = pb.ay * u[c];
   } else {
+    const bool pl = plain(pb);
     T rho = u[0], mx = u[1], my = u[2], E = u[3];
-    T ir = 1.0 / rho;
-    T v = mx * ir, w = my * ir;
-    T p = (pb.gamma - 1.0) * mad(-0.5, mad(mx, v, my * w), E);
+    T v, w;
+    velocities(pl, rho, mx, my, v, w);
+    T p = (pb.gamma - 1.0) * mad(pl, -0.5, mad(pl, mx, v, my * w), E);
     g[0] = my;
     g[1] = mx * w;
-    g[2] = mad(my, w, p);
+    g[2] = mad(pl, my, w, p);
     g[3] = w * (E + p);
   }
 }
@@ -345,13 +448,6 @@ int64_t bc_index(int64_t i, int64_t n, int bc) {
 // (a = j + P - 1 for stencil offset j).
 // ---------------------------------------------------------------------------
 
-// psi^p for one component, stencil S_p centred at the interface i+1/2.
-// Variants the paper describes beside the default method (bits of flags):
-// the first-order flux F^lo of the blend is Lax-Friedrichs or HLL instead of
-// Rusanov (Sec. 5 lists LF and HLL as the first-order schemes), the p = 2
-// indicator is the modified one of Sec. 3.2, and for scalar laws psi^1 may
-// use the upwind ratio chosen by the sign of Roe's speed (Sec. 3.1).
-enum { FLAG_FLO_LF = 1, FLAG_FLO_HLL = 2, FLAG_PSI2_MODIFIED = 4, FLAG_PSI1_ROE = 8, FLAG_SQUARE_2D = 16 };
 
 // Modified p = 2 indicator (Sec. 3.2): two pairs of lateral weights, each
 // joining the central sub-interval to one side; the larger ratio.
@@ -449,6 +545,31 @@ int select_order(const oracle_problem& pb, const double* const* comp, int G, dou
   return ps;
 }
 
+// The CAT flux F = sum_{k=1}^{m} 1/k! sum_l eta_l Fh^{k-1}_l (Sec. 2.2, the
+// interpolation A^{0,1/2} with the weights eta) from Fh^{k-1}_l = fh(k-1, l),
+// l = 0 .. nn-1, m = nn.  Fixed rounding: summed node by node,
+// sum_l eta_l (sum_k Fh^{k-1}_l / k!), fused; plain rounding: k-outer as
+// written, each term's interpolation divided by k!.
+template <class T, class FH>
+T final_flux(bool pl, int p, int nn, FH fh) {
+  const Tables& Tb = tables();
+  T s = 0.0;
+  if (pl) {
+    for (int k = 1; k <= nn; ++k) {
+      T a = 0.0;
+      for (int l = 0; l < nn; ++l) a = a + Tb.eta[p][l] * fh(k - 1, l);
+      s = s + a / Tb.fact[k];
+    }
+    return s;
+  }
+  for (int l = 0; l < nn; ++l) {
+    T t = 0.0;
+    for (int k = 1; k <= nn; ++k) t = fmad(Tb.invfact[k], fh(k - 1, l), t);
+    s = fmad(Tb.eta[p][l], t, s);
+  }
+  return s;
+}
+
 // ---------------------------------------------------------------------------
 // 1D CAT2p flux at one interface (Sec. 2.2 algorithm, scaled variables).
 // u[a][c]: state at node j = a - p + 1, a = 0 .. 2p-1.
@@ -456,6 +577,7 @@ int select_order(const oracle_problem& pb, const double* const* comp, int G, dou
 template <class T>
 void cat_flux_1d(const oracle_problem& pb, int p, const T (*u)[VMAX], double lam, T* F) {
   const Tables& Tb = tables();
+  const bool pl = plain(pb);
   const int nn = 2 * p, nv = pb.nvar;
   T Fh[NMAX][NMAX][VMAX];   // Fh[k][a][c] = dt^k f~^(k) at node a
   T U[NMAX][NMAX][VMAX];    // U[l][a][c]  = dt^l u~^(l) at node a
@@ -465,7 +587,7 @@ void cat_flux_1d(const oracle_problem& pb, int p, const T (*u)[VMAX], double lam
     for (int a = 0; a < nn; ++a)
       for (int c = 0; c < nv; ++c) {
         T s = 0.0;
-        for (int l = 0; l < nn; ++l) s = mad(Tb.g1[p][a][l], Fh[k - 2][l][c], s);
+        for (int l = 0; l < nn; ++l) s = mad(pl, Tb.g1[p][a][l], Fh[k - 2][l][c], s);
         U[k - 1][a][c] = -lam * s;
       }
     // (b) flux at the Taylor-predicted states at the time nodes r, and
@@ -481,26 +603,17 @@ void cat_flux_1d(const oracle_problem& pb, int p, const T (*u)[VMAX], double lam
           T w[VMAX];
           for (int c = 0; c < nv; ++c) {
             T s = u[a][c];
-            for (int l = 1; l <= k - 1; ++l) s = mad(Tb.taylor[r + PMAX - 1][l], U[l][a][c], s);
+            for (int l = 1; l <= k - 1; ++l) s = mad(pl, Tb.taylor[r + PMAX - 1][l], U[l][a][c], s);
             w[c] = s;
           }
           flux_f(pb, w, phi);
         }
-        for (int c = 0; c < nv; ++c) Fh[k - 1][a][c] = mad(Tb.gt[p][k - 1][ri], phi[c], Fh[k - 1][a][c]);
+        for (int c = 0; c < nv; ++c) Fh[k - 1][a][c] = mad(pl, Tb.gt[p][k - 1][ri], phi[c], Fh[k - 1][a][c]);
       }
     }
   }
-  // F = sum_{k=1}^{2p} 1/k! sum_l eta_l Fh^{k-1}_l, summed node by node:
-  // F = sum_l eta_l (sum_k Fh^{k-1}_l / k!)
-  for (int c = 0; c < nv; ++c) {
-    T s = 0.0;
-    for (int a = 0; a < nn; ++a) {
-      T t = 0.0;
-      for (int k = 1; k <= 2 * p; ++k) t = mad(Tb.invfact[k], Fh[k - 1][a][c], t);
-      s = mad(Tb.eta[p][a], t, s);
-    }
-    F[c] = s;
-  }
+  // F = sum_{k=1}^{2p} 1/k! sum_l eta_l Fh^{k-1}_l
+  for (int c = 0; c < nv; ++c) F[c] = final_flux<T>(pl, p, nn, [&](int k, int a) { return Fh[k][a][c]; });
 }
 
 // Smallest and largest characteristic speed along direction d (Davis
@@ -652,6 +765,7 @@ template <class T>
 void cat_corner_2d(const oracle_problem& pb, int q1, int q2, int qt, const T (*u)[NMAX][VMAX],
                    double lamx, double lamy, T* F, T* G) {
   const Tables& Tb = tables();
+  const bool pl = plain(pb);
   const int n1 = 2 * q1, n2 = 2 * q2, nt = 2 * qt, nv = pb.nvar;
   static thread_local T Fh[NMAX][NMAX][NMAX][VMAX];
   static thread_local T Gh[NMAX][NMAX][NMAX][VMAX];
@@ -664,14 +778,22 @@ void cat_corner_2d(const oracle_problem& pb, int q1, int q2, int qt, const T (*u
   for (int k = 2; k <= nt; ++k) {
     // (a) U^{k-1}_j = -lamx sum_l gamma^{1,j1}_{q1,l} Fh^{k-2}_{(l,j2)}
     //                 -lamy sum_l gamma^{1,j2}_{q2,l} Gh^{k-2}_{(j1,l)}
-    //     summed as one chain, row terms then column terms, with the
-    //     weights -lamx gamma and -lamy gamma
+    //     fixed rounding: one fused chain, row terms then column terms, with
+    //     the weights -lamx gamma and -lamy gamma; plain: the two sums, then
+    //     -lamx sx - lamy sy
     for (int a1 = 0; a1 < n1; ++a1)
       for (int a2 = 0; a2 < n2; ++a2)
         for (int c = 0; c < nv; ++c) {
+          if (pl) {
+            T sx = 0.0, sy = 0.0;
+            for (int l = 0; l < n1; ++l) sx = sx + Tb.g1[q1][a1][l] * Fh[k - 2][l][a2][c];
+            for (int l = 0; l < n2; ++l) sy = sy + Tb.g1[q2][a2][l] * Gh[k - 2][a1][l][c];
+            U[k - 1][a1][a2][c] = -lamx * sx - lamy * sy;
+            continue;
+          }
           T s = 0.0;
-          for (int l = 0; l < n1; ++l) s = mad(-lamx * Tb.g1[q1][a1][l], Fh[k - 2][l][a2][c], s);
-          for (int l = 0; l < n2; ++l) s = mad(-lamy * Tb.g1[q2][a2][l], Gh[k - 2][a1][l][c], s);
+          for (int l = 0; l < n1; ++l) s = fmad(-lamx * Tb.g1[q1][a1][l], Fh[k - 2][l][a2][c], s);
+          for (int l = 0; l < n2; ++l) s = fmad(-lamy * Tb.g1[q2][a2][l], Gh[k - 2][a1][l][c], s);
           U[k - 1][a1][a2][c] = s;
         }
     // (b), (c): f and g at the predicted states, time derivative at r = 0
@@ -687,44 +809,31 @@ void cat_corner_2d(const oracle_problem& pb, int q1, int q2, int qt, const T (*u
             T w[VMAX];
             for (int c = 0; c < nv; ++c) {
               T s = u[a1][a2][c];
-              for (int l = 1; l <= k - 1; ++l) s = mad(Tb.taylor[r + PMAX - 1][l], U[l][a1][a2][c], s);
+              for (int l = 1; l <= k - 1; ++l) s = mad(pl, Tb.taylor[r + PMAX - 1][l], U[l][a1][a2][c], s);
               w[c] = s;
             }
             flux_f(pb, w, pf);
             flux_g(pb, w, pg);
           }
           for (int c = 0; c < nv; ++c) {
-            Fh[k - 1][a1][a2][c] = mad(Tb.gt[qt][k - 1][ri], pf[c], Fh[k - 1][a1][a2][c]);
-            Gh[k - 1][a1][a2][c] = mad(Tb.gt[qt][k - 1][ri], pg[c], Gh[k - 1][a1][a2][c]);
+            Fh[k - 1][a1][a2][c] = mad(pl, Tb.gt[qt][k - 1][ri], pf[c], Fh[k - 1][a1][a2][c]);
+            Gh[k - 1][a1][a2][c] = mad(pl, Tb.gt[qt][k - 1][ri], pg[c], Gh[k - 1][a1][a2][c]);
           }
         }
       }
   }
-  // F = sum_k 1/k! sum_l eta_l Fh^{k-1}_(l,0), summed node by node (row j2 = 0)
+  // F = sum_k 1/k! sum_l eta_l Fh^{k-1}_(l,0) on row j2 = 0 (Taylor order
+  // nt = 2 q1 for F: qt = q1 whenever F is asked for)
   if (F) {
     const int a2 = q2 - 1;
-    for (int c = 0; c < nv; ++c) {
-      T s = 0.0;
-      for (int a = 0; a < n1; ++a) {
-        T t = 0.0;
-        for (int k = 1; k <= nt; ++k) t = mad(Tb.invfact[k], Fh[k - 1][a][a2][c], t);
-        s = mad(Tb.eta[q1][a], t, s);
-      }
-      F[c] = s;
-    }
+    for (int c = 0; c < nv; ++c)
+      F[c] = final_flux<T>(pl, q1, n1, [&](int k, int a) { return Fh[k][a][a2][c]; });
   }
-  // G likewise on column j1 = 0
+  // G likewise on column j1 = 0 (nt = 2 q2)
   if (G) {
     const int a1 = q1 - 1;
-    for (int c = 0; c < nv; ++c) {
-      T s = 0.0;
-      for (int a = 0; a < n2; ++a) {
-        T t = 0.0;
-        for (int k = 1; k <= nt; ++k) t = mad(Tb.invfact[k], Gh[k - 1][a1][a][c], t);
-        s = mad(Tb.eta[q2][a], t, s);
-      }
-      G[c] = s;
-    }
+    for (int c = 0; c < nv; ++c)
+      G[c] = final_flux<T>(pl, q2, n2, [&](int k, int a) { return Gh[k][a1][a][c]; });
   }
 }
 
@@ -902,7 +1011,9 @@ int check_problem(const oracle_problem* pb) {
   if (pb->flux == FLUX_BURGERS && (pb->nvar != 1 || pb->dim != 1)) return -2;
   if (pb->flux == FLUX_EULER && pb->nvar != (pb->dim == 1 ? 3 : 4)) return -2;
   if (pb->nx < 2 * std::max(pb->P, 2) || (pb->dim == 2 && pb->ny < 2 * std::max(pb->P, 2))) return -2;
-  if (pb->flags & ~(FLAG_FLO_LF | FLAG_FLO_HLL | FLAG_PSI2_MODIFIED | FLAG_PSI1_ROE | FLAG_SQUARE_2D)) return -2;
+  if (pb->flags & ~(FLAG_FLO_LF | FLAG_FLO_HLL | FLAG_PSI2_MODIFIED | FLAG_PSI1_ROE | FLAG_SQUARE_2D |
+                    FLAG_PLAIN_ROUNDING))
+    return -2;
   if ((pb->flags & FLAG_SQUARE_2D) && pb->dim != 2) return -2;
   if ((pb->flags & FLAG_FLO_LF) && (pb->flags & FLAG_FLO_HLL)) return -2;
   if ((pb->flags & FLAG_PSI1_ROE) && pb->flux == FLUX_EULER) return -2;   // scalar laws only
@@ -955,9 +1066,9 @@ int oracle_step1d_jvp(const oracle_problem* pb, const double* u, const double* d
   if (e) return e;
   size_t n = (size_t)pb->nvar * pb->nx;
   std::vector<Dual> x(n), y(n);
-  for (size_t a = 0; a < n; ++a) x[a] = Dual(u[a], du[a]);
+  for (size_t a = 0; a < n; ++a) { x[a] = Dual(u[a]); x[a].d[0] = du[a]; }
   step1d<Dual>(*pb, x.data(), y.data(), dt, 1, ord, psi1, alpha, nullptr, nthreads);
-  for (size_t a = 0; a < n; ++a) { uout[a] = y[a].v; duout[a] = y[a].d; }
+  for (size_t a = 0; a < n; ++a) { uout[a] = y[a].v; duout[a] = y[a].d[0]; }
   return 0;
 }
 
@@ -978,9 +1089,36 @@ int oracle_step2d_jvp(const oracle_problem* pb, const double* u, const double* d
   if (e) return e;
   size_t n = (size_t)pb->nvar * pb->nx * pb->ny;
   std::vector<Dual> x(n), y(n);
-  for (size_t a = 0; a < n; ++a) x[a] = Dual(u[a], du[a]);
+  for (size_t a = 0; a < n; ++a) { x[a] = Dual(u[a]); x[a].d[0] = du[a]; }
   step2d<Dual>(*pb, x.data(), y.data(), dt, 1, ordx, ordy, psix, psiy, alx, aly, nullptr, nullptr, nthreads);
-  for (size_t a = 0; a < n; ++a) { uout[a] = y[a].v; duout[a] = y[a].d; }
+  for (size_t a = 0; a < n; ++a) { uout[a] = y[a].v; duout[a] = y[a].d[0]; }
+  return 0;
+}
+
+// The same tangent along two directions at once: du and duout are [2][state].
+// decide = 0: the given decisions (frozen replay); decide = 1: the step
+// decides from the values of u (the decisions are written to the arrays),
+// which is the tangent of the replay map of the step's own decisions.
+int oracle_step2d_jvp2(const oracle_problem* pb, const double* u, const double* du, double* uout, double* duout,
+                       double dt, int8_t* ordx, int8_t* ordy, double* psix, double* psiy, double* alx, double* aly,
+                       int nthreads, int decide) {
+  int e = check_problem(pb);
+  if (e) return e;
+  if (!ordx || !ordy || !psix || !psiy || !alx || !aly) return -1;
+  size_t n = (size_t)pb->nvar * pb->nx * pb->ny;
+  std::vector<Dual2> x(n), y(n);
+  for (size_t a = 0; a < n; ++a) {
+    x[a] = Dual2(u[a]);
+    x[a].d[0] = du[a];
+    x[a].d[1] = du[n + a];
+  }
+  step2d<Dual2>(*pb, x.data(), y.data(), dt, decide ? 0 : 1, ordx, ordy, psix, psiy, alx, aly, nullptr, nullptr,
+                nthreads);
+  for (size_t a = 0; a < n; ++a) {
+    uout[a] = y[a].v;
+    duout[a] = y[a].d[0];
+    duout[n + a] = y[a].d[1];
+  }
   return 0;
 }
 

@@ -329,3 +329,42 @@ def test_adjoint_every_corner_class_forced(acat, q1, q2, bc):
     err = np.abs(got - want).max()
     print(f"class ({q1},{q2}) {bc}: max err {err:.3e}, non-finite {len(bad)} first {bad[:3].tolist()}", flush=True)
     assert np.all(np.isfinite(got)) and err <= TOL_DENSE * np.abs(want).max()
+
+
+def test_checkpointed_gradient_full_size_c5_matches_oracle_tangent(acat):
+    """The adjoint workload as the benchmark runs it: 2D Euler 512^2, P = 2,
+    200 CFL steps, checkpoint every 20 steps, graph-captured segments
+    (ACATRun).  <grad, d_j> for two smooth directions against the oracle's
+    tangent run (its own CFL steps and decisions, both tangents carried in
+    one pass): within 1e-10 relative; the GPU's final state equals the
+    oracle's bit for bit.  The misfit's target is the initial density (the
+    target only fixes the cotangent at the final time)."""
+    import time
+    w = workloads.adjoint_2d()
+    po, pg = from_workload(w)
+    nsteps, k = w["nsteps"], w["checkpoint_every"]
+    star = w["u"][0].copy()
+    run = acat.AdjointRun(pg, w["cfl"], nsteps, checkpoint_every=k)
+    u0 = torch.from_numpy(w["u"]).cuda().requires_grad_(True)
+    uT = acat.ACATRun.apply(u0, run)
+    loss = 0.5 * w["dx"] * w["dy"] * ((uT[0] - torch.from_numpy(star).cuda()) ** 2).sum()
+    loss.backward()
+    grad = u0.grad.cpu().numpy()
+    uT = uT.detach().cpu().numpy()
+    t0 = time.time()
+    u = w["u"].copy()
+    dirs = np.stack([w["directions"](0), w["directions"](1)])
+    dv = dirs.copy()
+    for n in range(nsteps):
+        dt = oracle.dt_cfl(po, u, w["cfl"])
+        u, dv = oracle.jvp2(po, u, dv, dt, nthreads=16)
+        if n % 50 == 49:
+            print(f"[C5 oracle tangent] step {n + 1} ({time.time() - t0:.0f} s)", flush=True)
+    assert np.array_equal(uT, u)
+    gT = w["dx"] * w["dy"] * (u[0] - star)
+    for j in range(2):
+        rhs = float(np.vdot(gT, dv[j][0]))
+        lhs = float(np.vdot(grad, dirs[j]))
+        print(f"[C5 full size] direction {j}: adjoint {lhs:.15e} tangent {rhs:.15e} "
+              f"rel {abs(lhs - rhs) / abs(rhs):.2e}", flush=True)
+        assert abs(lhs - rhs) <= TOL_JVP * abs(rhs), (j, lhs, rhs)

@@ -214,3 +214,38 @@ def test_batched_launch_shapes_and_autotuner_keep_results(acat, tmp_path):
     again = autotune.tune(batch, u, dt, cache=cache)           # from the cache
     assert {p: v[:2] for p, v in again.items()} == {p: tuple(v[:2]) for p, v in best.items()}
     say(f"[autotune] {best}")
+
+
+def test_batched_c4_full_run_500_graph_replayed_steps(acat):
+    """The whole batched workload run: 256 problems through BatchSolver,
+    2 eager steps then 249 replays of a captured 2-step graph (500 steps, the
+    time steps of each step reduced inside the previous one).  Sampled
+    problems (the largest, the smallest, two at each P) against 500 oracle
+    steps from the same initial data with the oracle's own CFL time steps:
+    bit for bit (so within 1e-11)."""
+    import torch
+    w = workloads.batch_1d()
+    probs = w["problems"]
+    batch = make_batch(acat, probs)
+    bs = acat.BatchSolver(batch, concat([p["u"] for p in probs]), w["cfl"])
+    bs.capture(2)
+    bs.replay(249)
+    torch.cuda.synchronize()
+    assert bs.nsteps == 500
+    parts = batch.split(bs.u.cpu().numpy())
+    Ns = np.array([p["u"].shape[1] for p in probs])
+    Ps = np.array([p["P"] for p in probs])
+    pick = {int(np.argmax(Ns)), int(np.argmin(Ns))}
+    for P in (2, 3, 4):
+        pick.update(int(b) for b in np.flatnonzero(Ps == P)[:2])
+    for b in sorted(pick):
+        po = oracle.Problem(dim=1, nvar=3, nx=int(Ns[b]), flux=oracle.FLUX_EULER, P=int(Ps[b]),
+                            bc=oracle.BC_TRANSMISSIVE if probs[b]["bc"] == "transmissive" else oracle.BC_PERIODIC,
+                            dx=probs[b]["dx"])
+        uo, _, nst = oracle.run(po, probs[b]["u"], w["cfl"], nsteps=500, nthreads=16)
+        scale = np.abs(uo).max(axis=1)
+        err = (np.abs(parts[b] - uo).max(axis=1) / scale).max()
+        say(f"[batched C4 500 steps] problem {b} N={Ns[b]} P={Ps[b]}: rel_err={err:.3e} "
+            f"bitwise={np.array_equal(parts[b], uo)}")
+        assert err <= 1e-11
+        assert np.array_equal(parts[b], uo), f"problem {b}"
