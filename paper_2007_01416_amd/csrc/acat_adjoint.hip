@@ -265,7 +265,7 @@ __global__ __launch_bounds__(BLOCK) void k_gather1d(KProb pb, KStep st, const do
 // adjoints of this node's series SF / SG; ub accumulates the adjoint of u,
 // f0b/g0b those of f(u), g(u).
 template <int FLUX, int NV, int Q1, int Q2, int QT>
-__device__ __forceinline__ void corner_adjoint(const Phys& ph, double lamx, double lamy, const double (&u)[NV],
+__device__ __forceinline__ void corner_adjoint(const Phys& ph, const double (&u)[NV],
                                                const double (&f0)[NV], const double (&g0)[NV],
                                                const double* gx, const double* gy,
                                                double2* xsb0, double2* xsb1, int stride, int& buf, int slot,
@@ -287,16 +287,16 @@ __device__ __forceinline__ void corner_adjoint(const Phys& ph, double lamx, doub
     Xch<NV>::put(xsw, stride, slot, fc, gc);
     Groups<(2 * Q1) * (2 * Q2)>::sync();
     const double* xr = reinterpret_cast<const double*>(xsw);
+    // U^{kk-1} as the forward step forms it: one chain over the row, then
+    // the column, with the weights -lamx gamma and -lamy gamma
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
-      double sx = 0.0, sy = 0.0;
+      double s = 0.0;
 #pragma unroll
-      for (int l = 0; l < N1; ++l)
-        sx = fma(gx[a1 * N1 + l], Xch<NV>::get(xr, stride, gbase + a2 * N1 + l, c, false), sx);
+      for (int l = 0; l < N1; ++l) s = fma(gx[a1 * N1 + l], Xch<NV>::get(xr, stride, gbase + a2 * N1 + l, c, false), s);
 #pragma unroll
-      for (int l = 0; l < N2; ++l)
-        sy = fma(gy[a2 * N2 + l], Xch<NV>::get(xr, stride, gbase + l * N1 + a1, c, true), sy);
-      U[kk - 1][c] = fma(-lamy, sy, -lamx * sx);
+      for (int l = 0; l < N2; ++l) s = fma(gy[a2 * N2 + l], Xch<NV>::get(xr, stride, gbase + l * N1 + a1, c, true), s);
+      U[kk - 1][c] = s;
     }
     buf ^= 1;
     if (kk == T) break;
@@ -387,21 +387,22 @@ __device__ __forceinline__ void corner_adjoint(const Phys& ph, double lamx, doub
         }
       }
     }
-    // U^{kk-1} = -lamx sum_l g1x[a1][l] Fh_(l,a2) - lamy sum_l g1y[a2][l] Gh_(a1,l)
-    //  => Fhbar_(a1,a2) += -lamx sum_j g1x[j][a1] Ubar_(j,a2); Ghbar likewise along the column
+    // U^{kk-1} = sum_l wx[a1][l] Fh_(l,a2) + sum_l wy[a2][l] Gh_(a1,l)
+    // (wx = -lamx gamma, wy = -lamy gamma)
+    //  => Fhbar_(a1,a2) += sum_j wx[j][a1] Ubar_(j,a2); Ghbar likewise along the column
     double2* xsw = buf ? xsb1 : xsb0;
     Xch<NV>::put(xsw, stride, slot, Ub[kk - 1], Ub[kk - 1]);
     Groups<(2 * Q1) * (2 * Q2)>::sync();
     const double* xr = reinterpret_cast<const double*>(xsw);
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
-      double sx = 0.0, sy = 0.0;
+      double sx = TB.INVFACT[kk - 1] * sfb[c], sy = TB.INVFACT[kk - 1] * sgb[c];
 #pragma unroll
-      for (int j = 0; j < N1; ++j) sx += gx[j * N1 + a1] * Xch<NV>::get(xr, stride, gbase + a2 * N1 + j, c, false);
+      for (int j = 0; j < N1; ++j) sx = fma(gx[j * N1 + a1], Xch<NV>::get(xr, stride, gbase + a2 * N1 + j, c, false), sx);
 #pragma unroll
-      for (int j = 0; j < N2; ++j) sy += gy[j * N2 + a2] * Xch<NV>::get(xr, stride, gbase + j * N1 + a1, c, true);
-      fhb[c] = TB.INVFACT[kk - 1] * sfb[c] - lamx * sx;
-      ghb[c] = TB.INVFACT[kk - 1] * sgb[c] - lamy * sy;
+      for (int j = 0; j < N2; ++j) sy = fma(gy[j * N2 + a2], Xch<NV>::get(xr, stride, gbase + j * N1 + a1, c, true), sy);
+      fhb[c] = sx;
+      ghb[c] = sy;
     }
     buf ^= 1;
   }
@@ -442,10 +443,12 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
   const int64_t nitems = pb.n1 * pb.n2;
   const int64_t cstride = nitems * LMAX;
 
-  // derivative weights in LDS, row-major: rows for the recursion, columns for its transpose
+  // derivative weights times -lamx (x) and -lamy (y) in LDS, row-major: rows
+  // for the recursion, columns for its transpose
   __shared__ double g1s[N1 * N1 + N2 * N2];
   for (int i = tid; i < N1 * N1 + N2 * N2; i += BLOCK)
-    g1s[i] = i < N1 * N1 ? TB.G1[Q1][i / N1][i % N1] : TB.G1[Q2][(i - N1 * N1) / N2][(i - N1 * N1) % N2];
+    g1s[i] = i < N1 * N1 ? -lamx * TB.G1[Q1][i / N1][i % N1]
+                         : -lamy * TB.G1[Q2][(i - N1 * N1) / N2][(i - N1 * N1) % N2];
   __syncthreads();
   const double* gx = g1s;
   const double* gy = g1s + N1 * N1;
@@ -511,14 +514,14 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
     }
     const int slot = g * L + nd;
     if constexpr (Q1 == Q2) {
-      corner_adjoint<FLUX, NV, Q1, Q2, Q1>(pb.ph, lamx, lamy, u, f0, g0, gx, gy, xs[0], xs[1], STRIDE, buf, slot,
+      corner_adjoint<FLUX, NV, Q1, Q2, Q1>(pb.ph, u, f0, g0, gx, gy, xs[0], xs[1], STRIDE, buf, slot,
                                            g * L, a1, a2, sfb, sgb, ub, f0b, g0b);
     } else {
       if constexpr ((PASSES & 1) != 0)
-        corner_adjoint<FLUX, NV, Q1, Q2, Q1>(pb.ph, lamx, lamy, u, f0, g0, gx, gy, xs[0], xs[1], STRIDE, buf, slot,
+        corner_adjoint<FLUX, NV, Q1, Q2, Q1>(pb.ph, u, f0, g0, gx, gy, xs[0], xs[1], STRIDE, buf, slot,
                                              g * L, a1, a2, sfb, zero, ub, f0b, g0b);
       if constexpr ((PASSES & 2) != 0)
-        corner_adjoint<FLUX, NV, Q1, Q2, Q2>(pb.ph, lamx, lamy, u, f0, g0, gx, gy, xs[0], xs[1], STRIDE, buf, slot,
+        corner_adjoint<FLUX, NV, Q1, Q2, Q2>(pb.ph, u, f0, g0, gx, gy, xs[0], xs[1], STRIDE, buf, slot,
                                              g * L, a1, a2, zero, sgb, ub, f0b, g0b);
     }
     // first-order parts (Rusanov or Lax-Friedrichs) of the FL-CAT2 blends, on
