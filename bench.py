@@ -58,23 +58,37 @@ def traffic_from_profiles(kernel: str):
         return None
 
 
-def cpu_baseline(w, nsteps_sample=1):
-    """The oracle, as it stands, on one full step of the same workload."""
+def _oracle_step_rate(w, nthreads):
+    """cell-updates/s of one oracle step (CFL time step included) of workload w."""
     import numpy as np
     import oracle
     n = w["u"].shape[-1]
-    cores = min(16, len(os.sched_getaffinity(0)))
     po = oracle.Problem(dim=2, nvar=4, nx=n, ny=n, flux=oracle.FLUX_EULER, P=w["P"], bc=oracle.BC_PERIODIC,
                         dx=w["dx"], dy=w["dy"], gamma=w["gamma"])
     u = np.ascontiguousarray(w["u"])
     t0 = time.perf_counter()
-    for _ in range(nsteps_sample):
-        dt = oracle.dt_cfl(po, u, w["cfl"])
-        u = oracle.step2d(po, u, dt, nthreads=cores)["u"]
+    dt = oracle.dt_cfl(po, u, w["cfl"])
+    oracle.step2d(po, u, dt, nthreads=nthreads)
     el = time.perf_counter() - t0
-    return {"value": n * n * nsteps_sample / el, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{nsteps_sample} full {n}x{n} P={w['P']} step(s) of the same workload from its initial "
-                      f"state ({el:.1f} s)"}
+    return n * n / el, el
+
+
+def cpu_baseline(w, workloads):
+    """The oracle, as it stands, on one full step of the same workload with
+    every host core this process may run on; beside it, one step of the same
+    recipe at 512^2 on one thread and on all of them (the single-thread
+    sample, bounded in time)."""
+    cores = len(os.sched_getaffinity(0))
+    n = w["u"].shape[-1]
+    rate, el = _oracle_step_rate(w, cores)
+    small = workloads.euler_2d(n=512, P=w["P"])
+    r1, e1 = _oracle_step_rate(small, 1)
+    rn, en = _oracle_step_rate(small, cores)
+    return {"value": rate, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 full {n}x{n} P={w['P']} step of the same workload from its initial state ({el:.1f} s, "
+                      f"{cores} OpenMP threads = all cores of the process's CPU affinity set)",
+            "single_thread": {"value": r1, "cores": 1, "seconds": e1, "all_cores_value_same_sample": rn,
+                              "sample": "1 step of the same recipe at 512x512 (P=%d) from its initial state" % w["P"]}}
 
 
 def bench_batched(acat, workloads, steps_batched=500, steps_single=10):
@@ -123,6 +137,30 @@ def bench_batched(acat, workloads, steps_batched=500, steps_single=10):
             s.step()
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
+    # the same per-problem steps captured into one HIP graph (two steps of every
+    # problem per replay, so the ping-pong buffers return to their start):
+    # measures the per-instance design without Python launch overhead
+    for s in singles:
+        s.step()
+        s.step()
+    torch.cuda.synchronize()
+    gi = torch.cuda.CUDAGraph()
+    starts = [s.cur for s in singles]
+    with torch.cuda.graph(gi):
+        for s in singles:
+            s.step()
+            s.step()
+    for s, c in zip(singles, starts):
+        s.cur = c
+    gi.replay()
+    torch.cuda.synchronize()
+    reps_g = max(steps_batched // 2, 1)
+    t0 = time.perf_counter()
+    for _ in range(reps_g):
+        gi.replay()
+    torch.cuda.synchronize()
+    tsg = time.perf_counter() - t0
+    steps_single_graph = 2 * reps_g
     # roofline of the dominant per-order flux kernel: a few eager steps with the
     # library's kernel timer and the per-order interface counts of each step
     from paper_2007_01416_amd import flops as F
@@ -152,8 +190,12 @@ def bench_batched(acat, workloads, steps_batched=500, steps_single=10):
     return {"workload": f"{batch.nprob} independent 1D Euler problems, N log-uniform in [512,16384] "
                         f"(total {cells} cells), P in {{2,3,4}}, transmissive, per-problem CFL 0.5",
             "value": vb, "unit": "cell-updates/s", "steps": steps_batched, "ms_per_step": 1e3 * tb / steps_batched,
-            "per_instance_value": vs, "per_instance_steps": steps_single,
-            "per_instance_ms_per_step": 1e3 * ts / steps_single, "speedup_vs_per_instance": vb / vs,
+            "per_instance_graph_value": cells * steps_single_graph / tsg,
+            "per_instance_graph_ms_per_step": 1e3 * tsg / steps_single_graph,
+            "per_instance_graph_steps": steps_single_graph,
+            "speedup_vs_per_instance_graph": vb / (cells * steps_single_graph / tsg),
+            "per_instance_eager_value": vs, "per_instance_eager_steps": steps_single,
+            "per_instance_eager_ms_per_step": 1e3 * ts / steps_single, "speedup_vs_per_instance_eager": vb / vs,
             "autotuned_launch": {f"p{p}": {"waves_per_block": v[0], "blocks_per_cu": v[1],
                                            "kernel_us": round(1e3 * v[2], 2)} for p, v in best.items()},
             "default_launch_ms_per_step": 1e3 * tdef / steps_batched,
@@ -233,8 +275,24 @@ def bench_adjoint(acat, workloads, F, fd_dirs=32, fd_h=(1e-4, 1e-5, 1e-6, 1e-7, 
                 c, ms = prof[name]
                 kern[name] = dict(launches=c, ms=ms, flops=int(hist[(q1 - 1) * P + (q2 - 1)]) *
                                   F.adjoint_corner_flops_2d(q1, q2))
+    ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+    per_kernel = {}
+    for name, v in kern.items():
+        q1, q2 = int(name[-2]), int(name[-1])
+        cnt = int(hist[(q1 - 1) * P + (q2 - 1)])
+        by = cnt * F.adjoint_corner_bytes_2d(q1, q2)
+        sec = v["ms"] * 1e-3
+        intensity = v["flops"] / max(by, 1)
+        bound = "alu" if intensity >= ridge else "hbm"
+        per_kernel[name] = {"ms": round(v["ms"], 3), "corners": cnt, "flops_per_byte": round(intensity, 2),
+                            "bound": bound,
+                            "frac": (v["flops"] / sec / 1e12 / PEAK_FP64_TFLOPS) if bound == "alu"
+                            else (by / sec / 1e9 / PEAK_HBM_GBS),
+                            "alu_frac": v["flops"] / sec / 1e12 / PEAK_FP64_TFLOPS,
+                            "hbm_frac": by / sec / 1e9 / PEAK_HBM_GBS}
     dom = max(kern, key=lambda x: kern[x]["ms"])
     achieved = kern[dom]["flops"] / (kern[dom]["ms"] * 1e-3) / 1e12
+    dom_alu = max((x for x in kern if per_kernel[x]["bound"] == "alu"), key=lambda x: kern[x]["ms"], default=None)
     # verified run (recomputed order maps and time steps checked) recording every step for the replay map
     vrun = acat.AdjointRun(pg, cfl, nsteps, k, record_all=True, verify=True)
     uT2 = vrun.forward(u0)
@@ -260,10 +318,16 @@ def bench_adjoint(acat, workloads, F, fd_dirs=32, fd_h=(1e-4, 1e-5, 1e-6, 1e-7, 
                         f"(rho_T - rho*_T)^2, gradient w.r.t. all of u0, checkpoint every {k}",
             "forward_plain_ms": 1e3 * t_plain, "forward_checkpointed_ms": 1e3 * t_fwd, "backward_ms": 1e3 * t_bwd,
             "adjoint_over_forward": t_bwd / t_plain,
-            "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                         "avg_launch_us": 1e3 * kern[dom]["ms"] / kern[dom]["launches"]},
-            "adjoint_kernels_ms": {x: round(v["ms"], 3) for x, v in kern.items()},
+            "roofline": ({"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                          "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS}
+                         if per_kernel[dom]["bound"] == "alu" else
+                         {"bound": "hbm", "kernel": dom,
+                          "achieved": per_kernel[dom]["hbm_frac"] * PEAK_HBM_GBS, "peak": PEAK_HBM_GBS,
+                          "unit": "GB/s", "frac": per_kernel[dom]["hbm_frac"]})
+                        | {"avg_launch_us": 1e3 * kern[dom]["ms"] / kern[dom]["launches"],
+                           "dominant_alu_bound_kernel": dom_alu,
+                           "dominant_alu_bound_frac": per_kernel[dom_alu]["alu_frac"] if dom_alu else None},
+            "adjoint_kernels": per_kernel,
             "loss": loss(uT), "grad_deterministic": deterministic,
             "fd_check": {"directions": fd_dirs, "h": list(fd_h), "max_rel_err_best_h": max(errs),
                          "median_rel_err_by_h": {f"{h:.0e}": float(np.median(per_h[h])) if per_h[h] else None
@@ -472,6 +536,18 @@ def main():
     acat.profile(False)
     hist = hist.cpu().numpy().astype(np.int64)
     flags = acat.device_status()
+    # the same step window again, captured once into a HIP graph and replayed
+    # (no per-launch events, no host launch gaps)
+    g = acat.Solver(prob, w["u"], w["cfl"])
+    g.run(max(args.warmup - 2, 0))
+    g.capture(args.steps if args.steps % 2 == 0 else args.steps + 1)   # its two warm-up steps run eagerly
+    gsteps = g.graph_steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.replay(1)
+    torch.cuda.synchronize()
+    el_graph = time.perf_counter() - t0
+    graph_ok = bool(torch.equal(g.u, s.u)) if gsteps == args.steps and args.warmup >= 2 else None
 
     cells = n * n
     value = cells * args.steps / el
@@ -511,6 +587,11 @@ def main():
                      "avg_launch_us": kernels[dom]["avg_us"],
                      "alg_flops_per_launch": class_flops[dom] / max(dom_launches, 1),
                      "frac_of_measured_fp64": achieved / peaks["fp64_fma_tflops"]},
+        "graph_replayed": {"value": cells * gsteps / el_graph, "unit": "cell-updates/s",
+                           "ms_per_step": 1e3 * el_graph / gsteps, "steps": gsteps,
+                           "first_step": max(args.warmup - 2, 0) + 2, "same_final_state_as_eager": graph_ok,
+                           "note": "the timed window replayed from one captured HIP graph, without the "
+                                   "library's per-launch event timer"},
         "measured_peaks": peaks,
         "step_alg_tflops": alg_total / el / 1e12,
         "kernel_time_fraction": kern_ms / (1e3 * el),
@@ -530,7 +611,7 @@ def main():
         out["adjoint"] = bench_adjoint(acat, workloads, F, fd_dirs=args.fd_dirs)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, workloads)
     print(json.dumps(out), flush=True)
 
 

@@ -159,3 +159,16 @@ def adjoint_corner_flops_2d(q1: int, q2: int, s: int = 4, cfg: int = C_FG_EULER2
     if q2 == 1:
         total += 2 * 4 * s
     return total
+
+
+def adjoint_corner_bytes_2d(q1: int, q2: int, s: int = 4) -> int:
+    """Compulsory HBM bytes per corner of the 2D adjoint kernel of class
+    (q1, q2), as a launch over a grid with about one corner per cell moves
+    them: the state and the incoming adjoint of one cell (each cell is read
+    once if neighbouring corners share it in cache), the recorded superbee
+    weight and Rusanov speed of each order-1 direction, the list entry, and
+    the written per-node contributions, one value per component at each of
+    the (2 q1)(2 q2) stencil nodes."""
+    nodes = (2 * q1) * (2 * q2)
+    dec = 16 * ((q1 == 1) + (q2 == 1))
+    return 8 * s + 8 * s + dec + 4 + 8 * s * nodes
