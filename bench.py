@@ -114,16 +114,21 @@ def bench_batched(acat, workloads, steps_batched=500, steps_single=10):
     bs.replay(steps_batched // 2)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
-    # the same graph-replayed steps with the default launch shapes
-    batch.set_launch(None)
-    bd = acat.BatchSolver(batch, u0, w["cfl"])
-    bd.capture(2)
-    bd.replay(2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    bd.replay(steps_batched // 2)
-    torch.cuda.synchronize()
-    tdef = time.perf_counter() - t0
+    # the same graph-replayed steps with the default launch (every order class
+    # in one flux launch: 6 launches per step) and with one flux launch per
+    # order class at the default shape (9 launches per step)
+    def graph_ms(table):
+        batch.set_launch(table)
+        bd = acat.BatchSolver(batch, u0, w["cfl"])
+        bd.capture(2)
+        bd.replay(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bd.replay(steps_batched // 2)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+    tdef = graph_ms(None)
+    tsep = graph_ms({p: (4, 0) for p in batch.orders})
     singles = []
     for p in probs:
         pg = acat.Problem(dim=1, nvar=3, nx=p["u"].shape[1], flux="euler", P=p["P"], bc=p["bc"], dx=p["dx"])
@@ -164,7 +169,7 @@ def bench_batched(acat, workloads, steps_batched=500, steps_single=10):
     # roofline of the dominant per-order flux kernel: a few eager steps with the
     # library's kernel timer and the per-order interface counts of each step
     from paper_2007_01416_amd import flops as F
-    batch.set_launch({p: v[:2] for p, v in best.items()})
+    batch.set_launch(None if all(v[0] == 0 for v in best.values()) else {p: v[:2] for p, v in best.items()})
     ue = torch.from_numpy(u0).cuda()
     uo = torch.empty_like(ue)
     dte = torch.empty(batch.nprob, dtype=torch.float64, device="cuda")
@@ -181,9 +186,19 @@ def bench_batched(acat, workloads, steps_batched=500, steps_single=10):
     prof = acat.profile_read()
     acat.profile(False)
     per_p = hist.cpu().numpy().astype(np.int64).sum(0)
-    kern = {p: prof[f"flux_b_p{p}"] for p in batch.orders if f"flux_b_p{p}" in prof}
-    dom = max(kern, key=lambda p: kern[p][1])
-    ach = per_p[dom - 1] * F.interface_flops_1d(dom, 3, F.C_F[("euler", 1)]) / (kern[dom][1] * 1e-3) / 1e12
+    cf = F.C_F[("euler", 1)]
+    if "flux_b_all" in prof:             # the default: every order class in one launch
+        dom_name = "flux_b_all"
+        dom_launches, dom_ms = prof[dom_name]
+        dom_flops = sum(int(per_p[p - 1]) * F.interface_flops_1d(p, 3, cf) for p in batch.orders)
+    else:
+        kern = {p: prof[f"flux_b_p{p}"] for p in batch.orders if f"flux_b_p{p}" in prof}
+        dom = max(kern, key=lambda p: kern[p][1])
+        dom_name = f"flux_b_p{dom}"
+        dom_launches, dom_ms = kern[dom]
+        dom_flops = int(per_p[dom - 1]) * F.interface_flops_1d(dom, 3, cf)
+    ach = dom_flops / (dom_ms * 1e-3) / 1e12
+    launch_kernels = {k: {"launches": c, "avg_us": round(1e3 * ms / max(c, 1), 2)} for k, (c, ms) in prof.items()}
     cells = batch.ncell
     vb = cells * steps_batched / tb
     vs = cells * steps_single / ts
@@ -196,12 +211,16 @@ def bench_batched(acat, workloads, steps_batched=500, steps_single=10):
             "speedup_vs_per_instance_graph": vb / (cells * steps_single_graph / tsg),
             "per_instance_eager_value": vs, "per_instance_eager_steps": steps_single,
             "per_instance_eager_ms_per_step": 1e3 * ts / steps_single, "speedup_vs_per_instance_eager": vb / vs,
-            "autotuned_launch": {f"p{p}": {"waves_per_block": v[0], "blocks_per_cu": v[1],
-                                           "kernel_us": round(1e3 * v[2], 2)} for p, v in best.items()},
+            "autotuned_launch": ("default: every order class in one launch (kept: per-class shapes not "
+                                 "2 % faster, graph-replayed)" if all(v[0] == 0 for v in best.values()) else
+                                 {f"p{p}": {"waves_per_block": v[0], "blocks_per_cu": v[1],
+                                            "kernel_us": round(1e3 * v[2], 2)} for p, v in best.items()}),
             "default_launch_ms_per_step": 1e3 * tdef / steps_batched,
-            "roofline": {"bound": "alu", "kernel": f"flux_b_p{dom}", "achieved": ach, "peak": PEAK_FP64_TFLOPS,
+            "per_class_launches_ms_per_step": 1e3 * tsep / steps_batched,
+            "launches_per_step": launch_kernels,
+            "roofline": {"bound": "alu", "kernel": dom_name, "achieved": ach, "peak": PEAK_FP64_TFLOPS,
                          "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS,
-                         "avg_launch_us": 1e3 * kern[dom][1] / kern[dom][0]}}
+                         "avg_launch_us": 1e3 * dom_ms / dom_launches}}
 
 
 def bench_adjoint(acat, workloads, F, fd_dirs=32, fd_h=(1e-4, 1e-5, 1e-6, 1e-7, 1e-8)):

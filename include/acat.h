@@ -226,11 +226,12 @@ typedef struct {
   const int32_t* P;     /* host [nprob] 1..4                                   */
   const int32_t* bc;    /* host [nprob] ACAT_BC_*                              */
   const double* dx;     /* host [nprob] > 0                                    */
-  /* host [8] or NULL: launch shape of the flux kernel of each order class
-   * p = 1..4, entries 2(p-1) and 2(p-1)+1 = waves per block (1, 2 or 4;
-   * 0 = 4) and persistent blocks per CU (0 = the occupancy limit, else
-   * 1..32).  Any shape gives the same results bit for bit; the autotuner
-   * chooses them by timing. */
+  /* host [8] or NULL.  NULL: every order class in one persistent launch of
+   * 256-thread blocks, the grid shared among the classes by their work.  A
+   * table: one launch per order class p = 1..4 with the shape of entries
+   * 2(p-1) and 2(p-1)+1 = waves per block (1, 2 or 4; 0 = 4) and persistent
+   * blocks per CU (0 = the occupancy limit, else 1..32).  Every choice gives
+   * the same results bit for bit; the autotuner chooses by timing. */
   const int32_t* launch;
 } acat_batch;
 

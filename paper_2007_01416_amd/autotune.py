@@ -1,14 +1,16 @@
 """Autotuner of the batched step's launch shapes.
 
-For each order class p of a batch, the flux kernel's shape is a number of
-waves per block (1, 2 or 4: 64, 128 or 256 threads, i.e. 32p ... 128/p
-interfaces per block round) and a number of persistent blocks per CU (the
-occupancy limit, or fewer).  The classes are independent launches, so each
-is tuned on its own: every candidate shape runs the whole batched step on
-a fixed state a few times with the library's kernel timer on, and the
-class's own kernel time decides; the per-class picks are then kept only if
-the whole graph-replayed step runs faster with them than with the default
-shapes.  Shapes never change results (tested bit for bit), only time.
+By default the batched step runs every order class in one launch.  The
+alternative is one launch per order class p, whose flux kernel's shape is a
+number of waves per block (1, 2 or 4: 64, 128 or 256 threads, i.e. 32p ...
+128/p interfaces per block round) and a number of persistent blocks per CU
+(the occupancy limit, or fewer).  The per-class launches are independent,
+so each is tuned on its own: every candidate shape runs the whole batched
+step on a fixed state a few times with the library's kernel timer on, and
+the class's own kernel time decides; the per-class picks are then kept only
+if the whole graph-replayed step runs faster with them than with the
+default single launch.  Launches never change results (tested bit for
+bit), only time.
 """
 from __future__ import annotations
 
@@ -34,41 +36,44 @@ def _time_classes(batch, u, dt, out, reps):
 
 def tune(batch, u: torch.Tensor, dt: torch.Tensor, reps: int = 5, waves=WAVES, per_cu=PER_CU,
          cache: str | None = None, verbose: bool = False) -> dict:
-    """Choose and set the fastest shape per order class; returns
-    {p: (waves, blocks_per_cu, ms)}.  With `cache` (a JSON file) a table
-    stored for the same batch signature is reused."""
+    """Choose and set the fastest launch: one launch per order class with the
+    fastest shape of each, or the default single launch of every class.
+    Returns {p: (waves, blocks_per_cu, ms)}: ms the class kernel's time, or
+    (0, 0, ms per step) for every p when the default launch is kept.  With
+    `cache` (a JSON file) a choice stored for the same batch signature is
+    reused."""
     key = signature(batch)
     if cache and os.path.exists(cache):
         stored = json.load(open(cache))
         if key in stored:
             table = {int(p): tuple(v[:2]) for p, v in stored[key].items()}
-            batch.set_launch(table)
+            batch.set_launch(None if all(v[0] == 0 for v in table.values()) else table)
             return {int(p): tuple(v) for p, v in stored[key].items()}
     out = torch.empty_like(u)
     batch.set_launch(None)
     batch.step(u, dt, out=out)               # warm-up (modules loaded)
-    best, default = {}, {}
+    best = {}
     for wv in waves:
         for pc in per_cu:
             batch.set_launch({p: (wv, pc) for p in batch.orders})
             times = _time_classes(batch, u, dt, out, reps)
-            if (wv, pc) == (4, 0):
-                default = dict(times)
             for p, ms in times.items():
                 if verbose:
                     print(f"[tune] p={p} waves={wv} per_cu={pc}: {ms * 1e3:.1f} us", flush=True)
                 if p not in best or ms < best[p][2]:
                     best[p] = (wv, pc, ms)
     # the per-class optimum is kept only if the whole graph-replayed step is
-    # at least 2 % faster with it than with the default shapes (shapes interact through
-    # the caches and the scheduler; the default is never beaten by a worse pick)
+    # at least 2 % faster with it than with the default single launch (the
+    # launches interact through the caches and the scheduler; the default is
+    # never replaced by a slower pick)
     tuned = {p: (v[0], v[1]) for p, v in best.items()}
     t_tuned = _time_graph(batch, u, dt, tuned)
     t_default = _time_graph(batch, u, dt, None)
     if verbose:
-        print(f"[tune] graph-replayed step: tuned {t_tuned * 1e3:.1f} us, default {t_default * 1e3:.1f} us", flush=True)
+        print(f"[tune] graph-replayed step: tuned {t_tuned * 1e3:.1f} us, default {t_default * 1e3:.1f} us",
+              flush=True)
     if not t_tuned < 0.98 * t_default:      # within 2 %: timing noise, keep the default
-        best = {p: (4, 0, default.get(p, v[2])) for p, v in best.items()}
+        best = {p: (0, 0, t_default) for p in best}   # waves 0: the default single launch of every class
         tuned = None
     batch.set_launch(tuned)
     if cache:

@@ -344,6 +344,7 @@ KBatch make_kbatch(const acat_batch* bt, const BLayout& L, char* w) {
     k.waves[p] = bt->launch && bt->launch[2 * (p - 1)] > 0 ? bt->launch[2 * (p - 1)] : 4;
     k.per_cu[p] = bt->launch ? bt->launch[2 * (p - 1) + 1] : 0;
   }
+  k.fused_flux = bt->launch ? 0 : 1;
   k.waves[0] = 4;
   k.per_cu[0] = 0;
   return k;

@@ -58,16 +58,24 @@ __global__ __launch_bounds__(BLOCK) void k_classify_b(KBatch bt, KBStep st) {
   block_hist(sh, valid, ps - 1, st.hist);
 }
 
+// LDS doubles of the exchange buffers of order p at BS threads per block
+template <int NV, int p, int BS>
+constexpr int flux_b_lds() {
+  return 2 * NV * Groups<2 * p, BS>::TOTAL * (2 * p + 1);
+}
+
 // Interfaces of order p of every problem (same arithmetic as k_flux1d), BS
-// threads per block: BS / 2p interfaces per round.
+// threads per block: BS / 2p interfaces per round; the block's share of the
+// class list is `sl`; xsmem: the block's LDS exchange buffers
+// (flux_b_lds<NV, p, BS>() doubles).
 template <int FLUX, int NV, int p, int BS>
-__global__ __launch_bounds__(BS) void k_flux_b(KBatch bt, KBStep st) {
+__device__ __forceinline__ void flux_b_body(const KBatch& bt, const KBStep& st, const Slice& sl, double* xsmem) {
   constexpr int L = 2 * p;
   using Grp = Groups<L, BS>;
   constexpr int GPB = Grp::PER_BLOCK;
   constexpr int SL = L + 1;
   constexpr int NS = Grp::TOTAL * SL;
-  __shared__ double xs[2][NV][NS];
+  auto& xs = *reinterpret_cast<double (*)[2][NV][NS]>(xsmem);
 
   const Grp grp(threadIdx.x);
   const int g = grp.g;
@@ -80,7 +88,6 @@ __global__ __launch_bounds__(BS) void k_flux_b(KBatch bt, KBStep st) {
   for (int l = 0; l < L; ++l) g1[l] = TB.G1[p][a][l];
 
   int buf = 0;
-  const Slice sl(st.counts, st.list, p - 1);
   for (int64_t base = sl.lo; base < sl.hi; base += GPB) {
     const bool valid = inblk && base + g < sl.hi;
     const int64_t kg = valid ? sl.items[base + g] : 0;
@@ -186,6 +193,64 @@ __global__ __launch_bounds__(BS) void k_flux_b(KBatch bt, KBStep st) {
       }
     }
     buf ^= 1;
+  }
+}
+
+template <int FLUX, int NV, int p, int BS>
+__global__ __launch_bounds__(BS) void k_flux_b(KBatch bt, KBStep st) {
+  __shared__ double xsmem[flux_b_lds<NV, p, BS>()];
+  flux_b_body<FLUX, NV, p, BS>(bt, st, Slice(st.counts, st.list, p - 1), xsmem);
+}
+
+// Every order class in one persistent launch (256 threads per block): the
+// grid is cut into runs of whole XCD groups of blocks, one run per class
+// with interfaces, sized by the class's work (interfaces times the flops of
+// one interface of that order); each block runs the kernel body of its
+// class over its share of that class's list.  Same arithmetic per interface
+// as the per-class launches.
+template <int NV>
+constexpr int flux_b_all_lds() {
+  constexpr int a = flux_b_lds<NV, 1, BLOCK>(), b = flux_b_lds<NV, 2, BLOCK>();
+  constexpr int c = flux_b_lds<NV, 3, BLOCK>(), d = flux_b_lds<NV, 4, BLOCK>();
+  constexpr int ab = a > b ? a : b, cd = c > d ? c : d;
+  return ab > cd ? ab : cd;
+}
+
+template <int FLUX, int NV>
+__global__ __launch_bounds__(BLOCK) void k_flux_b_all(KBatch bt, KBStep st) {
+  __shared__ double xsmem[flux_b_all_lds<NV>()];
+  // relative cost of one interface of order p (1D Euler flops of the recursion)
+  constexpr int64_t cost[BATCH_PMAX + 1] = {0, 172, 1268, 4650, 11528};
+  const int units = (int)gridDim.x / NXCD;
+  int64_t work[BATCH_PMAX + 1], total = 0;
+  int nz = 0;
+#pragma unroll
+  for (int p = 1; p <= BATCH_PMAX; ++p) {
+    work[p] = p <= bt.Pmax ? (int64_t)st.counts[p - 1] * cost[p] : 0;
+    total += work[p];
+    nz += work[p] > 0;
+  }
+  if (total == 0) return;
+  // units per class: one each for classes with work, the rest in proportion to the work
+  int u[BATCH_PMAX + 1], used = 0;
+#pragma unroll
+  for (int p = 1; p <= BATCH_PMAX; ++p) {
+    u[p] = work[p] > 0 ? 1 + (int)((int64_t)(units - nz) * work[p] / total) : 0;
+    used += u[p];
+  }
+  const int unit = (int)blockIdx.x / NXCD;
+  if (unit >= used) return;
+  int p = 1, first = 0;
+  while (unit >= first + u[p]) {
+    first += u[p];
+    ++p;
+  }
+  const int blk = (int)blockIdx.x - first * NXCD, nblk = u[p] * NXCD;
+  switch (p) {
+    case 1: flux_b_body<FLUX, NV, 1, BLOCK>(bt, st, Slice(st.counts, st.list, 0, blk, nblk), xsmem); break;
+    case 2: flux_b_body<FLUX, NV, 2, BLOCK>(bt, st, Slice(st.counts, st.list, 1, blk, nblk), xsmem); break;
+    case 3: flux_b_body<FLUX, NV, 3, BLOCK>(bt, st, Slice(st.counts, st.list, 2, blk, nblk), xsmem); break;
+    default: flux_b_body<FLUX, NV, 4, BLOCK>(bt, st, Slice(st.counts, st.list, 3, blk, nblk), xsmem); break;
   }
 }
 
@@ -340,10 +405,22 @@ hipError_t step_b_impl(const KBatch& bt, const KBStep& st, hipStream_t s) {
                                                          st.list);
   ACAT_CHECK_LAUNCH();
   hipError_t e;
-  if ((e = launch_flux_b<FLUX, NV, 1>(bt, st, s)) != hipSuccess) return e;
-  if ((e = launch_flux_b<FLUX, NV, 2>(bt, st, s)) != hipSuccess) return e;
-  if ((e = launch_flux_b<FLUX, NV, 3>(bt, st, s)) != hipSuccess) return e;
-  if ((e = launch_flux_b<FLUX, NV, 4>(bt, st, s)) != hipSuccess) return e;
+  if (bt.fused_flux) {
+    // one persistent launch for every order class
+    auto kern = k_flux_b_all<FLUX, NV>;
+    int grid = persistent_grid(kern, bt.nif, 0);
+    if (grid < NXCD * BATCH_PMAX) grid = NXCD * BATCH_PMAX;   // at least one XCD group per class
+    {
+      ProfScope ps("flux_b_all", s);
+      kern<<<grid, BLOCK, 0, s>>>(bt, st);
+    }
+    ACAT_CHECK_LAUNCH();
+  } else {
+    if ((e = launch_flux_b<FLUX, NV, 1>(bt, st, s)) != hipSuccess) return e;
+    if ((e = launch_flux_b<FLUX, NV, 2>(bt, st, s)) != hipSuccess) return e;
+    if ((e = launch_flux_b<FLUX, NV, 3>(bt, st, s)) != hipSuccess) return e;
+    if ((e = launch_flux_b<FLUX, NV, 4>(bt, st, s)) != hipSuccess) return e;
+  }
   {
     ProfScope ps("update_b", s);
     const unsigned grid = (unsigned)((bt.ncell + BLOCK - 1) / BLOCK);

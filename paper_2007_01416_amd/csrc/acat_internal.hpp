@@ -113,6 +113,7 @@ struct KBatch {
   const int32_t* pcell;     // [ncell] problem of each cell
   int waves[BATCH_PMAX + 1];    // per order class p: waves per block of the flux kernel (1, 2 or 4)
   int per_cu[BATCH_PMAX + 1];   // per order class p: persistent blocks per CU (0: occupancy limit)
+  int fused_flux;               // every order class in one launch (k_flux_b_all) instead of one per class
 };
 
 struct KBStep {

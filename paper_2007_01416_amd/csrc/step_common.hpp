@@ -135,13 +135,21 @@ struct Slice {
   const int32_t* items;
   int64_t lo, hi;
   __device__ Slice(const int32_t* counts, const int32_t* list, int c) {
+    init(counts, list, c, blockIdx.x, gridDim.x);
+  }
+  // block `blk` of `nblk` blocks working on class c (nblk a multiple of the
+  // XCD count, and blk on XCD blk % NXCD)
+  __device__ Slice(const int32_t* counts, const int32_t* list, int c, int blk, int nblk) {
+    init(counts, list, c, blk, nblk);
+  }
+  __device__ void init(const int32_t* counts, const int32_t* list, int c, int blk, int nblk) {
     int64_t base = 0;
     for (int k = 0; k < c; ++k) base += counts[k];
     const int64_t n = counts[c];
-    const int nb = gridDim.x / NXCD;
-    const int r = (blockIdx.x % NXCD) * nb + blockIdx.x / NXCD;
-    lo = n * r / gridDim.x;
-    hi = n * (r + 1) / gridDim.x;
+    const int nb = nblk / NXCD;
+    const int r = (blk % NXCD) * nb + blk / NXCD;
+    lo = n * r / nblk;
+    hi = n * (r + 1) / nblk;
     items = list + base;
   }
 };
