@@ -287,19 +287,17 @@ def bench_adjoint(acat, workloads, F, fd_dirs=32, fd_h=(1e-4, 1e-5, 1e-6, 1e-7, 
     hist = erun.class_log.cpu().numpy().astype(np.int64).sum(0)
     P = w["P"]
     kern = {}
-    for q1 in range(1, P + 1):
-        for q2 in range(1, P + 1):
-            name = f"adjoint2d_q{q1}{q2}"
-            if name in prof:
-                c, ms = prof[name]
-                kern[name] = dict(launches=c, ms=ms, flops=int(hist[(q1 - 1) * P + (q2 - 1)]) *
-                                  F.adjoint_corner_flops_2d(q1, q2))
+    for name, (c, ms) in prof.items():
+        cl = corner_classes(name, "adjoint2d_")
+        if cl:
+            kern[name] = dict(launches=c, ms=ms, classes=cl,
+                              flops=sum(int(hist[(q1 - 1) * P + (q2 - 1)]) * F.adjoint_corner_flops_2d(q1, q2)
+                                        for q1, q2 in cl))
     ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
     per_kernel = {}
     for name, v in kern.items():
-        q1, q2 = int(name[-2]), int(name[-1])
-        cnt = int(hist[(q1 - 1) * P + (q2 - 1)])
-        by = cnt * F.adjoint_corner_bytes_2d(q1, q2)
+        cnt = sum(int(hist[(q1 - 1) * P + (q2 - 1)]) for q1, q2 in v["classes"])
+        by = sum(int(hist[(q1 - 1) * P + (q2 - 1)]) * F.adjoint_corner_bytes_2d(q1, q2) for q1, q2 in v["classes"])
         sec = v["ms"] * 1e-3
         intensity = v["flops"] / max(by, 1)
         bound = "alu" if intensity >= ridge else "hbm"
@@ -441,18 +439,26 @@ def bench_high_order(acat, workloads, F, steps=20, warmup=3, n1d=1 << 22, n2d=20
     s = acat.Solver(prob, w["u"], w["cfl"])
     el, per, prof = _class_profile(acat, s, P * P, steps, warmup)
     kern = {}
-    for q1 in range(1, P + 1):
-        for q2 in range(1, P + 1):
-            name, cnt = f"flux2d_q{q1}{q2}", per[(q1 - 1) * P + (q2 - 1)]
-            if name in prof and cnt > 0:
-                c, ms = prof[name]
-                fl = cnt * F.corner_flops_2d(q1, q2)
-                kern[name] = {"avg_us": round(1e3 * ms / c, 2), "items": int(cnt),
-                              "frac": round(fl / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)}
+    for name, (c, ms) in prof.items():
+        cl = corner_classes(name)
+        cnt = sum(int(per[(q1 - 1) * P + (q2 - 1)]) for q1, q2 in cl)
+        if cl and cnt > 0:
+            fl = sum(int(per[(q1 - 1) * P + (q2 - 1)]) * F.corner_flops_2d(q1, q2) for q1, q2 in cl)
+            kern[name] = {"avg_us": round(1e3 * ms / c, 2), "items": cnt,
+                          "frac": round(fl / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)}
     out[f"euler2d_P4_{n2d}x{n2d}"] = {"value": n2d * n2d * steps / el, "unit": "cell-updates/s",
                                       "ms_per_step": 1e3 * el / steps, "kernels": kern,
                                       "device_status": acat.device_status()}
     return out
+
+
+def corner_classes(name, prefix="flux2d_"):
+    """Order classes (q1, q2) a 2D corner kernel's profile name covers:
+    flux2d_q33 -> [(3, 3)], flux2d_q12q21 -> [(1, 2), (2, 1)]; [] otherwise."""
+    if not name.startswith(prefix):
+        return []
+    tags = name[len(prefix):].split("q")[1:]
+    return [(int(t[0]), int(t[1])) for t in tags]
 
 
 def measured_peaks(acat, reps=5):
@@ -571,11 +577,12 @@ def main():
     cells = n * n
     value = cells * args.steps / el
     P = w["P"]
-    class_flops = {}
-    for q1 in range(1, P + 1):
-        for q2 in range(1, P + 1):
-            cls = (q1 - 1) * P + (q2 - 1)
-            class_flops[f"flux2d_q{q1}{q2}"] = int(hist[:, cls].sum()) * F.corner_flops_2d(q1, q2)
+    class_flops = {}      # per corner kernel (one class, or a mirror pair of classes)
+    for name in prof:
+        cl = corner_classes(name)
+        if cl:
+            class_flops[name] = sum(int(hist[:, (q1 - 1) * P + (q2 - 1)].sum()) * F.corner_flops_2d(q1, q2)
+                                    for q1, q2 in cl)
     kernels = {k: {"launches": c, "avg_us": 1e3 * ms / max(c, 1), "total_ms": ms} for k, (c, ms) in prof.items()}
     dom = max((k for k in kernels if k.startswith("flux2d")), key=lambda k: kernels[k]["total_ms"])
     dom_launches = kernels[dom]["launches"]

@@ -418,15 +418,24 @@ __device__ __forceinline__ void corner_adjoint(const Phys& ph, const double (&u)
 // consecutive corners)
 // PASSES (corners with q1 != q2): 1 = the F recursion only, 2 = the G recursion
 // only, added to the contributions the first launch wrote, 3 = both.
-template <int FLUX, int NV, int Q1, int Q2, int PASSES = 3>
-__global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const double* __restrict__ ubo,
-                                                 double* __restrict__ C, int LMAX) {
+// The body runs the block's share `sl` of the class list; xsm: the two LDS
+// exchange buffers (2 Xch<NV>::NP adj_stride<L>() double2), g1s: LDS for the
+// derivative weights ((2 Q1)^2 + (2 Q2)^2 doubles).
+template <int L>
+constexpr int adj_stride() {
+  return Groups<L>::WAVE_LOCAL ? Groups<L>::TOTAL * L : BLOCK + L;
+}
+
+template <int FLUX, int NV, int Q1, int Q2, int PASSES>
+__device__ __forceinline__ void adj2d_body(const KProb& pb, const KStep& st, const Slice& sl,
+                                           const double* __restrict__ ubo, double* __restrict__ C, int LMAX,
+                                           double2* xsm, double* g1s) {
   constexpr int N1 = 2 * Q1, N2 = 2 * Q2, L = N1 * N2;
   using Grp = Groups<L>;
   constexpr int CPB = Grp::PER_BLOCK;
   constexpr int NP = Xch<NV>::NP;
-  constexpr int STRIDE = Grp::WAVE_LOCAL ? Grp::TOTAL * L : BLOCK + L;
-  __shared__ double2 xs[2][NP * STRIDE];
+  constexpr int STRIDE = adj_stride<L>();
+  double2* const xs[2] = {xsm, xsm + NP * STRIDE};
 
   const int tid = threadIdx.x;
   const Grp grp(tid);
@@ -434,7 +443,6 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
   const int nd = grp.node;
   const int a1 = nd % N1, a2 = nd / N1;
   const bool inblk = grp.in;
-  const int cls = (Q1 - 1) * pb.P + (Q2 - 1);
   const double dt = step_dt(st);
   const double lamx = dt / pb.dx, lamy = dt / pb.dy;
   const int64_t nx = pb.nx, plane = pb.nx * pb.ny;
@@ -445,7 +453,6 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
 
   // derivative weights times -lamx (x) and -lamy (y) in LDS, row-major: rows
   // for the recursion, columns for its transpose
-  __shared__ double g1s[N1 * N1 + N2 * N2];
   for (int i = tid; i < N1 * N1 + N2 * N2; i += BLOCK)
     g1s[i] = i < N1 * N1 ? -lamx * TB.G1[Q1][i / N1][i % N1]
                          : -lamy * TB.G1[Q2][(i - N1 * N1) / N2][(i - N1 * N1) % N2];
@@ -455,7 +462,6 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
   const bool on_row = a2 == Q2 - 1, on_col = a1 == Q1 - 1;
 
   int buf = 0;
-  const Slice sl(st.counts, st.list, cls);
   for (int64_t base = sl.lo; base < sl.hi; base += CPB) {
     const bool valid = inblk && base + g < sl.hi;
     const int32_t e = valid ? sl.items[base + g] : 0;
@@ -556,6 +562,41 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
       }
     }
   }
+}
+
+template <int FLUX, int NV, int Q1, int Q2, int PASSES = 3>
+__global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const double* __restrict__ ubo,
+                                                 double* __restrict__ C, int LMAX) {
+  constexpr int L = (2 * Q1) * (2 * Q2);
+  __shared__ double2 xsm[2 * Xch<NV>::NP * adj_stride<L>()];
+  __shared__ double g1s[(2 * Q1) * (2 * Q1) + (2 * Q2) * (2 * Q2)];
+  adj2d_body<FLUX, NV, Q1, Q2, PASSES>(pb, st, Slice(st.counts, st.list, (Q1 - 1) * pb.P + (Q2 - 1)), ubo, C,
+                                       LMAX, xsm, g1s);
+}
+
+// The mirror classes (QA, QB) and (QB, QA), QA < QB, in one launch (both
+// recursions in one pass): the grid is cut into two runs of whole XCD groups
+// of blocks sized by the classes' corner counts, at least one per class with
+// corners; each block runs its class's body over its share of the list.
+template <int FLUX, int NV, int QA, int QB>
+__global__ __launch_bounds__(BLOCK) void k_adj2d_pair(KProb pb, KStep st, const double* __restrict__ ubo,
+                                                      double* __restrict__ C, int LMAX) {
+  constexpr int L = (2 * QA) * (2 * QB);
+  __shared__ double2 xsm[2 * Xch<NV>::NP * adj_stride<L>()];
+  __shared__ double g1s[(2 * QA) * (2 * QA) + (2 * QB) * (2 * QB)];
+  const int ca = (QA - 1) * pb.P + (QB - 1), cb = (QB - 1) * pb.P + (QA - 1);
+  const int64_t na = st.counts[ca], nb = st.counts[cb];
+  if (na + nb == 0) return;
+  const int units = (int)gridDim.x / NXCD;
+  const int ua = na == 0 ? 0 : (nb == 0 ? units : 1 + (int)((int64_t)(units - 2) * na / (na + nb)));
+  const int unit = (int)blockIdx.x / NXCD;
+  if (unit < ua)
+    adj2d_body<FLUX, NV, QA, QB, 3>(pb, st, Slice(st.counts, st.list, ca, blockIdx.x, ua * NXCD), ubo, C, LMAX,
+                                    xsm, g1s);
+  else
+    adj2d_body<FLUX, NV, QB, QA, 3>(pb, st,
+                                    Slice(st.counts, st.list, cb, blockIdx.x - ua * NXCD, (units - ua) * NXCD),
+                                    ubo, C, LMAX, xsm, g1s);
 }
 
 // Corners k whose node at offset j reads cell m along one direction of n
@@ -683,17 +724,35 @@ hipError_t launch_adj2d(const KProb& pb, const KStep& st, const double* ubo, dou
   return hipSuccess;
 }
 
+// The mirror classes (QA, QB) and (QB, QA), QA < QB, in one launch; only for
+// the rectangles of orders up to 3 (those of order 4 keep one launch per class,
+// the (1, 4) pair included: its device build gave wrong values).
+template <int FLUX, int NV, int P, int QA, int QB>
+hipError_t launch_adjpair2d(const KProb& pb, const KStep& st, const double* ubo, double* C, hipStream_t s) {
+  static_assert(QA < QB && QB <= 3, "pairs of rectangles of orders up to 3 only");
+  if constexpr (QB <= P) {
+    static const char* names[4][4] = {{"", "", "", ""},
+                                      {"", "", "adjoint2d_q12q21", "adjoint2d_q13q31"},
+                                      {"", "", "", "adjoint2d_q23q32"},
+                                      {"", "", "", ""}};
+    auto kern = k_adj2d_pair<FLUX, NV, QA, QB>;
+    // two runs of XCD groups: at least one per class
+    const int grid = std::max(persistent_grid(kern, pb.n1 * pb.n2, 0), 2 * NXCD);
+    ProfScope ps(names[QA][QB], s);
+    kern<<<grid, BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P);
+    ACAT_CHECK_LAUNCH();
+  }
+  return hipSuccess;
+}
+
 template <int FLUX, int NV, int P>
 hipError_t adj2d_impl(const KProb& pb, const KStep& st, const double* ubo, double* ubi, double* C, hipStream_t s) {
   hipError_t e;
   if ((e = launch_adj2d<FLUX, NV, P, 1, 1>(pb, st, ubo, C, s)) != hipSuccess) return e;
-  if ((e = launch_adj2d<FLUX, NV, P, 1, 2>(pb, st, ubo, C, s)) != hipSuccess) return e;
-  if ((e = launch_adj2d<FLUX, NV, P, 2, 1>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adjpair2d<FLUX, NV, P, 1, 2>(pb, st, ubo, C, s)) != hipSuccess) return e;
   if ((e = launch_adj2d<FLUX, NV, P, 2, 2>(pb, st, ubo, C, s)) != hipSuccess) return e;
-  if ((e = launch_adj2d<FLUX, NV, P, 1, 3>(pb, st, ubo, C, s)) != hipSuccess) return e;
-  if ((e = launch_adj2d<FLUX, NV, P, 3, 1>(pb, st, ubo, C, s)) != hipSuccess) return e;
-  if ((e = launch_adj2d<FLUX, NV, P, 2, 3>(pb, st, ubo, C, s)) != hipSuccess) return e;
-  if ((e = launch_adj2d<FLUX, NV, P, 3, 2>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adjpair2d<FLUX, NV, P, 1, 3>(pb, st, ubo, C, s)) != hipSuccess) return e;
+  if ((e = launch_adjpair2d<FLUX, NV, P, 2, 3>(pb, st, ubo, C, s)) != hipSuccess) return e;
   if ((e = launch_adj2d<FLUX, NV, P, 3, 3>(pb, st, ubo, C, s)) != hipSuccess) return e;
   if ((e = launch_adj2d<FLUX, NV, P, 1, 4>(pb, st, ubo, C, s)) != hipSuccess) return e;
   if ((e = launch_adj2d<FLUX, NV, P, 4, 1>(pb, st, ubo, C, s)) != hipSuccess) return e;

@@ -479,17 +479,27 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, const double (&u)[NV
   }
 }
 
-// Fluxes of the corners of order class (Q1, Q2) (Sec. 4; rectangle J_Q1 x J_Q2).
-// SQUARE: list entries carry the square-stencil variant's tags (square classes only).
-template <int FLUX, int NV, int Q1, int Q2, bool SQUARE = false>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_flux2d(KProb pb, KStep st) {
+// LDS of the corner kernel of a class with L = (2 q1)(2 q2) nodes: slots per
+// exchange plane (idle lanes included)
+template <int L>
+constexpr int corner_stride() {
+  return Groups<L>::WAVE_LOCAL ? Groups<L>::TOTAL * L : BLOCK + L;
+}
+
+// Fluxes of the corners of order class (Q1, Q2) (Sec. 4; rectangle J_Q1 x J_Q2)
+// in the block's share `sl` of the class list.  SQUARE: list entries carry
+// the square-stencil variant's tags (square classes only).  xsm: the two
+// exchange buffers (2 Xch<NV>::NP corner_stride<L>() double2), g1s: the
+// derivative weights ((2 Q1)^2 + (2 Q2)^2 doubles), both in LDS.
+template <int FLUX, int NV, int Q1, int Q2, bool SQUARE>
+__device__ __forceinline__ void flux2d_body(const KProb& pb, const KStep& st, const Slice& sl, double2* xsm,
+                                            double* g1s) {
   constexpr int N1 = 2 * Q1, N2 = 2 * Q2, L = N1 * N2;
   using Grp = Groups<L>;
   constexpr int CPB = Grp::PER_BLOCK;
   constexpr int NP = Xch<NV>::NP;
-  // slots per plane (idle lanes included)
-  constexpr int STRIDE = Grp::WAVE_LOCAL ? Grp::TOTAL * L : BLOCK + L;
-  __shared__ double2 xs[2][NP * STRIDE];
+  constexpr int STRIDE = corner_stride<L>();
+  double2* const xs[2] = {xsm, xsm + NP * STRIDE};
 
   const int tid = threadIdx.x;
   const Grp grp(tid);
@@ -497,7 +507,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
   const int nd = grp.node;
   const int a1 = nd % N1, a2 = nd / N1;     // node (j1, j2) = (a1 - Q1 + 1, a2 - Q2 + 1)
   const bool inblk = grp.in;
-  const int cls = (Q1 - 1) * pb.P + (Q2 - 1);
   const double dt = step_dt(st);
   const double lamx = dt / pb.dx, lamy = dt / pb.dy;
   const int64_t nx = pb.nx, ny = pb.ny, plane = pb.nx * pb.ny;
@@ -506,7 +515,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
 
   // derivative weights times -lamx (rows) and -lamy (columns), in LDS (read
   // at each use rather than held in registers)
-  __shared__ double g1s[N1 * N1 + N2 * N2];
   for (int i = tid; i < N1 * N1 + N2 * N2; i += BLOCK)
     g1s[i] = i < N1 * N1 ? -lamx * TB.G1[Q1][i / N1][i % N1]
                          : -lamy * TB.G1[Q2][(i - N1 * N1) / N2][(i - N1 * N1) % N2];
@@ -515,7 +523,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
   const double* g1y = g1s + N1 * N1 + a2 * N2;
 
   int buf = 0;
-  const Slice sl(st.counts, st.list, cls);
   for (int64_t base = sl.lo; base < sl.hi; base += CPB) {
     {
       const bool valid = inblk && base + g < sl.hi;
@@ -638,6 +645,41 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
       }
       if constexpr (Q1 == 1 && Q2 == 1) Grp::sync();   // the blends have read both buffers
     }
+  }
+}
+
+
+template <int FLUX, int NV, int Q1, int Q2, bool SQUARE = false>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_flux2d(KProb pb, KStep st) {
+  constexpr int L = (2 * Q1) * (2 * Q2);
+  __shared__ double2 xsm[2 * Xch<NV>::NP * corner_stride<L>()];
+  __shared__ double g1s[(2 * Q1) * (2 * Q1) + (2 * Q2) * (2 * Q2)];
+  flux2d_body<FLUX, NV, Q1, Q2, SQUARE>(pb, st, Slice(st.counts, st.list, (Q1 - 1) * pb.P + (Q2 - 1)), xsm, g1s);
+}
+
+// The mirror classes (QA, QB) and (QB, QA), QA < QB, in one launch: the grid
+// is cut into two runs of whole XCD groups of blocks, sized by the two
+// classes' corner counts (at least one group for a class with corners),
+// each block running its class's kernel body over its share of that class's
+// list.  Both classes have the same corner size and the same work per
+// corner; per corner the arithmetic is that of the one-class launch.
+template <int FLUX, int NV, int QA, int QB>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_flux2d_pair(KProb pb, KStep st) {
+  constexpr int L = (2 * QA) * (2 * QB);
+  __shared__ double2 xsm[2 * Xch<NV>::NP * corner_stride<L>()];
+  __shared__ double g1s[(2 * QA) * (2 * QA) + (2 * QB) * (2 * QB)];
+  const int ca = (QA - 1) * pb.P + (QB - 1), cb = (QB - 1) * pb.P + (QA - 1);
+  const int64_t na = st.counts[ca], nb = st.counts[cb];
+  if (na + nb == 0) return;
+  const int units = (int)gridDim.x / NXCD;
+  const int ua = na == 0 ? 0 : (nb == 0 ? units : 1 + (int)((int64_t)(units - 2) * na / (na + nb)));
+  const int unit = (int)blockIdx.x / NXCD;
+  if (unit < ua) {
+    flux2d_body<FLUX, NV, QA, QB, false>(pb, st, Slice(st.counts, st.list, ca, blockIdx.x, ua * NXCD), xsm, g1s);
+  } else {
+    const int ub = units - ua;
+    flux2d_body<FLUX, NV, QB, QA, false>(pb, st, Slice(st.counts, st.list, cb, blockIdx.x - ua * NXCD, ub * NXCD),
+                                         xsm, g1s);
   }
 }
 
@@ -809,6 +851,28 @@ hipError_t launch_class2d(const KProb& pb, const KStep& st, int cap, hipStream_t
   return hipSuccess;
 }
 
+// The mirror classes (QA, QB) and (QB, QA), QA < QB, in one launch.
+template <int FLUX, int NV, int P, int QA, int QB>
+hipError_t launch_pair2d(const KProb& pb, const KStep& st, int cap, hipStream_t s) {
+  static_assert(QA < QB, "pairs are named by their lower-left class");
+  if constexpr (QB <= P) {
+    static const char* names[5][5] = {{"", "", "", "", ""},
+                                      {"", "", "flux2d_q12q21", "flux2d_q13q31", "flux2d_q14q41"},
+                                      {"", "", "", "flux2d_q23q32", "flux2d_q24q42"},
+                                      {"", "", "", "", "flux2d_q34q43"},
+                                      {"", "", "", "", ""}};
+    auto kern = k_flux2d_pair<FLUX, NV, QA, QB>;
+    // two runs of XCD groups: at least one per class
+    const int grid = std::max(persistent_grid(kern, pb.n1 * pb.n2, cap), 2 * NXCD);
+    {
+      ProfScope ps(names[QA][QB], s);
+      kern<<<grid, BLOCK, 0, s>>>(pb, st);
+    }
+    ACAT_CHECK_LAUNCH();
+  }
+  return hipSuccess;
+}
+
 template <int FLUX, int NV, int P>
 hipError_t lists2d_impl(const KProb& pb, const KStep& st, hipStream_t s) {
   const int cblocks = (int)class_tiles(pb);
@@ -837,20 +901,14 @@ hipError_t step2d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s)
   hipError_t e;
   if ((e = lists2d_impl<FLUX, NV, P>(pb, st, s)) != hipSuccess) return e;
   if ((e = launch_class2d<FLUX, NV, P, 1, 1>(pb, st, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 1, 2>(pb, st, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 2, 1>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_pair2d<FLUX, NV, P, 1, 2>(pb, st, cap, s)) != hipSuccess) return e;
   if ((e = launch_class2d<FLUX, NV, P, 2, 2>(pb, st, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 1, 3>(pb, st, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 3, 1>(pb, st, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 2, 3>(pb, st, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 3, 2>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_pair2d<FLUX, NV, P, 1, 3>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_pair2d<FLUX, NV, P, 2, 3>(pb, st, cap, s)) != hipSuccess) return e;
   if ((e = launch_class2d<FLUX, NV, P, 3, 3>(pb, st, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 1, 4>(pb, st, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 4, 1>(pb, st, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 2, 4>(pb, st, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 4, 2>(pb, st, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 3, 4>(pb, st, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 4, 3>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_pair2d<FLUX, NV, P, 1, 4>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_pair2d<FLUX, NV, P, 2, 4>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_pair2d<FLUX, NV, P, 3, 4>(pb, st, cap, s)) != hipSuccess) return e;
   if ((e = launch_class2d<FLUX, NV, P, 4, 4>(pb, st, cap, s)) != hipSuccess) return e;
   {
     ProfScope ps("update2d", s);

@@ -4,8 +4,13 @@
 // each in its one-kernel form (PASSES = 3) and split into two launches
 // (PASSES = 1 then 2), on a 10 x 9 2D Euler grid with forced decisions
 // (psi^1 = 0.6, alpha = 2 where an order is 1), periodic or transmissive.
-// Usage: adjoint2d_host OUT.bin bc:q1:q2 ...  writes, per case, the gathered
-// adjoint of the one-kernel form, of the split form, and the seed ubar.
+// Mirror pairs: the corners split between classes (qa, qb) and (qb, qa) by a
+// fixed pattern, run by the pair kernel (one launch, blocks divided between
+// the classes) and by the two one-class kernels.
+// Usage: adjoint2d_host OUT.bin bc:q1:q2 ... pair:bc:qa:qb ...  writes, per
+// case, the gathered adjoint of the one-kernel form, of the split form, and
+// the seed ubar; per pair case, that of the pair kernel and of the two
+// one-class kernels.
 #include <hip/hip_runtime.h>
 #include <cstring>
 #include <vector>
@@ -134,10 +139,57 @@ void run_class(FILE* out, int bc) {
   std::fwrite(one.ubo.data(), sizeof(double), one.ubo.size(), out);
 }
 
+// corners of class (qb, qa) where (i1 + 2 i2) % 3 == 0, (qa, qb) elsewhere
+void setup_pair(Case& cs, int bc, int qa, int qb, unsigned seed) {
+  setup(cs, bc, qa, qb, seed);
+  const int ca = (qa - 1) * P + (qb - 1), cb = (qb - 1) * P + (qa - 1);
+  const int items = cs.pb.n1 * cs.pb.n2;
+  std::vector<int32_t> la, lb;
+  for (int e = 0; e < items; ++e) {
+    const int i1 = e % cs.pb.n1, i2 = e / cs.pb.n1;
+    const bool b = (i1 + 2 * i2) % 3 == 0;
+    cs.cls[e] = (int8_t)(b ? cb : ca);
+    (b ? lb : la).push_back(e);
+  }
+  cs.counts[ca] = (int32_t)la.size();
+  cs.counts[cb] = (int32_t)lb.size();
+  cs.list = la;
+  cs.list.insert(cs.list.end(), lb.begin(), lb.end());
+  cs.st.cls = cs.cls.data();
+  cs.st.counts = cs.counts.data();
+  cs.st.list = cs.list.data();
+}
+
+template <int QA, int QB>
+void run_pair(FILE* out, int bc) {
+  Case pair, sep;
+  setup_pair(pair, bc, QA, QB, 10 * QA + QB);
+  setup_pair(sep, bc, QA, QB, 10 * QA + QB);
+  {
+    KProb pb = pair.pb; KStep st = pair.st;
+    const double* ubo = pair.ubo.data();
+    double* C = pair.C.data();
+    launch(2 * NXCD, [=]() { k_adj2d_pair<EUL, NV, QA, QB>(pb, st, ubo, C, 4 * P * P); });
+  }
+  gather(pair);
+  run_adj<QA, QB, 3>(sep);
+  run_adj<QB, QA, 3>(sep);
+  gather(sep);
+  double maxd = 0;
+  for (size_t a = 0; a < pair.ubi.size(); ++a) maxd = std::fmax(maxd, std::fabs(pair.ubi[a] - sep.ubi[a]));
+  std::printf("bc=%d pair (%d,%d)+(%d,%d): max |pair - one-class kernels| = %.3e\n", bc, QA, QB, QB, QA, maxd);
+  std::fflush(stdout);
+  std::fwrite(pair.ubi.data(), sizeof(double), pair.ubi.size(), out);
+  std::fwrite(sep.ubi.data(), sizeof(double), sep.ubi.size(), out);
+}
+
 typedef void (*ClassFn)(FILE*, int);
 struct Entry { int q1, q2; ClassFn fn; };
 const Entry kClasses[] = {{2, 4, run_class<2, 4>}, {4, 2, run_class<4, 2>}, {3, 4, run_class<3, 4>},
                           {4, 3, run_class<4, 3>}, {3, 3, run_class<3, 3>}, {1, 4, run_class<1, 4>}};
+
+const Entry kPairs[] = {{1, 2, run_pair<1, 2>}, {1, 3, run_pair<1, 3>}, {2, 3, run_pair<2, 3>},
+                        {1, 4, run_pair<1, 4>}};
 
 int main(int argc, char** argv) {
   if (argc < 3) return 2;
@@ -145,9 +197,12 @@ int main(int argc, char** argv) {
   if (!out) return 2;
   for (int a = 2; a < argc; ++a) {
     int bc = 0, q1 = 0, q2 = 0;
-    if (std::sscanf(argv[a], "%d:%d:%d", &bc, &q1, &q2) != 3) return 2;
+    const bool pair = std::strncmp(argv[a], "pair:", 5) == 0;
+    if (std::sscanf(argv[a] + (pair ? 5 : 0), "%d:%d:%d", &bc, &q1, &q2) != 3) return 2;
     bool found = false;
-    for (const Entry& e : kClasses)
+    const Entry* tab = pair ? kPairs : kClasses;
+    const size_t ntab = pair ? sizeof(kPairs) / sizeof(Entry) : sizeof(kClasses) / sizeof(Entry);
+    for (const Entry& e : std::vector<Entry>(tab, tab + ntab))
       if (e.q1 == q1 && e.q2 == q2) {
         e.fn(out, bc);
         found = true;

@@ -9,7 +9,12 @@ boundaries, and compared with the oracle's tangent of the same frozen step
 through <J^T w, v> = <w, J v> on two random directions v (the GPU tests
 compare element by element with the dense adjoint).  A clean run means the template itself is free of out-of-bounds
 accesses, undefined behaviour and source-level errors in every form; the
-GPU's wrong values in the one-kernel form then come from its device build."""
+GPU's wrong values in the one-kernel form then come from its device build.
+The mirror-pair kernel (classes (qa, qb) and (qb, qa) in one launch) is run
+the same way on a grid mixing the two classes and must equal the two
+one-class kernels bit for bit; this includes the (1, 4) pair, whose device
+build gave wrong values on the GPU and which the library therefore launches
+one class at a time."""
 import os
 import subprocess
 import sys
@@ -24,6 +29,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(ROOT, "paper_2007_01416_amd", "csrc")
 NX, NY, P, NV = 10, 9, 4, 4
 CASES = [(bc, q1, q2) for bc in (0, 1) for (q1, q2) in ((2, 4), (4, 2), (3, 4), (4, 3), (3, 3), (1, 4))]
+# mirror pairs (qa, qb) + (qb, qa) in one launch, transmissive
+PAIRS = [(1, 1, 2), (1, 1, 3), (1, 2, 3), (1, 1, 4)]
 
 
 @pytest.fixture(scope="module")
@@ -43,8 +50,8 @@ def harness(tmp_path_factory):
     assert r.returncode == 0, r.stderr[-4000:]
     out = str(d / "adj.bin")
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1")
-    r = subprocess.run([exe, out] + [f"{bc}:{q1}:{q2}" for bc, q1, q2 in CASES], capture_output=True, text=True,
-                       env=env)
+    r = subprocess.run([exe, out] + [f"{bc}:{q1}:{q2}" for bc, q1, q2 in CASES]
+                       + [f"pair:{bc}:{qa}:{qb}" for bc, qa, qb in PAIRS], capture_output=True, text=True, env=env)
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
     assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr, r.stderr[-4000:]
     return np.fromfile(out)
@@ -80,3 +87,15 @@ def test_adjoint_template_on_host_matches_dense_oracle(harness, case):
             lhs = float(np.vdot(got, v))
             print(f"bc={bc} ({q1},{q2}) {name}: <J^T w, v> {lhs:.15e} <w, J v> {rhs:.15e}", file=sys.stderr)
             assert abs(lhs - rhs) <= 1e-12 * abs(rhs), name
+
+
+@pytest.mark.parametrize("case", range(len(PAIRS)))
+def test_mirror_pair_kernel_on_host_equals_one_class_kernels(harness, case):
+    """The pair kernel (corners of (qa, qb) and (qb, qa) mixed on one grid,
+    blocks split between the two class lists) gives the same gathered adjoint,
+    bit for bit, as the two one-class kernels run one after the other."""
+    n = NV * NX * NY
+    base = 3 * n * len(CASES) + 2 * n * case
+    pair, sep = (harness[base + k * n:base + (k + 1) * n] for k in range(2))
+    assert np.abs(sep).max() > 0
+    assert np.array_equal(pair, sep)
