@@ -23,6 +23,8 @@
 //   k_update*      conservative flux-difference update + status bits
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "acat_internal.hpp"
 #include "coeffs.hpp"
 #include "step_common.hpp"
@@ -388,6 +390,13 @@ __global__ __launch_bounds__(BLOCK) void k_classify2d(KProb pb, KStep st) {
   }
 }
 
+// f(integral_constant<int, k>) for k = 2, 3, ... in order (the recursion
+// levels, each compiled with its own constant k)
+template <class F, int... K>
+__device__ __forceinline__ void for_levels(F&& f, std::integer_sequence<int, K...>) {
+  (f(std::integral_constant<int, K + 2>{}), ...);
+}
+
 // One recursion over the rectangle J_Q1 x J_Q2 with time nodes J_QT
 // (Taylor order 2 QT).  Each lane is one node (a1, a2) and accumulates the
 // series SF = sum_k Fh^{k-1} / k! (DOF) and SG = sum_k Gh^{k-1} / k! (DOG)
@@ -418,11 +427,15 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, const double (&u)[NV
   for (int ri = 0; ri < 2 * QT; ++ri)
 #pragma unroll
     for (int c = 0; c < NV; ++c) W[ri][c] = u[c];
-#pragma unroll
-  for (int kk = 2; kk <= 2 * QT; ++kk) {
+  // one recursion level: exchange Fh^{kk-2}, Gh^{kk-2}; U^{kk-1}; predictions;
+  // Fh^{kk-1}, Gh^{kk-1} and their series terms (each level compiled with
+  // its own constant kk)
+  auto level = [&](auto kkc) {
+    constexpr int kk = decltype(kkc)::value;
     double2* xsw = buf ? xsb1 : xsb0;
     Xch<NV>::put(xsw, stride, slot, fc, gc);
     Groups<(2 * Q1) * (2 * Q2)>::sync();
+    buf ^= 1;
     const double* xr = reinterpret_cast<const double*>(xsw);
     // U^{kk-1} = -lamx d_x Fh^{kk-2} - lamy d_y Gh^{kk-2} at this node: one
     // chain of fused multiply-adds over the row (x) and then the column (y)
@@ -436,7 +449,6 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, const double (&u)[NV
       for (int l = 0; l < N2; ++l) s = fma(g1y[l], Xch<NV>::get(xr, stride, gbase + l * N1 + a1, c, true), s);
       Uk[c] = s;
     }
-    buf ^= 1;
 #pragma unroll
     for (int ri = 0; ri < 2 * QT; ++ri) {
       const int r = ri - QT + 1;
@@ -450,6 +462,16 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, const double (&u)[NV
       nf[c] = 0.0;
       ng[c] = 0.0;
     }
+    // Euler: the reciprocal densities of all predicted states first, their
+    // Newton steps interleaved (time node r = 0 is the node state: its flux
+    // is f0, g0)
+    double rho[2 * QT - 1], ir[2 * QT - 1];
+    if constexpr (FLUX == EUL) {
+#pragma unroll
+      for (int ri = 0; ri < 2 * QT; ++ri)
+        if (ri != QT - 1) rho[ri < QT - 1 ? ri : ri - 1] = W[ri][0];
+      recip_n(rho, ir);
+    }
 #pragma unroll
     for (int ri = 0; ri < 2 * QT; ++ri) {
       const int r = ri - QT + 1;
@@ -460,6 +482,8 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, const double (&u)[NV
           pf[c] = f0[c];
           pg[c] = g0[c];
         }
+      } else if constexpr (FLUX == EUL) {
+        euler2d_ir(ph, W[ri], ir[ri < QT - 1 ? ri : ri - 1], pf, pg);
       } else {
         flux2d<FLUX, NV>(ph, W[ri], pf, pg);
       }
@@ -476,14 +500,23 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, const double (&u)[NV
       if (DOF) SF[c] = fma(TB.INVFACT[kk], nf[c], SF[c]);
       if (DOG) SG[c] = fma(TB.INVFACT[kk], ng[c], SG[c]);
     }
-  }
+  };
+  for_levels(level, std::make_integer_sequence<int, 2 * QT - 1>{});
 }
 
-// LDS of the corner kernel of a class with L = (2 q1)(2 q2) nodes: slots per
-// exchange plane (idle lanes included)
+// Exchange slots of a group of L = (2 q1)(2 q2) corner nodes: node (a1, a2)
+// of group g at g GS + a2 (2 q1) + a1.  Groups of 36 nodes (class (3, 3))
+// start 38 slots apart: 36 apart, the first rows of two groups that share a
+// 16-lane phase of a 128-bit LDS access fall on the same banks.
+template <int L>
+constexpr int corner_group_stride() {
+  return L == 36 ? L + 2 : L;
+}
+
+// slots per exchange plane (spare groups of idle lanes included)
 template <int L>
 constexpr int corner_stride() {
-  return Groups<L>::WAVE_LOCAL ? Groups<L>::TOTAL * L : BLOCK + L;
+  return Groups<L>::TOTAL * corner_group_stride<L>();
 }
 
 // Fluxes of the corners of order class (Q1, Q2) (Sec. 4; rectangle J_Q1 x J_Q2)
@@ -499,6 +532,7 @@ __device__ __forceinline__ void flux2d_body(const KProb& pb, const KStep& st, co
   constexpr int CPB = Grp::PER_BLOCK;
   constexpr int NP = Xch<NV>::NP;
   constexpr int STRIDE = corner_stride<L>();
+  constexpr int GS = corner_group_stride<L>();
   double2* const xs[2] = {xsm, xsm + NP * STRIDE};
 
   const int tid = threadIdx.x;
@@ -541,15 +575,15 @@ __device__ __forceinline__ void flux2d_body(const KProb& pb, const KStep& st, co
       double f0[NV], g0[NV];
       flux2d<FLUX, NV>(pb.ph, u, f0, g0);
       double SF[NV], SG[NV];
-      const int slot = g * L + nd;
+      const int slot = g * GS + nd;
       if constexpr (Q1 == Q2) {
         corner_pass<FLUX, NV, Q1, Q2, Q1, true, true>(pb.ph, u, f0, g0, g1x, g1y, xs[0], xs[1],
-                                                      STRIDE, buf, slot, g * L, a1, a2, SF, SG);
+                                                      STRIDE, buf, slot, g * GS, a1, a2, SF, SG);
       } else {
         corner_pass<FLUX, NV, Q1, Q2, Q1, true, false>(pb.ph, u, f0, g0, g1x, g1y, xs[0], xs[1],
-                                                       STRIDE, buf, slot, g * L, a1, a2, SF, SG);
+                                                       STRIDE, buf, slot, g * GS, a1, a2, SF, SG);
         corner_pass<FLUX, NV, Q1, Q2, Q2, false, true>(pb.ph, u, f0, g0, g1x, g1y, xs[0], xs[1],
-                                                       STRIDE, buf, slot, g * L, a1, a2, SF, SG);
+                                                       STRIDE, buf, slot, g * GS, a1, a2, SF, SG);
       }
       // F_c = sum_l eta_l SF_(l,0),c and G_c = sum_l eta_l SG_(0,l),c on 2 NV lanes
       {
@@ -568,10 +602,10 @@ __device__ __forceinline__ void flux2d_body(const KProb& pb, const KStep& st, co
         double t = 0.0;
         if (!isG) {
 #pragma unroll
-          for (int l = 0; l < N1; ++l) t = fma(TB.ETA[Q1][l], Xch<NV>::get(xr, STRIDE, g * L + (Q2 - 1) * N1 + l, c, false), t);
+          for (int l = 0; l < N1; ++l) t = fma(TB.ETA[Q1][l], Xch<NV>::get(xr, STRIDE, g * GS + (Q2 - 1) * N1 + l, c, false), t);
         } else {
 #pragma unroll
-          for (int l = 0; l < N2; ++l) t = fma(TB.ETA[Q2][l], Xch<NV>::get(xr, STRIDE, g * L + l * N1 + (Q1 - 1), c, true), t);
+          for (int l = 0; l < N2; ++l) t = fma(TB.ETA[Q2][l], Xch<NV>::get(xr, STRIDE, g * GS + l * N1 + (Q1 - 1), c, true), t);
         }
         acc[tk] = t;
       }
@@ -608,7 +642,7 @@ __device__ __forceinline__ void flux2d_body(const KProb& pb, const KStep& st, co
             // nodes (0,0) and (1,0) (x) or (0,1) (y) of this corner
             const double* p0 = reinterpret_cast<const double*>(xs[0]);
             const double* p1 = reinterpret_cast<const double*>(xs[1]);
-            const int sl0 = g * L, slr = g * L + (isG ? N1 : 1);
+            const int sl0 = g * GS, slr = g * GS + (isG ? N1 : 1);
 #pragma unroll
             for (int cc = 0; cc < NV; ++cc) {
               uL[cc] = Xch<NV>::get(p0, STRIDE, sl0, cc, false);

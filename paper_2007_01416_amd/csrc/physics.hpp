@@ -70,6 +70,48 @@ __device__ __forceinline__ double recip(double x) {
   return fma(rem, r, r);
 }
 
+// recip() of N values at once, its steps interleaved across the values (the
+// same operations on each, so the same results)
+template <int N>
+__device__ __forceinline__ void recip_n(const double (&x)[N], double (&r)[N]) {
+  double e[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) r[i] = __builtin_amdgcn_rcp(x[i]);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) e[i] = fma(-x[i], r[i], 1.0);
+#pragma unroll
+    for (int i = 0; i < N; ++i) r[i] = fma(r[i], e[i], r[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) e[i] = fma(-x[i], r[i], 1.0);
+#pragma unroll
+  for (int i = 0; i < N; ++i) r[i] = fma(e[i], r[i], r[i]);
+}
+
+// 2D Euler fluxes at one state given ir = recip(rho)
+template <int NV>
+__device__ __forceinline__ void euler2d_ir(const Phys& ph, const double (&u)[NV], double ir, double (&f)[NV],
+                                           double (&g)[NV]) {
+  static_assert(NV == 4, "2D Euler has 4 conserved variables");
+  const double v = u[1] * ir;
+  const double w = u[2] * ir;
+  // the product-sums are fused multiply-adds: m v + n w, E - (m v + n w)/2,
+  // m v + p and n w + p, each rounded once
+  const double s = fma(u[1], v, u[2] * w);
+  const double p = ph.gm1 * fma(-0.5, s, u[3]);
+  const double ep = u[3] + p;
+  f[0] = u[1];
+  f[1] = fma(u[1], v, p);
+  f[2] = u[2] * v;
+  f[3] = v * ep;
+  g[0] = u[2];
+  g[1] = u[1] * w;
+  g[2] = fma(u[2], w, p);
+  g[3] = w * ep;
+}
+
 // x- and y-direction fluxes of a 2D law at one state (shared primitives)
 template <int FLUX, int NV>
 __device__ __forceinline__ void flux2d(const Phys& ph, const double (&u)[NV], double (&f)[NV], double (&g)[NV]) {
@@ -81,22 +123,7 @@ __device__ __forceinline__ void flux2d(const Phys& ph, const double (&u)[NV], do
     }
   } else {
     static_assert(FLUX == EUL && NV == 4, "2D Euler has 4 conserved variables");
-    const double ir = recip(u[0]);
-    const double v = u[1] * ir;
-    const double w = u[2] * ir;
-    // the product-sums are fused multiply-adds: m v + n w, E - (m v + n w)/2,
-    // m v + p and n w + p, each rounded once
-    const double s = fma(u[1], v, u[2] * w);
-    const double p = ph.gm1 * fma(-0.5, s, u[3]);
-    const double ep = u[3] + p;
-    f[0] = u[1];
-    f[1] = fma(u[1], v, p);
-    f[2] = u[2] * v;
-    f[3] = v * ep;
-    g[0] = u[2];
-    g[1] = u[1] * w;
-    g[2] = fma(u[2], w, p);
-    g[3] = w * ep;
+    euler2d_ir(ph, u, recip(u[0]), f, g);
   }
 }
 
