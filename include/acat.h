@@ -193,6 +193,24 @@ acat_status acat_step_adjoint(const acat_problem* prob, const double* u_in, doub
                               const acat_decisions* dec, const double* ubar_out, double* ubar_in,
                               void* workspace, size_t workspace_bytes, void* stream);
 
+/* acat_step_adjoint without its classification and list passes: the
+ * order-class map and per-class corner (2D) or interface (1D) lists are
+ * read from `step_workspace`, the workspace of the forward step of the same
+ * u_in whose decisions `dec` holds (acat_step or acat_step_cfl recording
+ * into `dec`, or acat_step_replay of `dec`; Sec. 3 order selection, the
+ * lists group the items by the order the step selected).  No call may have
+ * written step_workspace since that step.  Results equal acat_step_adjoint's
+ * bit for bit.  The pairing is the caller's: only the sizes are checked
+ * (ACAT_ERR_WORKSPACE when step_workspace_bytes < acat_workspace_size(prob));
+ * a workspace of another step gives wrong results, not an error.  The
+ * library reads step_workspace and does not modify it; `workspace` is the
+ * adjoint workspace as in acat_step_adjoint.  For a reverse sweep over many
+ * steps this keeps one step workspace per recomputed step. */
+acat_status acat_step_adjoint_lists(const acat_problem* prob, const double* u_in, double dt, const double* dt_dev,
+                                    const acat_decisions* dec, const double* ubar_out, double* ubar_in,
+                                    const void* step_workspace, size_t step_workspace_bytes, void* workspace,
+                                    size_t workspace_bytes, void* stream);
+
 /* smax_dev[d] = max over cells of the spectral radius of the flux Jacobian
  * in direction d (d < dim): |u| (Burgers), |a| (advection), |v|+c (Euler). */
 acat_status acat_max_wave_speed(const acat_problem* prob, const double* u, double* smax_dev, void* stream);

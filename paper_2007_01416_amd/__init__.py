@@ -65,6 +65,9 @@ _SIGS = {
     "acat_adjoint_workspace_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
     "acat_step_adjoint": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "acat_step_adjoint_lists": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "acat_max_wave_speed": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "acat_cfl_dt": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                     ctypes.c_void_p, ctypes.c_void_p],
@@ -282,6 +285,24 @@ def step_adjoint(prob: Problem, u: torch.Tensor, dt, dec: Decisions, ubar_out: t
     _check(load().acat_step_adjoint(ctypes.byref(prob.c()), _ptr(u), dtv, dtp, ctypes.byref(dec.c()),
                                     _ptr(ubar_out), _ptr(ubar_in), _ptr(ws), ws.numel(), _stream(stream)),
            "acat_step_adjoint")
+    return ubar_in
+
+
+def step_adjoint_lists(prob: Problem, u: torch.Tensor, dt, dec: Decisions, ubar_out: torch.Tensor,
+                       step_ws: torch.Tensor, ubar_in: torch.Tensor = None, ws: torch.Tensor = None,
+                       stream=None) -> torch.Tensor:
+    """step_adjoint reusing the class lists that the forward step of u with
+    decisions `dec` left in its workspace `step_ws`."""
+    _check_state(prob, u, "u")
+    _check_state(prob, ubar_out, "ubar_out")
+    ubar_in = torch.empty_like(u) if ubar_in is None else ubar_in
+    _check_state(prob, ubar_in, "ubar_in")
+    ws = adjoint_workspace(prob, u.device) if ws is None else ws
+    dtv, dtp = (float(dt), None) if not torch.is_tensor(dt) else (0.0, _ptr(dt))
+    _check(load().acat_step_adjoint_lists(ctypes.byref(prob.c()), _ptr(u), dtv, dtp, ctypes.byref(dec.c()),
+                                          _ptr(ubar_out), _ptr(ubar_in), _ptr(step_ws), step_ws.numel(),
+                                          _ptr(ws), ws.numel(), _stream(stream)),
+           "acat_step_adjoint_lists")
     return ubar_in
 
 

@@ -402,9 +402,11 @@ acat_status acat_adjoint_workspace_size(const acat_problem* prob, size_t* bytes)
   return ACAT_OK;
 }
 
-acat_status acat_step_adjoint(const acat_problem* prob, const double* u_in, double dt, const double* dt_dev,
-                              const acat_decisions* dec, const double* ubar_out, double* ubar_in, void* workspace,
-                              size_t workspace_bytes, void* stream) {
+// lists_ws: the workspace of the forward step whose class lists the adjoint
+// reuses (acat_step_adjoint_lists), or NULL to build them here
+acat_status do_adjoint(const acat_problem* prob, const double* u_in, double dt, const double* dt_dev,
+                       const acat_decisions* dec, const double* ubar_out, double* ubar_in, void* workspace,
+                       size_t workspace_bytes, const void* lists_ws, size_t lists_ws_bytes, void* stream) {
   acat_status rc = check_adjoint(prob);
   if (rc != ACAT_OK) return rc;
   if (!u_in || !ubar_out || !ubar_in || !dec) return ACAT_ERR_NULL;
@@ -433,13 +435,38 @@ acat_status acat_step_adjoint(const acat_problem* prob, const double* u_in, doub
   st.hist = reinterpret_cast<int32_t*>(w + L.hist);
   st.offs = reinterpret_cast<int32_t*>(w + L.offs);
   st.list = reinterpret_cast<int32_t*>(w + L.list);
+  if (lists_ws) {
+    // the forward step's class map, per-class counts and lists
+    const Layout F = layout(k);
+    if (lists_ws_bytes < F.total) return ACAT_ERR_WORKSPACE;
+    char* fw = const_cast<char*>(static_cast<const char*>(lists_ws));
+    st.counts = reinterpret_cast<int32_t*>(fw + F.hdr);
+    st.cls = reinterpret_cast<int8_t*>(fw + F.cls);
+    st.list = reinterpret_cast<int32_t*>(fw + F.list);
+  }
   st.status = status_ptr();
   if (!st.status) return ACAT_ERR_DEVICE;
   st.replay = 1;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_lists(k, st, s);
+  hipError_t e = lists_ws ? hipSuccess : launch_lists(k, st, s);
   if (e == hipSuccess) e = launch_adjoint(k, st, ubar_out, ubar_in, reinterpret_cast<double*>(w + L.C), s);
   return e == hipSuccess ? ACAT_OK : ACAT_ERR_DEVICE;
+}
+
+acat_status acat_step_adjoint(const acat_problem* prob, const double* u_in, double dt, const double* dt_dev,
+                              const acat_decisions* dec, const double* ubar_out, double* ubar_in, void* workspace,
+                              size_t workspace_bytes, void* stream) {
+  return do_adjoint(prob, u_in, dt, dt_dev, dec, ubar_out, ubar_in, workspace, workspace_bytes, nullptr, 0,
+                    stream);
+}
+
+acat_status acat_step_adjoint_lists(const acat_problem* prob, const double* u_in, double dt, const double* dt_dev,
+                                    const acat_decisions* dec, const double* ubar_out, double* ubar_in,
+                                    const void* step_workspace, size_t step_workspace_bytes, void* workspace,
+                                    size_t workspace_bytes, void* stream) {
+  if (!step_workspace) return ACAT_ERR_NULL;
+  return do_adjoint(prob, u_in, dt, dt_dev, dec, ubar_out, ubar_in, workspace, workspace_bytes, step_workspace,
+                    step_workspace_bytes, stream);
 }
 
 acat_status acat_max_wave_speed(const acat_problem* prob, const double* u, double* smax_dev, void* stream) {

@@ -12,13 +12,15 @@ with the decisions of every step (orders, psi^1, alpha) and its time step
 frozen at the forward run's values.  The forward keeps a state checkpoint
 every k steps; the backward recomputes each k-step segment from its
 checkpoint (recording decisions and time steps) and runs the adjoint steps
-of the segment in reverse.
+of the segment in reverse.  Each recomputed step keeps its own step
+workspace, so that its adjoint step reuses the step's order-class lists
+(acat_step_adjoint_lists) instead of classifying again.
 """
 from __future__ import annotations
 
 import torch
 
-from . import (Batch, Decisions, Problem, adjoint_workspace, cfl_dt, max_wave_speed, step, step_adjoint,
+from . import (Batch, Decisions, Problem, adjoint_workspace, cfl_dt, max_wave_speed, step, step_adjoint_lists,
                step_cfl, step_replay, workspace)
 
 
@@ -199,6 +201,7 @@ class AdjointRun:
         self.seg_dt = torch.zeros(k, dtype=torch.float64, device=device)
         self.seg_dec = [Decisions(prob, device) for _ in range(k)]
         self.seg_u = [torch.empty(shape, dtype=torch.float64, device=device) for _ in range(k)]
+        self.seg_ws = [workspace(prob, device) for _ in range(k)]   # one per recomputed step: its class lists
         self.seg_cls = torch.zeros((k, 16), dtype=torch.int32, device=device)
         self.fa = torch.empty(shape, dtype=torch.float64, device=device)    # forward state at segment bounds
         self.fb = torch.empty(shape, dtype=torch.float64, device=device)
@@ -225,12 +228,12 @@ class AdjointRun:
     def _bwd_body(self, m):
         for j in range(m):
             out = self.seg_u[j + 1] if j + 1 < m else self.tmp   # the segment's last state is not needed
-            step_cfl(self.prob, self.seg_u[j], self.cfl, self.seg_dt[j:j + 1], out=out, ws=self.ws,
+            step_cfl(self.prob, self.seg_u[j], self.cfl, self.seg_dt[j:j + 1], out=out, ws=self.seg_ws[j],
                      dec=self.seg_dec[j])
         for j in reversed(range(m)):
-            step_adjoint(self.prob, self.seg_u[j], self.seg_dt[j:j + 1], self.seg_dec[j], self.ub,
-                         ubar_in=self.ub, ws=self.aws)
-            self.seg_cls[j].copy_(self.aws[:64].view(torch.int32))
+            step_adjoint_lists(self.prob, self.seg_u[j], self.seg_dt[j:j + 1], self.seg_dec[j], self.ub,
+                               self.seg_ws[j], ubar_in=self.ub, ws=self.aws)
+            self.seg_cls[j].copy_(self.seg_ws[j][:64].view(torch.int32))
 
     def _run(self, cache, m, body):
         """Run body(m) once; with graphs, the first run of a length is eager

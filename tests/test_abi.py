@@ -211,6 +211,22 @@ def test_adjoint_argument_errors_before_launch(lib):
     # 2D needs the y decisions too
     p2 = _prob(dim=2, nvar=4, nx=16, ny=16, dy=0.1)
     assert adj(ctypes.byref(p2.c()), a, 0.1, None, ctypes.byref(dec), b, c, ws, 16, None) == -1
+    # the list-reusing form: the same checks, then the step workspace's presence and size
+    adl = lib.acat_step_adjoint_lists
+    need = ctypes.c_size_t(0)
+    assert lib.acat_adjoint_workspace_size(ctypes.byref(pc), ctypes.byref(need)) == 0
+    big = ctypes.create_string_buffer(need.value)
+    swn = ctypes.c_size_t(0)
+    assert lib.acat_workspace_size(ctypes.byref(pc), ctypes.byref(swn)) == 0
+    assert adl(ctypes.byref(pc), a, 0.1, None, ctypes.byref(dec), b, c, None, swn.value, big, need.value,
+               None) == -1
+    assert adl(ctypes.byref(pc), a, 0.1, None, ctypes.byref(dec), b, a, ws, swn.value, big, need.value,
+               None) == -3
+    assert adl(ctypes.byref(pc), a, 0.1, None, ctypes.byref(dec), b, c, ws, swn.value, ws, 16, None) == -6
+    assert adl(ctypes.byref(pc), a, 0.1, None, ctypes.byref(dec), b, c, ws, swn.value - 1, big, need.value,
+               None) == -6
+    assert adl(ctypes.byref(_prob(flags=2).c()), a, 0.1, None, ctypes.byref(dec), b, c, ws, swn.value, big,
+               need.value, None) == -4
 
 
 def test_step_cfl_argument_errors_before_launch(lib):

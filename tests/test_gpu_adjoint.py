@@ -176,6 +176,41 @@ def test_adjoint_in_place_device_dt_and_zero_dt(acat):
     assert acat.device_status() == 0
 
 
+@pytest.mark.parametrize("case", ["1d P=3", "1d P=6", "2d P=2", "2d P=3", "2d P=4"])
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+@pytest.mark.parametrize("fwd", ["cfl", "replay"])
+def test_adjoint_reusing_step_lists_equals_adjoint(acat, case, bc, fwd):
+    """acat_step_adjoint_lists after the forward step (recording, or replaying
+    the recorded decisions) gives acat_step_adjoint's result bit for bit, and
+    leaves the step workspace unchanged."""
+    dim, P = int(case[0]), int(case[-1])
+    if dim == 1:
+        w = workloads.euler_1d(n=200, P=P)
+        po, pg = from_workload(w, bc=bc)
+        u = w["u"]
+    else:
+        n = 40
+        u = smooth_2d(n)
+        po, pg = both_problems(2, 4, n, "euler", P, bc, 1.0 / n, ny=n, dy=1.0 / n)
+    ug = torch.from_numpy(np.ascontiguousarray(u)).cuda()
+    dec = acat.Decisions(pg)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    sws = acat.workspace(pg)
+    out = torch.empty_like(ug)
+    acat.step_cfl(pg, ug, 0.4, dt, out=out, ws=sws, dec=dec)
+    if fwd == "replay":
+        sws = acat.workspace(pg)
+        acat.step_replay(pg, ug, dt, dec, out=out, ws=sws)
+    ub = torch.from_numpy(np.random.default_rng(P).standard_normal(u.shape)).cuda()
+    ref = acat.step_adjoint(pg, ug, dt, dec, ub)
+    before = sws.clone()
+    got = acat.step_adjoint_lists(pg, ug, dt, dec, ub, sws)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    assert torch.equal(sws, before)
+    assert acat.device_status() == 0
+
+
 def test_adjoint_1d_bad_recorded_order_is_flagged(acat):
     w = workloads.euler_1d(n=32, P=3)
     po, pg = from_workload(w)
