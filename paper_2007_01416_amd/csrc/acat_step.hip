@@ -8,18 +8,21 @@
 //                  p_s = 1 the superbee weight psi^1 (Sec. 3.1) and the
 //                  Rusanov speed; writes the order (1D) or the corner's
 //                  order class (2D) as one byte, and a per-block histogram
-//   k_sum_hist     per-class item counts (instrumentation)
-//   k_flux*<class> persistent kernels, one per order class.  A block walks
-//                  tiles of the class map, compacts the matching items into
-//                  an LDS ring (wave ballots, no global atomics; items keep
-//                  their spatial order) and processes them in rounds with
-//                  one LANE PER STENCIL NODE: a 1D interface of order p
-//                  occupies 2p lanes, a 2D corner of orders (q1, q2)
-//                  2q1 x 2q2 lanes.  Each lane keeps its node's state and
-//                  Taylor history in registers and evaluates the flux at its
-//                  own predicted states; the spatial derivatives of the
-//                  time-derivative fluxes go through LDS (Sec. 2.2
-//                  recursion, Sec. 4 corner recursion)
+//   k_scan_hist    per-class exclusive prefix of the tile histograms (and,
+//                  in CFL mode, the time step from the classification's
+//                  per-block maxima)
+//   k_scatter      the item lists: every class's items in tile order
+//                  (wave ballots, no global atomics)
+//   k_flux*<class> persistent kernels, one per order class (2D: one per
+//                  square class and one per mirror pair (q1,q2) + (q2,q1)).
+//                  A block takes a contiguous slice of its class's list and
+//                  processes it in rounds with one LANE PER STENCIL NODE: a
+//                  1D interface of order p occupies 2p lanes, a 2D corner of
+//                  orders (q1, q2) 2q1 x 2q2 lanes.  Each lane keeps its
+//                  node's state and Taylor predictions in registers and
+//                  evaluates the flux at its own predicted states; the
+//                  spatial derivatives of the time-derivative fluxes go
+//                  through LDS (Sec. 2.2 recursion, Sec. 4 corner recursion)
 //   k_update*      conservative flux-difference update + status bits
 #include <hip/hip_runtime.h>
 
@@ -862,22 +865,17 @@ hipError_t step1d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s)
   return hipSuccess;
 }
 
-template <int FLUX, int NV, int P, int Q1, int Q2>
+// A square class (Q, Q); the other classes run as mirror pairs (launch_pair2d).
+template <int FLUX, int NV, int P, int Q>
 hipError_t launch_class2d(const KProb& pb, const KStep& st, int cap, hipStream_t s) {
-  if constexpr (Q1 <= P && Q2 <= P) {
-    static const char* names[5][5] = {{"", "", "", "", ""},
-                                      {"", "flux2d_q11", "flux2d_q12", "flux2d_q13", "flux2d_q14"},
-                                      {"", "flux2d_q21", "flux2d_q22", "flux2d_q23", "flux2d_q24"},
-                                      {"", "flux2d_q31", "flux2d_q32", "flux2d_q33", "flux2d_q34"},
-                                      {"", "flux2d_q41", "flux2d_q42", "flux2d_q43", "flux2d_q44"}};
-    // under the square-stencil variant only the square classes have items
-    auto kern = k_flux2d<FLUX, NV, Q1, Q2>;
-    if constexpr (Q1 == Q2) {
-      if (pb.flags & FLAG_SQUARE_2D) kern = k_flux2d<FLUX, NV, Q1, Q2, true>;
-    }
+  if constexpr (Q <= P) {
+    static const char* names[5] = {"", "flux2d_q11", "flux2d_q22", "flux2d_q33", "flux2d_q44"};
+    // under the square-stencil variant only the square classes have items,
+    // tagged with the flux they store
+    auto kern = (pb.flags & FLAG_SQUARE_2D) ? k_flux2d<FLUX, NV, Q, Q, true> : k_flux2d<FLUX, NV, Q, Q>;
     const int grid = persistent_grid(kern, pb.n1 * pb.n2, cap);
     {
-      ProfScope ps(names[Q1][Q2], s);
+      ProfScope ps(names[Q], s);
       kern<<<grid, BLOCK, 0, s>>>(pb, st);
     }
     ACAT_CHECK_LAUNCH();
@@ -934,16 +932,16 @@ template <int FLUX, int NV, int P>
 hipError_t step2d_impl(const KProb& pb, const KStep& st, int cap, hipStream_t s) {
   hipError_t e;
   if ((e = lists2d_impl<FLUX, NV, P>(pb, st, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 1, 1>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 1>(pb, st, cap, s)) != hipSuccess) return e;
   if ((e = launch_pair2d<FLUX, NV, P, 1, 2>(pb, st, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 2, 2>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 2>(pb, st, cap, s)) != hipSuccess) return e;
   if ((e = launch_pair2d<FLUX, NV, P, 1, 3>(pb, st, cap, s)) != hipSuccess) return e;
   if ((e = launch_pair2d<FLUX, NV, P, 2, 3>(pb, st, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 3, 3>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 3>(pb, st, cap, s)) != hipSuccess) return e;
   if ((e = launch_pair2d<FLUX, NV, P, 1, 4>(pb, st, cap, s)) != hipSuccess) return e;
   if ((e = launch_pair2d<FLUX, NV, P, 2, 4>(pb, st, cap, s)) != hipSuccess) return e;
   if ((e = launch_pair2d<FLUX, NV, P, 3, 4>(pb, st, cap, s)) != hipSuccess) return e;
-  if ((e = launch_class2d<FLUX, NV, P, 4, 4>(pb, st, cap, s)) != hipSuccess) return e;
+  if ((e = launch_class2d<FLUX, NV, P, 4>(pb, st, cap, s)) != hipSuccess) return e;
   {
     ProfScope ps("update2d", s);
     k_update2d<FLUX, NV><<<(unsigned)((pb.nx * pb.ny + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(pb, st);
