@@ -352,6 +352,61 @@ def bench_adjoint(acat, workloads, F, fd_dirs=32, fd_h=(1e-4, 1e-5, 1e-6, 1e-7, 
                          "seconds": t_fd}}
 
 
+def bench_small(acat, workloads, cpu: bool = True):
+    """The two 1D configurations to their final times: the Burgers shock
+    (200 cells, P = 2, t = 0.6) and the Euler Riemann problem (4096 cells,
+    P = 4, t = 0.2).  GPU: steps to t_final counted on one eager run, then
+    the per-step time of a captured 64-step graph (steps past t_final have
+    dt = 0 and are not counted) and time to solution = steps x that.
+    CPU (with cpu): the oracle's full run of the Burgers case on one thread
+    and on every core; the Euler case on every core in full and on one
+    thread over its first 50 steps, extrapolated to the full step count."""
+    import numpy as np
+    import torch
+    out = {}
+    cores = len(os.sched_getaffinity(0))
+    for name, w, kw in (("burgers1d_N200_P2_t0.6", workloads.burgers_1d(), dict(nvar=1, flux="burgers")),
+                        ("euler1d_N4096_P4_t0.2", workloads.euler_1d(), dict(nvar=3, flux="euler"))):
+        n = w["u"].shape[-1]
+        bc = w["bc"]
+        prob = acat.Problem(dim=1, nx=n, P=w["P"], bc=bc, dx=w["dx"], gamma=w.get("gamma", 1.4), **kw)
+        s = acat.Solver(prob, w["u"], w["cfl"], t_final=w["t_final"])
+        nsteps = 0
+        while s.time() < w["t_final"]:
+            s.step()
+            nsteps += 1
+        g = acat.Solver(prob, w["u"], w["cfl"], t_final=w["t_final"])
+        g.capture(64)
+        g.replay(1)
+        torch.cuda.synchronize()
+        reps = 10
+        t0 = time.perf_counter()
+        g.replay(reps)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / (reps * 64)
+        o = {"steps_to_t_final": nsteps, "graph_ms_per_step": ms, "time_to_solution_ms": nsteps * ms,
+             "value": n * nsteps / (nsteps * ms * 1e-3), "unit": "cell-updates/s"}
+        if cpu:
+            import oracle
+            po = oracle.Problem(dim=1, nvar=kw["nvar"], nx=n, flux=oracle.FLUX_BURGERS if kw["flux"] == "burgers"
+                                else oracle.FLUX_EULER, P=w["P"], bc=oracle.BC_PERIODIC if bc == "periodic"
+                                else oracle.BC_TRANSMISSIVE, dx=w["dx"], gamma=w.get("gamma", 1.4))
+            t0 = time.perf_counter()
+            _, _, on = oracle.run(po, w["u"], w["cfl"], t_final=w["t_final"], nthreads=cores)
+            t_all = time.perf_counter() - t0
+            o["oracle_all_cores"] = {"cores": cores, "steps": on, "seconds": t_all, "value": n * on / t_all}
+            one_steps = on if n <= 1024 else min(on, 50)
+            t0 = time.perf_counter()
+            oracle.run(po, w["u"], w["cfl"], nsteps=one_steps, nthreads=1)
+            t1 = time.perf_counter() - t0
+            o["oracle_one_thread"] = {"cores": 1, "steps_timed": one_steps, "seconds": t1,
+                                      "value": n * one_steps / t1,
+                                      "time_to_solution_s": t1 * on / one_steps,
+                                      "extrapolated": one_steps < on}
+        out[name] = o
+    return out
+
+
 def bench_paper(acat, workloads):
     """Cost of ACAT2 / ACAT4 / ACAT6 (P = 1, 2, 3) on the paper's two timed
     experiments, next to the paper's CPU-time ratios (Matlab, Sec. 5.3 and
@@ -506,7 +561,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and adjoint workloads")
     ap.add_argument("--fd-dirs", type=int, default=32, help="finite-difference directions of the adjoint check")
-    ap.add_argument("--only", choices=["batched", "adjoint", "paper", "high"],
+    ap.add_argument("--only", choices=["batched", "adjoint", "paper", "high", "small"],
                     help="run only that workload and print its object (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference dispatch for HBM byte counters)")
@@ -524,6 +579,9 @@ def main():
     acat.load()
     if args.only == "batched":
         print(json.dumps(bench_batched(acat, workloads)), flush=True)
+        return
+    if args.only == "small":
+        print(json.dumps(bench_small(acat, workloads, cpu=not args.no_cpu_baseline)), flush=True)
         return
     if args.only == "paper":
         print(json.dumps(bench_paper(acat, workloads)), flush=True)
@@ -629,6 +687,8 @@ def main():
     if not args.no_extra:
         print("[bench] batched 1D workload", file=sys.stderr, flush=True)
         out["batched"] = bench_batched(acat, workloads)
+        print("[bench] 1D configurations to their final times", file=sys.stderr, flush=True)
+        out["small_configs"] = bench_small(acat, workloads, cpu=not args.no_cpu_baseline)
         print("[bench] paper experiments", file=sys.stderr, flush=True)
         out["paper_cost_ratios"] = bench_paper(acat, workloads)
         print("[bench] higher orders", file=sys.stderr, flush=True)
