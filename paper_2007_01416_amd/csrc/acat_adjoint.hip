@@ -668,7 +668,7 @@ hipError_t launch_adj1d(const KProb& pb, const KStep& st, const double* ubo, dou
     static const char* names[7] = {"", "adjoint1d_p1", "adjoint1d_p2", "adjoint1d_p3", "adjoint1d_p4",
                                    "adjoint1d_p5", "adjoint1d_p6"};
     auto kern = k_adj1d<FLUX, NV, p>;
-    const int grid = persistent_grid(kern, pb.nIx, 0);
+    const int grid = group_grid<2 * p>(kern, pb.nIx, 0);
     {
       ProfScope ps(names[p], s);
       kern<<<grid, BLOCK, 0, s>>>(pb, st, ubo, C, 2 * P);
@@ -711,11 +711,11 @@ hipError_t launch_adj2d(const KProb& pb, const KStep& st, const double* ubo, dou
       auto k1 = k_adj2d<FLUX, NV, Q1, Q2, 1>;
       auto k2 = k_adj2d<FLUX, NV, Q1, Q2, 2>;
       ProfScope ps(names[Q1][Q2], s);
-      k1<<<persistent_grid(k1, pb.n1 * pb.n2, 0), BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P);
-      k2<<<persistent_grid(k2, pb.n1 * pb.n2, 0), BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P);
+      k1<<<group_grid<(2 * Q1) * (2 * Q2)>(k1, pb.n1 * pb.n2, 0), BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P);
+      k2<<<group_grid<(2 * Q1) * (2 * Q2)>(k2, pb.n1 * pb.n2, 0), BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P);
     } else {
       auto kern = k_adj2d<FLUX, NV, Q1, Q2>;
-      const int grid = persistent_grid(kern, pb.n1 * pb.n2, 0);
+      const int grid = group_grid<(2 * Q1) * (2 * Q2)>(kern, pb.n1 * pb.n2, 0);
       ProfScope ps(names[Q1][Q2], s);
       kern<<<grid, BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P);
     }
@@ -737,7 +737,7 @@ hipError_t launch_adjpair2d(const KProb& pb, const KStep& st, const double* ubo,
                                       {"", "", "", ""}};
     auto kern = k_adj2d_pair<FLUX, NV, QA, QB>;
     // two runs of XCD groups: at least one per class
-    const int grid = std::max(persistent_grid(kern, pb.n1 * pb.n2, 0), 2 * NXCD);
+    const int grid = std::max(group_grid<(2 * QA) * (2 * QB)>(kern, pb.n1 * pb.n2, 0), 2 * NXCD);
     ProfScope ps(names[QA][QB], s);
     kern<<<grid, BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P);
     ACAT_CHECK_LAUNCH();

@@ -816,7 +816,7 @@ hipError_t launch_class1d(const KProb& pb, const KStep& st, int cap, hipStream_t
     static const char* names[7] = {"", "flux1d_p1", "flux1d_p2", "flux1d_p3", "flux1d_p4", "flux1d_p5",
                                    "flux1d_p6"};
     auto kern = k_flux1d<FLUX, NV, p>;
-    const int grid = persistent_grid(kern, pb.nIx, cap);
+    const int grid = group_grid<2 * p>(kern, pb.nIx, cap);
     {
       ProfScope ps(names[p], s);
       kern<<<grid, BLOCK, 0, s>>>(pb, st);
@@ -873,7 +873,7 @@ hipError_t launch_class2d(const KProb& pb, const KStep& st, int cap, hipStream_t
     // under the square-stencil variant only the square classes have items,
     // tagged with the flux they store
     auto kern = (pb.flags & FLAG_SQUARE_2D) ? k_flux2d<FLUX, NV, Q, Q, true> : k_flux2d<FLUX, NV, Q, Q>;
-    const int grid = persistent_grid(kern, pb.n1 * pb.n2, cap);
+    const int grid = group_grid<(2 * Q) * (2 * Q)>(kern, pb.n1 * pb.n2, cap);
     {
       ProfScope ps(names[Q], s);
       kern<<<grid, BLOCK, 0, s>>>(pb, st);
@@ -895,7 +895,7 @@ hipError_t launch_pair2d(const KProb& pb, const KStep& st, int cap, hipStream_t 
                                       {"", "", "", "", ""}};
     auto kern = k_flux2d_pair<FLUX, NV, QA, QB>;
     // two runs of XCD groups: at least one per class
-    const int grid = std::max(persistent_grid(kern, pb.n1 * pb.n2, cap), 2 * NXCD);
+    const int grid = std::max(group_grid<(2 * QA) * (2 * QB)>(kern, pb.n1 * pb.n2, cap), 2 * NXCD);
     {
       ProfScope ps(names[QA][QB], s);
       kern<<<grid, BLOCK, 0, s>>>(pb, st);

@@ -434,6 +434,16 @@ struct Groups {
   }
 };
 
+// Persistent grid of a lane-per-node kernel whose blocks take PER_BLOCK
+// items (groups of L lanes) per round: at most one block per PER_BLOCK of
+// the nitems items the kernel's lists can hold (a round's worth each), and
+// otherwise as persistent_grid.
+template <int L, class K>
+int group_grid(K kernel, int64_t nitems, int cap) {
+  constexpr int PB = Groups<L>::PER_BLOCK;
+  return persistent_grid(kernel, (nitems + PB - 1) / PB * BLOCK, cap);
+}
+
 // LDS exchange of the time-derivative fluxes of a 2D corner: per node, the
 // NV components of Fh and of Gh stored as double2 pairs in component-major
 // planes (consecutive lanes write consecutive 16-byte words).
