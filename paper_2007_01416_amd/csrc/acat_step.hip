@@ -523,13 +523,15 @@ constexpr int corner_stride() {
 }
 
 // Fluxes of the corners of order class (Q1, Q2) (Sec. 4; rectangle J_Q1 x J_Q2)
-// in the block's share `sl` of the class list.  SQUARE: list entries carry
+// in the block's share `sl` of the class list; every class but (1,1), which
+// runs one lane per corner (k_flux2d_q11).  SQUARE: list entries carry
 // the square-stencil variant's tags (square classes only).  xsm: the two
 // exchange buffers (2 Xch<NV>::NP corner_stride<L>() double2), g1s: the
 // derivative weights ((2 Q1)^2 + (2 Q2)^2 doubles), both in LDS.
 template <int FLUX, int NV, int Q1, int Q2, bool SQUARE>
 __device__ __forceinline__ void flux2d_body(const KProb& pb, const KStep& st, const Slice& sl, double2* xsm,
                                             double* g1s) {
+  static_assert(Q1 > 1 || Q2 > 1, "class (1,1) runs in k_flux2d_q11");
   constexpr int N1 = 2 * Q1, N2 = 2 * Q2, L = N1 * N2;
   using Grp = Groups<L>;
   constexpr int CPB = Grp::PER_BLOCK;
@@ -613,14 +615,6 @@ __device__ __forceinline__ void flux2d_body(const KProb& pb, const KStep& st, co
         acc[tk] = t;
       }
       buf ^= 1;   // the assembly may still read this buffer
-      if constexpr (Q1 == 1 && Q2 == 1) {
-        // the FL-CAT2 blends of a (1,1) corner read the corner's own nodes:
-        // states and point fluxes pass through both buffers, (u, f) and (g, g)
-        Grp::sync();   // the assembly has read its buffer
-        Xch<NV>::put(xs[0], STRIDE, slot, u, f0);
-        Xch<NV>::put(xs[1], STRIDE, slot, g0, g0);
-        Grp::sync();
-      }
       // finish and store the assembled components
 #pragma unroll
       for (int tk = 0; tk < 2; ++tk) {
@@ -641,29 +635,13 @@ __device__ __forceinline__ void flux2d_body(const KProb& pb, const KStep& st, co
           const double psi = isG ? st.psiy[ei] : st.psix[ei];
           const double al = isG ? st.aly[ei] : st.alx[ei];
           double uL[NV], uR[NV], fL[NV], gL[NV], fR[NV], gR[NV];
-          if constexpr (Q1 == 1 && Q2 == 1) {
-            // nodes (0,0) and (1,0) (x) or (0,1) (y) of this corner
-            const double* p0 = reinterpret_cast<const double*>(xs[0]);
-            const double* p1 = reinterpret_cast<const double*>(xs[1]);
-            const int sl0 = g * GS, slr = g * GS + (isG ? N1 : 1);
 #pragma unroll
-            for (int cc = 0; cc < NV; ++cc) {
-              uL[cc] = Xch<NV>::get(p0, STRIDE, sl0, cc, false);
-              uR[cc] = Xch<NV>::get(p0, STRIDE, slr, cc, false);
-              fL[cc] = Xch<NV>::get(p0, STRIDE, sl0, cc, true);
-              fR[cc] = Xch<NV>::get(p0, STRIDE, slr, cc, true);
-              gL[cc] = Xch<NV>::get(p1, STRIDE, sl0, cc, false);
-              gR[cc] = Xch<NV>::get(p1, STRIDE, slr, cc, false);
-            }
-          } else {
-#pragma unroll
-            for (int cc = 0; cc < NV; ++cc) {
-              uL[cc] = st.u[(cc * ny + y0) * nx + x0];
-              uR[cc] = st.u[(cc * ny + yr) * nx + xr];
-            }
-            flux2d<FLUX, NV>(pb.ph, uL, fL, gL);
-            flux2d<FLUX, NV>(pb.ph, uR, fR, gR);
+          for (int cc = 0; cc < NV; ++cc) {
+            uL[cc] = st.u[(cc * ny + y0) * nx + x0];
+            uR[cc] = st.u[(cc * ny + yr) * nx + xr];
           }
+          flux2d<FLUX, NV>(pb.ph, uL, fL, gL);
+          flux2d<FLUX, NV>(pb.ph, uR, fR, gR);
           double ul = 0.0, ur = 0.0, hl = 0.0, hr = 0.0;
 #pragma unroll
           for (int cc = 0; cc < NV; ++cc)
@@ -680,7 +658,6 @@ __device__ __forceinline__ void flux2d_body(const KProb& pb, const KStep& st, co
         if (isG) st.Gy[((int64_t)c * pb.nIy + (i2 - ioff)) * nx + i1] = v;
         else st.Fx[((int64_t)c * ny + i2) * pb.nIx + (i1 - ioff)] = v;
       }
-      if constexpr (Q1 == 1 && Q2 == 1) Grp::sync();   // the blends have read both buffers
     }
   }
 }
@@ -692,6 +669,118 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
   __shared__ double2 xsm[2 * Xch<NV>::NP * corner_stride<L>()];
   __shared__ double g1s[(2 * Q1) * (2 * Q1) + (2 * Q2) * (2 * Q2)];
   flux2d_body<FLUX, NV, Q1, Q2, SQUARE>(pb, st, Slice(st.counts, st.list, (Q1 - 1) * pb.P + (Q2 - 1)), xsm, g1s);
+}
+
+// Order class (1,1) with ONE LANE PER CORNER.  The corner's four nodes
+// (j1, j2) in {0,1}^2 (cells (i1 + j1, i2 + j2)) live in one lane, which
+// computes, with the same operations in the same order as the node-per-lane
+// kernel, just the quantities the corner's fluxes read (Sec. 4 with
+// q1 = q2 = 1: one recursion level): the point fluxes at the four nodes, U^1
+// at the three nodes of row j2 = 0 and column j1 = 0, the flux at their
+// Taylor predictions, the series of F on the row and of G on the column,
+// the eta-weighted sums and the FL-CAT2 blends.  No LDS exchange and no
+// barrier; a wavefront holds 64 independent corners.
+template <int FLUX, int NV, bool SQUARE = false>
+__global__ __launch_bounds__(BLOCK) void k_flux2d_q11(KProb pb, KStep st) {
+  const double dt = step_dt(st);
+  const double lamx = dt / pb.dx, lamy = dt / pb.dy;
+  // derivative weights times -lamx (x) and -lamy (y): gx[a][l], gy[a][l]
+  double gx[2][2], gy[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+      gx[a][l] = -lamx * TB.G1[1][a][l];
+      gy[a][l] = -lamy * TB.G1[1][a][l];
+    }
+  const double tay = TB.TAYLOR[PMAX][1];                      // r = 1, first term
+  const double gt0 = TB.GT[1][1][0], gt1 = TB.GT[1][1][1];    // time derivative weights at r = 0, 1
+  const int64_t nx = pb.nx, ny = pb.ny, plane = pb.nx * pb.ny;
+  const int nx32 = (int)pb.nx, ny32 = (int)pb.ny, ioff = (int)pb.ioff;
+  const uint32_t n1u = (uint32_t)pb.n1;
+  const Slice sl(st.counts, st.list, 0);
+  for (int64_t it = sl.lo + threadIdx.x; it < sl.hi; it += BLOCK) {
+    const int32_t raw = sl.items[it];
+    const int32_t e = SQUARE ? (raw & ((1 << LIST_TAG_SHIFT) - 1)) : raw;
+    const int tag = SQUARE ? (raw >> LIST_TAG_SHIFT) : 0;
+    const uint32_t eq = (uint32_t)e / n1u;
+    const int i2 = (int)eq + ioff, i1 = (int)((uint32_t)e - eq * n1u) + ioff;
+    int xs[2], ys[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      xs[a] = bc_index32(i1 + a, nx32, pb.bc);
+      ys[a] = bc_index32(i2 + a, ny32, pb.bc);
+    }
+    // node states and point fluxes, [j2][j1]
+    double u[2][2][NV], f0[2][2][NV], g0[2][2][NV];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) u[b][a][c] = st.u[c * plane + (int64_t)ys[b] * nx + xs[a]];
+        flux2d<FLUX, NV>(pb.ph, u[b][a], f0[b][a], g0[b][a]);
+      }
+    // series of F on the row j2 = 0 (nodes (0,0), (1,0)) and of G on the
+    // column j1 = 0 (nodes (0,0), (0,1)): S = Fh^0 / 1! + Fh^1 / 2!
+    double SF[2][NV], SG[2][NV];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const int a = n == 1 ? 1 : 0, b = n == 2 ? 1 : 0;   // nodes (0,0), (1,0), (0,1)
+      double w[NV];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        // U^1 = -lamx d_x Fh^0 - lamy d_y Gh^0: one chain, row then column
+        double s = 0.0;
+        s = fma(gx[a][0], f0[b][0][c], s);
+        s = fma(gx[a][1], f0[b][1][c], s);
+        s = fma(gy[b][0], g0[0][a][c], s);
+        s = fma(gy[b][1], g0[1][a][c], s);
+        w[c] = fma(tay, s, u[b][a][c]);
+      }
+      double pf[NV], pg[NV];
+      flux2d<FLUX, NV>(pb.ph, w, pf, pg);
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        if (b == 0) {   // on the row: F's series
+          const double nf = fma(gt1, pf[c], fma(gt0, f0[b][a][c], 0.0));
+          SF[a][c] = fma(TB.INVFACT[2], nf, fma(TB.INVFACT[1], f0[b][a][c], 0.0));
+        }
+        if (a == 0) {   // on the column: G's series
+          const double ng = fma(gt1, pg[c], fma(gt0, g0[b][a][c], 0.0));
+          SG[b][c] = fma(TB.INVFACT[2], ng, fma(TB.INVFACT[1], g0[b][a][c], 0.0));
+        }
+      }
+    }
+    const bool needF = i2 >= 0 && tag != 2, needG = i1 >= 0 && tag != 1;
+    if (needF) {
+      // F: eta-weighted row sum, FL-CAT2 blend with the nodes (0,0), (1,0)
+      const int64_t ei = (int64_t)i2 * pb.nIx + (i1 - ioff);
+      const double psi = st.psix[ei], al = st.alx[ei];
+      const double alf = pb.dx / ((double)pb.dim * dt);
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        double v = fma(TB.ETA[1][1], SF[1][c], fma(TB.ETA[1][0], SF[0][c], 0.0));
+        const double lo = lo_flux<FLUX, 2, NV>(pb.ph, pb.flags, 0, u[0][0], u[0][1], f0[0][0][c], f0[0][1][c],
+                                               u[0][0][c], u[0][1][c], al, alf);
+        v = psi * v + (1.0 - psi) * lo;
+        st.Fx[((int64_t)c * ny + i2) * pb.nIx + (i1 - ioff)] = v;
+      }
+    }
+    if (needG) {
+      const int64_t ei = (int64_t)(i2 - ioff) * nx + i1;
+      const double psi = st.psiy[ei], al = st.aly[ei];
+      const double alf = pb.dy / ((double)pb.dim * dt);
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        double v = fma(TB.ETA[1][1], SG[1][c], fma(TB.ETA[1][0], SG[0][c], 0.0));
+        const double lo = lo_flux<FLUX, 2, NV>(pb.ph, pb.flags, 1, u[0][0], u[1][0], g0[0][0][c], g0[1][0][c],
+                                               u[0][0][c], u[1][0][c], al, alf);
+        v = psi * v + (1.0 - psi) * lo;
+        st.Gy[((int64_t)c * pb.nIy + (i2 - ioff)) * nx + i1] = v;
+      }
+    }
+  }
 }
 
 // The mirror classes (QA, QB) and (QB, QA), QA < QB, in one launch: the grid
@@ -872,8 +961,17 @@ hipError_t launch_class2d(const KProb& pb, const KStep& st, int cap, hipStream_t
     static const char* names[5] = {"", "flux2d_q11", "flux2d_q22", "flux2d_q33", "flux2d_q44"};
     // under the square-stencil variant only the square classes have items,
     // tagged with the flux they store
-    auto kern = (pb.flags & FLAG_SQUARE_2D) ? k_flux2d<FLUX, NV, Q, Q, true> : k_flux2d<FLUX, NV, Q, Q>;
-    const int grid = group_grid<(2 * Q) * (2 * Q)>(kern, pb.n1 * pb.n2, cap);
+    // (1,1): one lane per corner (k_flux2d_q11); the others one lane per node
+    const bool sq = (pb.flags & FLAG_SQUARE_2D) != 0;
+    void (*kern)(KProb, KStep);
+    int grid;
+    if constexpr (Q == 1) {
+      kern = sq ? k_flux2d_q11<FLUX, NV, true> : k_flux2d_q11<FLUX, NV>;
+      grid = persistent_grid(kern, pb.n1 * pb.n2, cap);
+    } else {
+      kern = sq ? k_flux2d<FLUX, NV, Q, Q, true> : k_flux2d<FLUX, NV, Q, Q>;
+      grid = group_grid<(2 * Q) * (2 * Q)>(kern, pb.n1 * pb.n2, cap);
+    }
     {
       ProfScope ps(names[Q], s);
       kern<<<grid, BLOCK, 0, s>>>(pb, st);
