@@ -574,6 +574,182 @@ __global__ __launch_bounds__(BLOCK) void k_adj2d(KProb pb, KStep st, const doubl
                                        LMAX, xsm, g1s);
 }
 
+// Order class (1,1) with ONE LANE PER CORNER: the adjoint of the one-lane
+// forward kernel.  The lane holds the corner's four nodes (j1, j2) in
+// {0,1}^2 and runs the same reverse sweep as the node-per-lane kernel
+// (recursion level 2 backwards, the transposed centred differences, the
+// blends' first-order parts, the Jacobian-transpose products), skipping
+// the terms that are zero for this class: the predicted-state adjoint at
+// node (1,1), which no flux reads.  Writes the four nodes' contributions.
+template <int FLUX, int NV>
+__global__ __launch_bounds__(BLOCK) void k_adj2d_q11(KProb pb, KStep st, const double* __restrict__ ubo,
+                                                     double* __restrict__ C, int LMAX) {
+  const double dt = step_dt(st);
+  const double lamx = dt / pb.dx, lamy = dt / pb.dy;
+  double gx[2][2], gy[2][2];   // -lamx G1[1][a][l], -lamy G1[1][a][l]
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+      gx[a][l] = -lamx * TB.G1[1][a][l];
+      gy[a][l] = -lamy * TB.G1[1][a][l];
+    }
+  const double tay = TB.TAYLOR[PMAX][1];
+  const double gt0 = TB.GT[1][1][0], gt1 = TB.GT[1][1][1];
+  const int64_t nx = pb.nx, plane = pb.nx * pb.ny;
+  const int nx32 = (int)pb.nx, ny32 = (int)pb.ny, ioff = (int)pb.ioff;
+  const uint32_t n1u = (uint32_t)pb.n1;
+  const int64_t nitems = pb.n1 * pb.n2;
+  const int64_t cstride = nitems * LMAX;
+  const bool per = pb.bc == PERIODIC;
+  const Slice sl(st.counts, st.list, 0);
+  for (int64_t it = sl.lo + threadIdx.x; it < sl.hi; it += BLOCK) {
+    const int32_t e = sl.items[it];
+    const uint32_t eq = (uint32_t)e / n1u;
+    const int i2 = (int)eq + ioff, i1 = (int)((uint32_t)e - eq * n1u) + ioff;
+    int xs[2], ys[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      xs[a] = bc_index32(i1 + a, nx32, pb.bc);
+      ys[a] = bc_index32(i2 + a, ny32, pb.bc);
+    }
+    // Fbar = lamx (ubar_{i+e1} - ubar_i), Gbar = lamy (ubar_{i+e2} - ubar_i);
+    // ghost-row corners carry no x-flux, ghost-column corners no y-flux
+    const bool hasF = i2 >= 0, hasG = i1 >= 0;
+    double Fb[NV], Gb[NV];
+    {
+      const bool in1 = per || i1 >= 0, inr1 = per || i1 + 1 < nx32;
+      const bool in2 = per || i2 >= 0, inr2 = per || i2 + 1 < ny32;
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        const double u0 = ubo[c * plane + (int64_t)ys[0] * nx + xs[0]];
+        const double ux = ubo[c * plane + (int64_t)ys[0] * nx + xs[1]];
+        const double uy = ubo[c * plane + (int64_t)ys[1] * nx + xs[0]];
+        Fb[c] = hasF ? lamx * ((inr1 ? ux : 0.0) - (in1 ? u0 : 0.0)) : 0.0;
+        Gb[c] = hasG ? lamy * ((inr2 ? uy : 0.0) - (in2 ? u0 : 0.0)) : 0.0;
+      }
+    }
+    double psix = 1.0, alx = 0.0, psiy = 1.0, aly = 0.0;
+    if (hasF) {
+      const int64_t ex = (int64_t)i2 * pb.nIx + (i1 - ioff);
+      psix = st.psix[ex];
+      alx = st.alx[ex];
+    }
+    if (hasG) {
+      const int64_t ey = (int64_t)(i2 - ioff) * nx + i1;
+      psiy = st.psiy[ey];
+      aly = st.aly[ey];
+    }
+    if (pb.flags & FLAG_FLO_LF) {
+      alx = pb.dx / ((double)pb.dim * dt);
+      aly = pb.dy / ((double)pb.dim * dt);
+    }
+    // node states and point fluxes, [j2][j1]
+    double u[2][2][NV], f0[2][2][NV], g0[2][2][NV];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) u[b][a][c] = st.u[c * plane + (int64_t)ys[b] * nx + xs[a]];
+        flux2d<FLUX, NV>(pb.ph, u[b][a], f0[b][a], g0[b][a]);
+      }
+    // adjoints: ub of the node states, f0b/g0b of the point fluxes, Ub1 of U^1
+    double ub[2][2][NV], f0b[2][2][NV], g0b[2][2][NV], Ub1[2][2][NV];
+    // series adjoints: sfb on the row j2 = 0, sgb on the column j1 = 0
+    double sfb[2][NV], sgb[2][NV];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        sfb[a][c] = TB.ETA[1][a] * psix * Fb[c];
+        sgb[a][c] = TB.ETA[1][a] * psiy * Gb[c];
+      }
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+          // level 2 backwards, time node r = 0: the point fluxes' share
+          const double fhb = (b == 0) ? TB.INVFACT[2] * sfb[a][c] : 0.0;
+          const double ghb = (a == 0) ? TB.INVFACT[2] * sgb[b][c] : 0.0;
+          f0b[b][a][c] = gt0 * fhb;
+          g0b[b][a][c] = gt0 * ghb;
+          ub[b][a][c] = 0.0;
+          Ub1[b][a][c] = 0.0;
+        }
+    // time node r = 1 at the row and column nodes: the prediction
+    // w = u + tay U^1, the flux Jacobians' transpose at w
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const int a = n == 1 ? 1 : 0, b = n == 2 ? 1 : 0;
+      double w[NV], pfb[NV], pgb[NV], wb[NV];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        double s = 0.0;
+        s = fma(gx[a][0], f0[b][0][c], s);
+        s = fma(gx[a][1], f0[b][1][c], s);
+        s = fma(gy[b][0], g0[0][a][c], s);
+        s = fma(gy[b][1], g0[1][a][c], s);
+        w[c] = fma(tay, s, u[b][a][c]);
+        pfb[c] = (b == 0) ? gt1 * (TB.INVFACT[2] * sfb[a][c]) : 0.0;
+        pgb[c] = (a == 0) ? gt1 * (TB.INVFACT[2] * sgb[b][c]) : 0.0;
+        wb[c] = 0.0;
+      }
+      flux2d_vjp<FLUX, NV>(pb.ph, w, pfb, pgb, wb);
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        ub[b][a][c] += wb[c];
+        Ub1[b][a][c] = tay * wb[c];
+      }
+    }
+    // U^1 = sum_l gx[a1][l] Fh_(l,a2) + sum_l gy[a2][l] Gh_(a1,l) transposed:
+    // Fh^0bar_(a1,a2) = Fh^0 series term + sum_j gx[j][a1] Ub1_(j,a2), and
+    // Gh^0bar along the column
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+          double sx = (b == 0) ? TB.INVFACT[1] * sfb[a][c] : 0.0;
+          double sy = (a == 0) ? TB.INVFACT[1] * sgb[b][c] : 0.0;
+          sx = fma(gx[0][a], Ub1[b][0][c], sx);
+          sx = fma(gx[1][a], Ub1[b][1][c], sx);
+          sy = fma(gy[0][b], Ub1[0][a][c], sy);
+          sy = fma(gy[1][b], Ub1[1][a][c], sy);
+          f0b[b][a][c] += sx;
+          g0b[b][a][c] += sy;
+        }
+    // first-order parts of the FL-CAT2 blends on the two nodes each reads:
+    // x on (0,0), (1,0); y on (0,0), (0,1)
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      const double lx = 0.5 * (1.0 - psix) * Fb[c];
+      f0b[0][0][c] += lx;
+      ub[0][0][c] += alx * lx;
+      f0b[0][1][c] += lx;
+      ub[0][1][c] += -alx * lx;
+      const double ly = 0.5 * (1.0 - psiy) * Gb[c];
+      g0b[0][0][c] += ly;
+      ub[0][0][c] += aly * ly;
+      g0b[1][0][c] += ly;
+      ub[1][0][c] += -aly * ly;
+    }
+    // Jacobian-transpose products at the node states; contributions
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        flux2d_vjp<FLUX, NV>(pb.ph, u[b][a], f0b[b][a], g0b[b][a], ub[b][a]);
+        const int cslot = (b - 1 + pb.P) * (2 * pb.P) + (a - 1 + pb.P);
+#pragma unroll
+        for (int c = 0; c < NV; ++c) C[c * cstride + (int64_t)cslot * nitems + e] = ub[b][a][c];
+      }
+  }
+}
+
 // The mirror classes (QA, QB) and (QB, QA), QA < QB, in one launch (both
 // recursions in one pass): the grid is cut into two runs of whole XCD groups
 // of blocks sized by the classes' corner counts, at least one per class with
@@ -707,7 +883,13 @@ hipError_t launch_adj2d(const KProb& pb, const KStep& st, const double* ubo, dou
     // them in two launches (one recursion each, in order on the stream):
     // together in one kernel they exceed the register file several times
     constexpr bool SPLIT = Q1 != Q2 && Q1 >= 2 && Q2 >= 2 && Q1 + Q2 >= 6;
-    if constexpr (SPLIT) {
+    if constexpr (Q1 == 1 && Q2 == 1) {
+      // one lane per corner
+      auto kern = k_adj2d_q11<FLUX, NV>;
+      const int grid = persistent_grid(kern, pb.n1 * pb.n2, 0);
+      ProfScope ps(names[1][1], s);
+      kern<<<grid, BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P);
+    } else if constexpr (SPLIT) {
       auto k1 = k_adj2d<FLUX, NV, Q1, Q2, 1>;
       auto k2 = k_adj2d<FLUX, NV, Q1, Q2, 2>;
       ProfScope ps(names[Q1][Q2], s);
