@@ -791,12 +791,15 @@ __device__ __forceinline__ void corners_reading(int m, int j, int n, bool per, i
 
 // 2D gather: cell m collects node (j1, j2) of every corner whose rectangle
 // holds that node and whose node reads cell m (j2, corner row, j1, corner
-// column: one fixed order).
-template <int NV, bool PER>
+// column: one fixed order).  P (the problem's largest half-width) is a
+// template argument: with periodic boundaries every offset has exactly one
+// corner, the loops unroll and the (2P)^2 class-map loads are issued
+// together instead of one after another.
+template <int NV, bool PER, int P>
 __global__ __launch_bounds__(BLOCK) void k_gather2d(KProb pb, KStep st, const double* __restrict__ ubo,
                                                     const double* __restrict__ C, int LMAX, double* ubi) {
   const int64_t m = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  const int nx = (int)pb.nx, ny = (int)pb.ny, P = pb.P, ioff = (int)pb.ioff;
+  const int nx = (int)pb.nx, ny = (int)pb.ny, ioff = (int)pb.ioff;
   if (m >= (int64_t)nx * ny) return;
   constexpr bool per = PER;
   const int m1 = (int)(m % nx), m2 = (int)(m / nx);
@@ -806,6 +809,35 @@ __global__ __launch_bounds__(BLOCK) void k_gather2d(KProb pb, KStep st, const do
   double acc[NV];
 #pragma unroll
   for (int c = 0; c < NV; ++c) acc[c] = ubo[c * plane + m];
+  if constexpr (PER) {
+    int8_t cl[2 * P][2 * P];
+    int64_t ek[2 * P][2 * P];
+#pragma unroll
+    for (int j2 = -P + 1; j2 <= P; ++j2)
+#pragma unroll
+      for (int j1 = -P + 1; j1 <= P; ++j1) {
+        const int r2 = bc_index32(m2 - j2, ny, PERIODIC), r1 = bc_index32(m1 - j1, nx, PERIODIC);
+        const int64_t e = (int64_t)r2 * pb.n1 + r1;
+        ek[j2 + P - 1][j1 + P - 1] = e;
+        cl[j2 + P - 1][j1 + P - 1] = st.cls[e];
+      }
+#pragma unroll
+    for (int j2 = -P + 1; j2 <= P; ++j2)
+#pragma unroll
+      for (int j1 = -P + 1; j1 <= P; ++j1) {
+        const int c0 = cl[j2 + P - 1][j1 + P - 1];
+        if (c0 < 0) continue;
+        const int q1 = c0 / P + 1, q2 = c0 % P + 1;
+        if (j1 < -q1 + 1 || j1 > q1 || j2 < -q2 + 1 || j2 > q2) continue;
+        const int64_t e = ek[j2 + P - 1][j1 + P - 1];
+        const int64_t slot = (int64_t)(j2 + P - 1) * (2 * P) + (j1 + P - 1);
+#pragma unroll
+        for (int c = 0; c < NV; ++c) acc[c] += C[c * cstride + slot * nitems + e];
+      }
+#pragma unroll
+    for (int c = 0; c < NV; ++c) ubi[c * plane + m] = acc[c];
+    return;
+  }
   for (int j2 = -P + 1; j2 <= P; ++j2) {
     int lo2, hi2;
     corners_reading(m2, j2, ny, per, lo2, hi2);
@@ -946,8 +978,8 @@ hipError_t adj2d_impl(const KProb& pb, const KStep& st, const double* ubo, doubl
   {
     ProfScope ps("gather2d", s);
     const unsigned gb = (unsigned)((pb.nx * pb.ny + BLOCK - 1) / BLOCK);
-    if (pb.bc == PERIODIC) k_gather2d<NV, true><<<gb, BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P, ubi);
-    else k_gather2d<NV, false><<<gb, BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P, ubi);
+    if (pb.bc == PERIODIC) k_gather2d<NV, true, P><<<gb, BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P, ubi);
+    else k_gather2d<NV, false, P><<<gb, BLOCK, 0, s>>>(pb, st, ubo, C, 4 * P * P, ubi);
   }
   ACAT_CHECK_LAUNCH();
   return hipSuccess;

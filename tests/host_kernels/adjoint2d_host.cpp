@@ -109,8 +109,8 @@ void gather(Case& cs) {
   const double* C = cs.C.data();
   double* ubi = cs.ubi.data();
   const int grid = (NX * NY + BLOCK - 1) / BLOCK;
-  if (pb.bc == PERIODIC) launch(grid, [=]() { k_gather2d<NV, true>(pb, st, ubo, C, 4 * P * P, ubi); });
-  else launch(grid, [=]() { k_gather2d<NV, false>(pb, st, ubo, C, 4 * P * P, ubi); });
+  if (pb.bc == PERIODIC) launch(grid, [=]() { k_gather2d<NV, true, P>(pb, st, ubo, C, 4 * P * P, ubi); });
+  else launch(grid, [=]() { k_gather2d<NV, false, P>(pb, st, ubo, C, 4 * P * P, ubi); });
 }
 
 template <int Q1, int Q2>
