@@ -22,7 +22,8 @@ Flux evaluations (distinct operations, shared subexpressions once):
   advection f = a u                                            = 1 per variable
 
 Adjoint (reverse mode) of one 2D corner, adjoint_corner_flops_2d: the
-forward recursion up to U^{T-1} (its values are the linearisation points),
+forward recursion up to U^{T-1} (its values are the linearisation points;
+U^{T-1} only on the row and column the fluxes read),
 then the reverse sweep: per level and node, the time-derivative weights
 applied to the incoming adjoint, the Jacobian-transpose products at the
 T-1 predicted states, the adjoint of the Taylor predictions, and the
@@ -125,9 +126,11 @@ def _adj_pass_2d(n1, n2, qt, do_f, do_g, s, cfg, vfg):
     ut_cost = s * (2 * n1 + 2 * n2 + 4)          # transposed differences, scalings, series term
     nlast = (n1 if do_f else 0) + (n2 if do_g else 0) - (1 if (do_f and do_g) else 0)
     total = 0
-    # forward: U^1 .. U^{T-1}, Fh/Gh up to level T-2, predictions up to level T-1
+    # forward: U^1 .. U^{T-1} (U^{T-1} only where the last level's predictions
+    # are read: the row and column of the fluxes), Fh/Gh up to level T-2,
+    # predictions up to level T-1
     for kk in range(2, T + 1):
-        total += R * u_cost
+        total += (R if kk < T else nlast) * u_cost
         if kk < T:
             total += R * (T - 1) * (2 * s + cfg)
             total += R * 2 * (2 * s * T)
