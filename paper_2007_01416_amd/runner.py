@@ -181,10 +181,13 @@ class AdjointRun:
     record_all, the decisions of every step for replay()).  backward(ubar_n)
     -> ubar_0 = (d u_n / d u0)^T ubar_n with the decisions and time steps of
     the forward run frozen; segments are recomputed from their checkpoints.
-    With verify, the order maps and time steps of the recomputation are
-    checked against the forward pass.  With graphs, each segment (k forward
-    steps; k recomputed steps and k adjoint steps) is captured once into a
-    HIP graph on fixed buffers and replayed per segment.
+    The forward runs its last segment into the recomputation buffers (states,
+    decisions, class lists of every step), so the first segment of the
+    reverse pass needs no recomputation (without record_all).  With verify,
+    the order maps and time steps of the recomputation are checked against
+    the forward pass.  With graphs, each segment (k forward steps; k
+    recomputed steps and k adjoint steps) is captured once into a HIP graph
+    on fixed buffers and replayed per segment.
     """
 
     def __init__(self, prob: Problem, cfl: float, nsteps: int, checkpoint_every: int = 20,
@@ -214,6 +217,7 @@ class AdjointRun:
         self._fgraphs, self._bgraphs = {}, {}
         self.hashes = torch.zeros(self.nsteps, dtype=torch.int64, device=device) if verify else None
         self.checkpoints = []
+        self.resident = None    # segment whose steps the recomputation buffers hold
         self.class_log = None   # optional int32 [nsteps, 16]: per-class item counts of each adjoint step
 
     # ------------------------------------------------------------ segments
@@ -225,38 +229,54 @@ class AdjointRun:
         if a is not self.fa:
             self.fa.copy_(a)
 
-    def _bwd_body(self, m):
+    def _rec_body(self, m):
+        """The segment's m steps from seg_u[0], keeping every step's input
+        state, decisions and class lists; the last output goes to tmp."""
         for j in range(m):
-            out = self.seg_u[j + 1] if j + 1 < m else self.tmp   # the segment's last state is not needed
+            out = self.seg_u[j + 1] if j + 1 < m else self.tmp
             step_cfl(self.prob, self.seg_u[j], self.cfl, self.seg_dt[j:j + 1], out=out, ws=self.seg_ws[j],
                      dec=self.seg_dec[j])
+
+    def _adj_body(self, m):
         for j in reversed(range(m)):
             step_adjoint_lists(self.prob, self.seg_u[j], self.seg_dt[j:j + 1], self.seg_dec[j], self.ub,
                                self.seg_ws[j], ubar_in=self.ub, ws=self.aws)
             self.seg_cls[j].copy_(self.seg_ws[j][:64].view(torch.int32))
 
-    def _run(self, cache, m, body):
-        """Run body(m) once; with graphs, the first run of a length is eager
-        and is followed by a capture that later segments of that length replay."""
+    def _bwd_body(self, m):
+        self._rec_body(m)
+        self._adj_body(m)
+
+    def _run(self, cache, key, body):
+        """Run body() once; with graphs, the first run of a key (segment kind
+        and length) is eager and is followed by a capture that later runs of
+        that key replay."""
         if not self.graphs:
             body()
-        elif m in cache:
-            cache[m].replay()
+        elif key in cache:
+            cache[key].replay()
         else:
             body()
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g):
                 body()
-            cache[m] = g
+            cache[key] = g
 
     def forward(self, u0: torch.Tensor) -> torch.Tensor:
         self.fa.copy_(torch.as_tensor(u0, dtype=torch.float64, device=self.device))
         self.checkpoints = []
+        self.resident = None
+        last = (self.nsteps - 1) // self.k
         for s, n0 in enumerate(range(0, self.nsteps, self.k)):
             m = min(self.k, self.nsteps - n0)
             self.checkpoints.append(self.fa.clone())
             if self.record_all:       # every step's decisions kept: eager, into their own buffers
                 self._fwd_body(m, self.all_dec[n0:n0 + m])
+            elif s == last:           # into the recomputation buffers, kept for backward
+                self.seg_u[0].copy_(self.fa)
+                self._run(self._fgraphs, ("rec", m), lambda: self._rec_body(m))
+                self.fa.copy_(self.tmp)
+                self.resident = s
             else:
                 decs = self.seg_dec if self.verify else [None] * m
                 self._run(self._fgraphs, m, lambda: self._fwd_body(m, decs))
@@ -288,8 +308,12 @@ class AdjointRun:
         for s in reversed(range(len(self.checkpoints))):
             n0 = s * self.k
             m = min(self.k, self.nsteps - n0)
-            self.seg_u[0].copy_(self.checkpoints[s])
-            self._run(self._bgraphs, m, lambda: self._bwd_body(m))
+            if s == self.resident:
+                self._run(self._bgraphs, ("adj", m), lambda: self._adj_body(m))
+            else:
+                self.seg_u[0].copy_(self.checkpoints[s])
+                self._run(self._bgraphs, m, lambda: self._bwd_body(m))
+                self.resident = s
             dts[n0:n0 + m].copy_(self.seg_dt[:m])
             if self.class_log is not None:
                 self.class_log[n0:n0 + m].copy_(self.seg_cls[:m])

@@ -317,7 +317,8 @@ def test_checkpointed_run_matches_fd_of_replay(acat):
 def test_graph_captured_segments_match_eager(acat):
     """AdjointRun with graph-captured segments (k = 4, 10 steps: lengths 4
     and 2) gives the same forward state and gradient, bit for bit, as the
-    eager run."""
+    eager run; a second backward after one forward (whose last segment is
+    then no longer resident) gives the same gradient."""
     import torch
     w = workloads.adjoint_2d(n=64)
     po, pg = from_workload(w)
@@ -329,7 +330,8 @@ def test_graph_captured_segments_match_eager(acat):
         g = run.backward(uT * 0.5)
         uT2 = run.forward(u0)                       # replayed graphs the second time
         g2 = run.backward(uT2 * 0.5)
-        assert torch.equal(uT, uT2) and torch.equal(g, g2)
+        g3 = run.backward(uT2 * 0.5)
+        assert torch.equal(uT, uT2) and torch.equal(g, g2) and torch.equal(g, g3)
         res.append((uT, g))
     assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
 
