@@ -461,4 +461,5 @@ def profile_read(max_kernels: int = 64) -> dict:
     return out
 
 
-from .runner import ACATRun, AdjointRun, BatchSolver, Solver  # noqa: E402  (time loops and graph capture)
+from .runner import (ACATRun, AdjointRun, BatchSolver, Solver, auto_checkpoint,  # noqa: E402  (time loops, graphs)
+                     resident_bytes_per_step)

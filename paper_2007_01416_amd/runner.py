@@ -14,14 +14,16 @@ every k steps; the backward recomputes each k-step segment from its
 checkpoint (recording decisions and time steps) and runs the adjoint steps
 of the segment in reverse.  Each recomputed step keeps its own step
 workspace, so that its adjoint step reuses the step's order-class lists
-(acat_step_adjoint_lists) instead of classifying again.
+(acat_step_adjoint_lists) instead of classifying again.  With
+checkpoint_every="auto" the segment is as long as a device-memory budget
+allows (every step resident when it fits: no recomputation at all).
 """
 from __future__ import annotations
 
 import torch
 
 from . import (Batch, Decisions, Problem, adjoint_workspace, cfl_dt, max_wave_speed, step, step_adjoint_lists,
-               step_cfl, step_replay, workspace)
+               step_cfl, step_replay, workspace, workspace_bytes)
 
 
 class Solver:
@@ -174,6 +176,26 @@ def _order_hash(dec: Decisions) -> torch.Tensor:
     return h
 
 
+def resident_bytes_per_step(prob: Problem) -> int:
+    """Device bytes one step of a recomputed segment holds: its input state,
+    its step workspace (order-class lists) and its decisions."""
+    def numel(shape):
+        n = 1
+        for d in (shape if isinstance(shape, tuple) else (shape,)):
+            n *= d
+        return n
+    nif = sum(numel(s) for s in prob.interfaces if s is not None)
+    return 8 * numel(tuple(prob.shape)) + workspace_bytes(prob) + nif * (1 + 8 + 8)
+
+
+def auto_checkpoint(nsteps: int, per_step: int, budget: int) -> int:
+    """Longest segment (steps between checkpoints) whose resident steps fit
+    in `budget` bytes: nsteps when the whole run fits, at least 1."""
+    if nsteps < 1 or per_step < 1:
+        raise ValueError("nsteps and per_step must be >= 1")
+    return int(max(1, min(nsteps, budget // per_step)))
+
+
 class AdjointRun:
     """n CFL steps of one problem with a reverse pass.
 
@@ -190,8 +212,13 @@ class AdjointRun:
     on fixed buffers and replayed per segment.
     """
 
-    def __init__(self, prob: Problem, cfl: float, nsteps: int, checkpoint_every: int = 20,
-                 record_all: bool = False, verify: bool = True, graphs: bool = True, device="cuda"):
+    def __init__(self, prob: Problem, cfl: float, nsteps: int, checkpoint_every=20,
+                 record_all: bool = False, verify: bool = True, graphs: bool = True, device="cuda",
+                 memory_budget: int = None):
+        if checkpoint_every == "auto":
+            # default budget: half of the device memory free now
+            budget = memory_budget if memory_budget is not None else torch.cuda.mem_get_info(device)[0] // 2
+            checkpoint_every = auto_checkpoint(int(nsteps), resident_bytes_per_step(prob), int(budget))
         if nsteps < 1 or checkpoint_every < 1:
             raise ValueError("nsteps and checkpoint_every must be >= 1")
         self.prob, self.cfl, self.nsteps, self.k = prob, float(cfl), int(nsteps), int(checkpoint_every)

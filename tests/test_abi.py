@@ -121,6 +121,22 @@ def test_workspace_grows_with_problem(lib):
     assert w2 > 9 * 4 * 64 * 32
 
 
+def test_auto_checkpoint_spacing(lib):
+    """AdjointRun(checkpoint_every="auto"): the segment is the longest whose
+    resident steps (state, step workspace, decisions) fit the budget."""
+    import paper_2007_01416_amd as acat
+    p2 = _prob(dim=2, nvar=4, nx=64, ny=32, dy=0.1, P=3)
+    per = acat.resident_bytes_per_step(p2)
+    # state 4 x 64 x 32 doubles, the step workspace, and per interface an
+    # order (1 byte), psi^1 and alpha (8 bytes each) in both directions
+    assert per == 8 * 4 * 64 * 32 + acat.workspace_bytes(p2) + (32 * 64 + 32 * 64) * 17
+    assert acat.auto_checkpoint(200, per, 10 ** 15) == 200
+    assert acat.auto_checkpoint(200, per, 7 * per + per - 1) == 7
+    assert acat.auto_checkpoint(200, per, 0) == 1
+    with pytest.raises(ValueError):
+        acat.auto_checkpoint(0, per, 10 ** 9)
+
+
 def _batch_struct(n, P, bc, dx, flux=2, nvar=3):
     import paper_2007_01416_amd as acat
     n = np.ascontiguousarray(n, np.int64); P = np.ascontiguousarray(P, np.int32)

@@ -336,6 +336,26 @@ def test_graph_captured_segments_match_eager(acat):
     assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
 
 
+def test_auto_checkpoint_gives_the_same_gradient(acat):
+    """checkpoint_every="auto" (the whole 10-step run resident: no
+    recomputation) and a budget of three steps (segments 3, 3, 3, 1) give the
+    gradient of checkpoint_every=4 bit for bit."""
+    import torch
+    w = workloads.adjoint_2d(n=64)
+    po, pg = from_workload(w)
+    u0 = torch.from_numpy(w["u"]).cuda()
+    ref = acat.AdjointRun(pg, w["cfl"], 10, checkpoint_every=4)
+    g_ref = ref.backward(ref.forward(u0) * 0.5)
+    auto = acat.AdjointRun(pg, w["cfl"], 10, checkpoint_every="auto")
+    assert auto.k == 10
+    g_auto = auto.backward(auto.forward(u0) * 0.5)
+    per = acat.resident_bytes_per_step(pg)
+    small = acat.AdjointRun(pg, w["cfl"], 10, checkpoint_every="auto", memory_budget=3 * per + 1)
+    assert small.k == 3
+    g_small = small.backward(small.forward(u0) * 0.5)
+    assert torch.equal(g_ref, g_auto) and torch.equal(g_ref, g_small)
+
+
 @pytest.mark.parametrize("bc", ["periodic", "transmissive"])
 @pytest.mark.parametrize("q1,q2", [(a, b) for a in range(1, 5) for b in range(1, 5)])
 def test_adjoint_every_corner_class_forced(acat, q1, q2, bc):
