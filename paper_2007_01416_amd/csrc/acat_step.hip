@@ -425,6 +425,12 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, const double (&u)[NV
   // Taylor predictions W_r = u + sum_{l<kk} r^l/l! U^l at the time nodes r != 0,
   // extended by one term per level (the same chain of fused multiply-adds as
   // summing from u each level)
+  // the row derivative weights of this node in registers for the pass (the
+  // column weights are read from LDS at each use: both held would cost the
+  // order-6 square class its third wave per SIMD)
+  double wx[N1];
+#pragma unroll
+  for (int l = 0; l < N1; ++l) wx[l] = g1x[l];
   double W[2 * QT][NV];
 #pragma unroll
   for (int ri = 0; ri < 2 * QT; ++ri)
@@ -447,7 +453,7 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, const double (&u)[NV
     for (int c = 0; c < NV; ++c) {
       double s = 0.0;
 #pragma unroll
-      for (int l = 0; l < N1; ++l) s = fma(g1x[l], Xch<NV>::get(xr, stride, gbase + a2 * N1 + l, c, false), s);
+      for (int l = 0; l < N1; ++l) s = fma(wx[l], Xch<NV>::get(xr, stride, gbase + a2 * N1 + l, c, false), s);
 #pragma unroll
       for (int l = 0; l < N2; ++l) s = fma(g1y[l], Xch<NV>::get(xr, stride, gbase + l * N1 + a1, c, true), s);
       Uk[c] = s;
@@ -552,8 +558,9 @@ __device__ __forceinline__ void flux2d_body(const KProb& pb, const KStep& st, co
   const int nx32 = (int)pb.nx, ny32 = (int)pb.ny, ioff = (int)pb.ioff;
   const uint32_t n1u = (uint32_t)pb.n1;
 
-  // derivative weights times -lamx (rows) and -lamy (columns), in LDS (read
-  // at each use rather than held in registers)
+  // derivative weights times -lamx (rows) and -lamy (columns), in LDS (the
+  // corner pass holds a node's row weights in registers and reads its column
+  // weights at each use)
   for (int i = tid; i < N1 * N1 + N2 * N2; i += BLOCK)
     g1s[i] = i < N1 * N1 ? -lamx * TB.G1[Q1][i / N1][i % N1]
                          : -lamy * TB.G1[Q2][(i - N1 * N1) / N2][(i - N1 * N1) % N2];
