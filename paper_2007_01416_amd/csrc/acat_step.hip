@@ -425,12 +425,17 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, const double (&u)[NV
   // Taylor predictions W_r = u + sum_{l<kk} r^l/l! U^l at the time nodes r != 0,
   // extended by one term per level (the same chain of fused multiply-adds as
   // summing from u each level)
-  // the row derivative weights of this node in registers for the pass (the
-  // column weights are read from LDS at each use: both held would cost the
-  // order-6 square class its third wave per SIMD)
-  double wx[N1];
+  // the row derivative weights of this node in registers for the pass; the
+  // column weights too in the order-8 square class (two waves per SIMD with
+  // or without them), elsewhere read from LDS at each use (held, they would
+  // cost the order-6 square class its third wave per SIMD; the order-4 one
+  // ran slower)
+  constexpr bool WYR = Q1 == 4 && Q2 == 4;
+  double wx[N1], wy[WYR ? N2 : 1];
 #pragma unroll
   for (int l = 0; l < N1; ++l) wx[l] = g1x[l];
+#pragma unroll
+  for (int l = 0; l < (WYR ? N2 : 1); ++l) wy[l] = WYR ? g1y[l] : 0.0;
   double W[2 * QT][NV];
 #pragma unroll
   for (int ri = 0; ri < 2 * QT; ++ri)
@@ -455,7 +460,8 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, const double (&u)[NV
 #pragma unroll
       for (int l = 0; l < N1; ++l) s = fma(wx[l], Xch<NV>::get(xr, stride, gbase + a2 * N1 + l, c, false), s);
 #pragma unroll
-      for (int l = 0; l < N2; ++l) s = fma(g1y[l], Xch<NV>::get(xr, stride, gbase + l * N1 + a1, c, true), s);
+      for (int l = 0; l < N2; ++l)
+        s = fma(WYR ? wy[WYR ? l : 0] : g1y[l], Xch<NV>::get(xr, stride, gbase + l * N1 + a1, c, true), s);
       Uk[c] = s;
     }
 #pragma unroll
