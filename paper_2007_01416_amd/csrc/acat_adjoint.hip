@@ -280,6 +280,13 @@ __device__ __forceinline__ void corner_adjoint(const Phys& ph, const double (&u)
     gc[c] = g0[c];
   }
   double U[T][NV];
+  // this node's derivative weights of the forward differences, in registers
+  // for the pass (the transposed ones are read from LDS at each use)
+  double wfx[N1], wfy[N2];
+#pragma unroll
+  for (int l = 0; l < N1; ++l) wfx[l] = gx[a1 * N1 + l];
+#pragma unroll
+  for (int l = 0; l < N2; ++l) wfy[l] = gy[a2 * N2 + l];
   // forward: U^1 .. U^{T-1}
 #pragma unroll
   for (int kk = 2; kk <= T; ++kk) {
@@ -293,9 +300,9 @@ __device__ __forceinline__ void corner_adjoint(const Phys& ph, const double (&u)
     for (int c = 0; c < NV; ++c) {
       double s = 0.0;
 #pragma unroll
-      for (int l = 0; l < N1; ++l) s = fma(gx[a1 * N1 + l], Xch<NV>::get(xr, stride, gbase + a2 * N1 + l, c, false), s);
+      for (int l = 0; l < N1; ++l) s = fma(wfx[l], Xch<NV>::get(xr, stride, gbase + a2 * N1 + l, c, false), s);
 #pragma unroll
-      for (int l = 0; l < N2; ++l) s = fma(gy[a2 * N2 + l], Xch<NV>::get(xr, stride, gbase + l * N1 + a1, c, true), s);
+      for (int l = 0; l < N2; ++l) s = fma(wfy[l], Xch<NV>::get(xr, stride, gbase + l * N1 + a1, c, true), s);
       U[kk - 1][c] = s;
     }
     buf ^= 1;
