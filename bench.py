@@ -294,8 +294,9 @@ def bench_adjoint(acat, workloads, F, fd_dirs=32, fd_h=(1e-4, 1e-5, 1e-6, 1e-7, 
         v.numel() * v.element_size() for d in rrun.seg_dec for v in vars(d).values() if torch.is_tensor(v))
     del rrun
     # kernel durations: the same backward launched eagerly (graph replays are not
-    # bracketed by the library's events), with the per-step class counts
-    erun = acat.AdjointRun(pg, cfl, nsteps, k, verify=False, graphs=False)
+    # bracketed by the library's events) on one stream (the timed run overlaps
+    # recomputation and adjoint steps on two), with the per-step class counts
+    erun = acat.AdjointRun(pg, cfl, nsteps, k, verify=False, graphs=False, overlap=False)
     erun.forward(u0)
     erun.class_log = torch.zeros((nsteps, 16), dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()

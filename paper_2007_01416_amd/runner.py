@@ -196,6 +196,21 @@ def auto_checkpoint(nsteps: int, per_step: int, budget: int) -> int:
     return int(max(1, min(nsteps, budget // per_step)))
 
 
+class _Segment:
+    """Buffers of one recomputed segment of up to k steps: every step's input
+    state, decisions, time step, step workspace (class lists) and class
+    counts, and a sink for the segment's last output."""
+
+    def __init__(self, prob: Problem, k: int, device):
+        shape = prob.shape
+        self.dt = torch.zeros(k, dtype=torch.float64, device=device)
+        self.dec = [Decisions(prob, device) for _ in range(k)]
+        self.u = [torch.empty(shape, dtype=torch.float64, device=device) for _ in range(k)]
+        self.ws = [workspace(prob, device) for _ in range(k)]
+        self.cls = torch.zeros((k, 16), dtype=torch.int32, device=device)
+        self.tmp = torch.empty(shape, dtype=torch.float64, device=device)
+
+
 class AdjointRun:
     """n CFL steps of one problem with a reverse pass.
 
@@ -205,16 +220,20 @@ class AdjointRun:
     the forward run frozen; segments are recomputed from their checkpoints.
     The forward runs its last segment into the recomputation buffers (states,
     decisions, class lists of every step), so the first segment of the
-    reverse pass needs no recomputation (without record_all).  With verify,
-    the order maps and time steps of the recomputation are checked against
-    the forward pass.  With graphs, each segment (k forward steps; k
-    recomputed steps and k adjoint steps) is captured once into a HIP graph
-    on fixed buffers and replayed per segment.
+    reverse pass needs no recomputation (without record_all).  With overlap
+    (the default; more than one segment), two sets of segment buffers
+    alternate: the recomputation of segment s - 1 runs on a second stream
+    (default priority) while the adjoint steps of segment s run on the
+    caller's stream; the results are those of the serial pass, bit for bit.  With verify, the order
+    maps and time steps of the recomputation are checked against the forward
+    pass.  With graphs, each segment (k forward steps; k recomputed steps; k
+    adjoint steps) is captured once per buffer set into a HIP graph on fixed
+    buffers and replayed per segment.
     """
 
     def __init__(self, prob: Problem, cfl: float, nsteps: int, checkpoint_every=20,
                  record_all: bool = False, verify: bool = True, graphs: bool = True, device="cuda",
-                 memory_budget: int = None):
+                 memory_budget: int = None, overlap: bool = True):
         if checkpoint_every == "auto":
             # default budget: half of the device memory free now
             budget = memory_budget if memory_budget is not None else torch.cuda.mem_get_info(device)[0] // 2
@@ -228,15 +247,15 @@ class AdjointRun:
         self.ws = workspace(prob, device)
         self.aws = adjoint_workspace(prob, device)
         self.dts = torch.zeros(self.nsteps, dtype=torch.float64, device=device)
-        self.seg_dt = torch.zeros(k, dtype=torch.float64, device=device)
-        self.seg_dec = [Decisions(prob, device) for _ in range(k)]
-        self.seg_u = [torch.empty(shape, dtype=torch.float64, device=device) for _ in range(k)]
-        self.seg_ws = [workspace(prob, device) for _ in range(k)]   # one per recomputed step: its class lists
-        self.seg_cls = torch.zeros((k, 16), dtype=torch.int32, device=device)
+        nseg = (self.nsteps + self.k - 1) // self.k
+        self.overlap = bool(overlap) and nseg > 1
+        self.segs = [_Segment(prob, k, device) for _ in range(2 if self.overlap else 1)]
+        seg = self.segs[0]
+        self.seg_dt, self.seg_dec, self.seg_u, self.seg_ws, self.seg_cls = seg.dt, seg.dec, seg.u, seg.ws, seg.cls
+        self.side = torch.cuda.Stream(device=device) if self.overlap else None   # default priority
         self.fa = torch.empty(shape, dtype=torch.float64, device=device)    # forward state at segment bounds
         self.fb = torch.empty(shape, dtype=torch.float64, device=device)
         self.ub = torch.empty(shape, dtype=torch.float64, device=device)    # adjoint state
-        self.tmp = torch.empty(shape, dtype=torch.float64, device=device)
         self.record_all = record_all
         self.all_dec = [Decisions(prob, device) for _ in range(self.nsteps)] if record_all else None
         self.verify = verify
@@ -244,7 +263,7 @@ class AdjointRun:
         self._fgraphs, self._bgraphs = {}, {}
         self.hashes = torch.zeros(self.nsteps, dtype=torch.int64, device=device) if verify else None
         self.checkpoints = []
-        self.resident = None    # segment whose steps the recomputation buffers hold
+        self.resident = None    # segment whose steps the first buffer set holds
         self.class_log = None   # optional int32 [nsteps, 16]: per-class item counts of each adjoint step
 
     # ------------------------------------------------------------ segments
@@ -256,28 +275,29 @@ class AdjointRun:
         if a is not self.fa:
             self.fa.copy_(a)
 
-    def _rec_body(self, m):
-        """The segment's m steps from seg_u[0], keeping every step's input
-        state, decisions and class lists; the last output goes to tmp."""
+    def _rec_body(self, m, b=0):
+        """The segment's m steps from u[0] of buffer set b, keeping every
+        step's input state, decisions and class lists."""
+        sg = self.segs[b]
         for j in range(m):
-            out = self.seg_u[j + 1] if j + 1 < m else self.tmp
-            step_cfl(self.prob, self.seg_u[j], self.cfl, self.seg_dt[j:j + 1], out=out, ws=self.seg_ws[j],
-                     dec=self.seg_dec[j])
+            out = sg.u[j + 1] if j + 1 < m else sg.tmp
+            step_cfl(self.prob, sg.u[j], self.cfl, sg.dt[j:j + 1], out=out, ws=sg.ws[j], dec=sg.dec[j])
 
-    def _adj_body(self, m):
+    def _adj_body(self, m, b=0):
+        sg = self.segs[b]
         for j in reversed(range(m)):
-            step_adjoint_lists(self.prob, self.seg_u[j], self.seg_dt[j:j + 1], self.seg_dec[j], self.ub,
-                               self.seg_ws[j], ubar_in=self.ub, ws=self.aws)
-            self.seg_cls[j].copy_(self.seg_ws[j][:64].view(torch.int32))
+            step_adjoint_lists(self.prob, sg.u[j], sg.dt[j:j + 1], sg.dec[j], self.ub, sg.ws[j],
+                               ubar_in=self.ub, ws=self.aws)
+            sg.cls[j].copy_(sg.ws[j][:64].view(torch.int32))
 
     def _bwd_body(self, m):
         self._rec_body(m)
         self._adj_body(m)
 
     def _run(self, cache, key, body):
-        """Run body() once; with graphs, the first run of a key (segment kind
-        and length) is eager and is followed by a capture that later runs of
-        that key replay."""
+        """Run body() once; with graphs, the first run of a key (segment kind,
+        buffer set and length) is eager and is followed by a capture that
+        later runs of that key replay (on the current stream)."""
         if not self.graphs:
             body()
         elif key in cache:
@@ -301,8 +321,8 @@ class AdjointRun:
                 self._fwd_body(m, self.all_dec[n0:n0 + m])
             elif s == last:           # into the recomputation buffers, kept for backward
                 self.seg_u[0].copy_(self.fa)
-                self._run(self._fgraphs, ("rec", m), lambda: self._rec_body(m))
-                self.fa.copy_(self.tmp)
+                self._run(self._fgraphs, ("rec", 0, m), lambda: self._rec_body(m))
+                self.fa.copy_(self.segs[0].tmp)
                 self.resident = s
             else:
                 decs = self.seg_dec if self.verify else [None] * m
@@ -326,31 +346,79 @@ class AdjointRun:
             u, nxt = nxt, u
         return u
 
+    def _record(self, s, b, dts, hashes):
+        """Bookkeeping of segment s held in buffer set b (on the current stream)."""
+        n0 = s * self.k
+        m = min(self.k, self.nsteps - n0)
+        sg = self.segs[b]
+        dts[n0:n0 + m].copy_(sg.dt[:m])
+        if self.class_log is not None:
+            self.class_log[n0:n0 + m].copy_(sg.cls[:m])
+        if self.verify:
+            for j in range(m):
+                hashes[n0 + j] = _order_hash(sg.dec[j])
+
+    def _seg_len(self, s):
+        return min(self.k, self.nsteps - s * self.k)
+
     def backward(self, ubar: torch.Tensor) -> torch.Tensor:
         if not self.checkpoints:
             raise RuntimeError("backward before forward")
         self.ub.copy_(torch.as_tensor(ubar, dtype=torch.float64, device=self.device))
         dts = torch.zeros(self.nsteps, dtype=torch.float64, device=self.device)
         hashes = torch.zeros_like(self.hashes) if self.verify else None
-        for s in reversed(range(len(self.checkpoints))):
-            n0 = s * self.k
-            m = min(self.k, self.nsteps - n0)
-            if s == self.resident:
-                self._run(self._bgraphs, ("adj", m), lambda: self._adj_body(m))
-            else:
-                self.seg_u[0].copy_(self.checkpoints[s])
-                self._run(self._bgraphs, m, lambda: self._bwd_body(m))
-                self.resident = s
-            dts[n0:n0 + m].copy_(self.seg_dt[:m])
-            if self.class_log is not None:
-                self.class_log[n0:n0 + m].copy_(self.seg_cls[:m])
-            if self.verify:
-                for j in range(m):
-                    hashes[n0 + j] = _order_hash(self.seg_dec[j])
+        if self.overlap:
+            self._backward_overlapped(dts, hashes)
+        else:
+            for s in reversed(range(len(self.checkpoints))):
+                m = self._seg_len(s)
+                if s == self.resident:
+                    self._run(self._bgraphs, ("adj", 0, m), lambda: self._adj_body(m))
+                else:
+                    self.seg_u[0].copy_(self.checkpoints[s])
+                    self._run(self._bgraphs, m, lambda: self._bwd_body(m))
+                    self.resident = s
+                self._record(s, 0, dts, hashes)
         if self.verify:
             if not torch.equal(hashes, self.hashes) or not torch.equal(dts, self.dts):
                 raise RuntimeError("recomputed decisions differ from the forward run")
         return self.ub.clone()
+
+    def _backward_overlapped(self, dts, hashes):
+        """Segments in reverse; segment s - 1 is recomputed on the side stream
+        into the other buffer set while the adjoint steps of segment s run on
+        the caller's stream.  Events order each buffer set's reuse: a
+        recomputation waits for the adjoint steps that last read its set, the
+        adjoint steps wait for the recomputation that filled theirs."""
+        main, side = torch.cuda.current_stream(self.device), self.side
+        nseg = len(self.checkpoints)
+        rec_done = [torch.cuda.Event() for _ in range(2)]
+        adj_done = [torch.cuda.Event() for _ in range(2)]
+        for e in adj_done:
+            e.record(main)
+        side.wait_stream(main)        # the checkpoints and ubar are ready
+        b = 0
+        if self.resident != nseg - 1:  # the last segment recomputed first, on the caller's stream
+            m = self._seg_len(nseg - 1)
+            self.segs[0].u[0].copy_(self.checkpoints[nseg - 1])
+            self._run(self._bgraphs, ("rec", 0, m), lambda: self._rec_body(m, 0))
+        for s in reversed(range(nseg)):
+            nb = 1 - b
+            if s > 0:
+                mp = self._seg_len(s - 1)
+                side.wait_event(adj_done[nb])
+                with torch.cuda.stream(side):
+                    self.segs[nb].u[0].copy_(self.checkpoints[s - 1])
+                    self._run(self._bgraphs, ("rec", nb, mp), lambda: self._rec_body(mp, nb))
+                    rec_done[nb].record(side)
+            m = self._seg_len(s)
+            self._run(self._bgraphs, ("adj", b, m), lambda: self._adj_body(m, b))
+            self._record(s, b, dts, hashes)
+            adj_done[b].record(main)
+            if s > 0:
+                main.wait_event(rec_done[nb])
+            b = nb
+        self.resident = None      # the buffer sets now hold segments 0 and 1 in no fixed order
 
 
 class ACATRun(torch.autograd.Function):
