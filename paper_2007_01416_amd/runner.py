@@ -264,7 +264,9 @@ class AdjointRun:
         self.hashes = torch.zeros(self.nsteps, dtype=torch.int64, device=device) if verify else None
         self.checkpoints = []
         self.resident = None    # segment whose steps the first buffer set holds
-        self.class_log = None   # optional int32 [nsteps, 16]: per-class item counts of each adjoint step
+        # optional int32 [nsteps, 16]: per-class item counts of each adjoint step
+        # (entries (q1 - 1) P + (q2 - 1); the later entries of a row are not defined)
+        self.class_log = None
 
     # ------------------------------------------------------------ segments
     def _fwd_body(self, m, decs):

@@ -342,19 +342,25 @@ def test_overlapped_reverse_pass_equals_serial(acat, graphs):
     stream (two buffer sets, the default) gives the serial pass's gradient
     bit for bit, with the recomputed decisions verified against the forward
     run; 23 steps, checkpoints every 5 (segments 5, 5, 5, 5, 3), backward
-    twice after one forward."""
+    twice after one forward; the per-step class counts agree too."""
     import torch
     w = workloads.adjoint_2d(n=64)
     po, pg = from_workload(w)
     u0 = torch.from_numpy(w["u"]).cuda()
     ser = acat.AdjointRun(pg, w["cfl"], 23, checkpoint_every=5, graphs=False, overlap=False)
+    ser.class_log = torch.zeros((23, 16), dtype=torch.int32, device="cuda")
     g_ser = ser.backward(ser.forward(u0) * 0.5)
     ovl = acat.AdjointRun(pg, w["cfl"], 23, checkpoint_every=5, graphs=graphs)
     assert ovl.overlap and len(ovl.segs) == 2
+    ovl.class_log = torch.zeros((23, 16), dtype=torch.int32, device="cuda")
     uT = ovl.forward(u0)
     g1 = ovl.backward(uT * 0.5)
     g2 = ovl.backward(uT * 0.5)
     assert torch.equal(g_ser, g1) and torch.equal(g_ser, g2)
+    # the per-step class counts of each adjoint step land on the same steps
+    # (P = 2: classes 0..3; the later entries of a log row are not defined)
+    ncls = w["P"] * w["P"]
+    assert torch.equal(ser.class_log[:, :ncls], ovl.class_log[:, :ncls]) and int(ser.class_log[:, :ncls].sum()) > 0
 
 
 def test_auto_checkpoint_gives_the_same_gradient(acat):
