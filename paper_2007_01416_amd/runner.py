@@ -16,7 +16,8 @@ of the segment in reverse.  Each recomputed step keeps its own step
 workspace, so that its adjoint step reuses the step's order-class lists
 (acat_step_adjoint_lists) instead of classifying again.  With
 checkpoint_every="auto" the segment is as long as a device-memory budget
-allows (every step resident when it fits: no recomputation at all).
+allows (every step resident when it fits: no recomputation at all; otherwise
+the budget holds the two alternating buffer sets of the overlapped pass).
 """
 from __future__ import annotations
 
@@ -237,7 +238,10 @@ class AdjointRun:
         if checkpoint_every == "auto":
             # default budget: half of the device memory free now
             budget = memory_budget if memory_budget is not None else torch.cuda.mem_get_info(device)[0] // 2
-            checkpoint_every = auto_checkpoint(int(nsteps), resident_bytes_per_step(prob), int(budget))
+            per = resident_bytes_per_step(prob)
+            checkpoint_every = auto_checkpoint(int(nsteps), per, int(budget))
+            if checkpoint_every < nsteps and overlap:   # two buffer sets alternate
+                checkpoint_every = auto_checkpoint(int(nsteps), 2 * per, int(budget))
         if nsteps < 1 or checkpoint_every < 1:
             raise ValueError("nsteps and checkpoint_every must be >= 1")
         self.prob, self.cfl, self.nsteps, self.k = prob, float(cfl), int(nsteps), int(checkpoint_every)
