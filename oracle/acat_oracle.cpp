@@ -53,10 +53,12 @@
 // identities and tables, closed forms (CAT2 in 1D and 2D, the order-2p
 // Lax-Wendroff stencil and the q1 != q2 rectangles for linear flux), exact
 // shift at unit Courant number, convergence orders, conservation, symmetries,
-// reductions, and exact Riemann solutions of the paper's shock tubes.  Parity
-// unpinned: the values of nonlinear shocked states, and the nonlinear flux
-// evaluations on q1 != q2 rectangles, for which no closed form or printed
-// value exists.
+// reductions (every forced corner class, nonlinear Euler data constant along
+// one direction, against the 1D fluxes of that direction's order), and exact
+// Riemann solutions of the paper's shock tubes.  Parity unpinned: the values
+// of nonlinear shocked states, and the coupling of the two directions in the
+// nonlinear flux evaluations on q1 != q2 rectangles (pinned for linear flux by
+// the closed form), for which no closed form or printed value exists.
 //
 // Build: g++ -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math).
 #include <cmath>

@@ -95,6 +95,52 @@ def test_y_invariant_data_reproduces_1d(P, bc):
     assert np.abs(r2["u"][2]).max() < 1e-13
 
 
+@pytest.mark.parametrize("q1,q2", [(a, b) for a in range(1, 5) for b in range(1, 5)])
+def test_forced_rectangles_reduce_to_1d(q1, q2):
+    """Every corner class (q1, q2) of P = 4 forced on nonlinear 2D Euler data
+    that is constant along one direction (the transverse velocity zero): the
+    x-fluxes equal the 1D Euler fluxes of order q1 (whatever q2), and on
+    data constant along x the y-fluxes equal the 1D fluxes of order q2
+    (whatever q1) — each recursion of a rectangle runs on its own direction's
+    stencil and time nodes.  Not bit for bit: the transverse differences of
+    the constant transverse flux are zero only up to rounding."""
+    n, m, P, dt, d = 32, 8, 4, 0.004, 1.0 / 32
+    x = (np.arange(n) + 0.5) / n
+    rho = 1 + 0.2 * np.sin(2 * np.pi * x)
+    v = 0.3 + 0.1 * np.cos(2 * np.pi * x)
+    p = 1 + 0.1 * np.sin(2 * np.pi * (x + 0.1))
+    E = p / (G - 1) + 0.5 * rho * v * v
+    u1 = np.stack([rho, rho * v, E])
+    p1 = oracle.Problem(dim=1, nvar=3, nx=n, flux=EUL, P=P, bc=0, dx=d)
+    nI = p1.n_interfaces[0]
+    for qa, direction in ((q1, "x"), (q2, "y")):
+        r1 = oracle.step1d(p1, u1, dt, order=np.full(nI, qa, np.int8), psi1=np.full(nI, 0.6),
+                           alpha=np.full(nI, 2.0))
+        if direction == "x":    # constant along y: (rho, m, 0, E)
+            u2 = np.stack([np.tile(c, (m, 1)) for c in (rho, rho * v, 0 * rho, E)])
+            p2 = prob2d(n, m, P, dx=d, dy=d)
+        else:                   # constant along x: (rho, 0, n, E), the same profile along y
+            u2 = np.stack([np.tile(c[:, None], (1, m)) for c in (rho, 0 * rho, rho * v, E)])
+            p2 = prob2d(m, n, P, dx=d, dy=d)
+        nIx, nIy = p2.n_interfaces
+        maps = (np.full((p2.ny, nIx), q1, np.int8), np.full((nIy, p2.nx), q2, np.int8),
+                np.full((p2.ny, nIx), 0.6), np.full((nIy, p2.nx), 0.6),
+                np.full((p2.ny, nIx), 2.0), np.full((nIy, p2.nx), 2.0))
+        r2 = oracle.step2d(p2, u2, dt, maps=maps)
+        want = r1["flux"]
+        scale = np.abs(want).max()
+        if direction == "x":
+            got = r2["F"][[0, 1, 3]]                 # [3, m, n]
+            assert np.abs(r2["F"][2]).max() < 1e-13 * scale
+            for j in range(m):
+                assert np.abs(got[:, j, :] - want).max() < 1e-12 * scale, (q1, q2, direction, j)
+        else:
+            got = r2["G"][[0, 2, 3]]                 # [3, n, m]
+            assert np.abs(r2["G"][1]).max() < 1e-13 * scale
+            for i in range(m):
+                assert np.abs(got[:, :, i] - want).max() < 1e-12 * scale, (q1, q2, direction, i)
+
+
 @pytest.mark.parametrize("P", [1, 2, 3, 4])
 def test_transpose_symmetry(P):
     rng = np.random.default_rng(20 + P)
