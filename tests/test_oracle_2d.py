@@ -157,6 +157,36 @@ def test_transpose_symmetry(P):
         assert (a["ordx"] != a["ordy"]).any()   # mixed rectangles were exercised
 
 
+@pytest.mark.parametrize("q1,q2", [(a, b) for a in range(1, 5) for b in range(1, 5) if a != b])
+def test_forced_rectangles_transpose_symmetry(q1, q2):
+    """Class (q1, q2) forced on smooth 2D Euler data of a 20 x 16 grid with
+    dx != dy, and class (q2, q1) on the transposed data, grid and spacings
+    (momenta swapped): the x-fluxes of the one are the y-fluxes of the other
+    and the new states agree — the two directions' recursions are coupled
+    symmetrically on every rectangle (a direction-specific slip, such as a
+    swapped lamx / lamy or an nx / ny mix-up, breaks it)."""
+    rng = np.random.default_rng(40 + 4 * q1 + q2)
+    n1, n2, P, dt = 20, 16, 4, 0.002
+    u = smooth_state(rng, n1, n2, jump=False)
+    uT = np.stack([u[0].T, u[2].T, u[1].T, u[3].T])
+    pa = prob2d(n1, n2, P, dx=0.05, dy=0.04)
+    pb = prob2d(n2, n1, P, dx=0.04, dy=0.05)
+
+    def maps(pr, qx, qy):
+        nIx, nIy = pr.n_interfaces
+        return (np.full((pr.ny, nIx), qx, np.int8), np.full((nIy, pr.nx), qy, np.int8),
+                np.full((pr.ny, nIx), 0.6), np.full((nIy, pr.nx), 0.6),
+                np.full((pr.ny, nIx), 2.0), np.full((nIy, pr.nx), 2.0))
+    a = oracle.step2d(pa, u, dt, maps=maps(pa, q1, q2))
+    b = oracle.step2d(pb, uT, dt, maps=maps(pb, q2, q1))
+    perm = [0, 2, 1, 3]
+    scale = np.abs(a["F"]).max()
+    assert np.abs(a["F"] - b["G"][perm].transpose(0, 2, 1)).max() < 1e-13 * scale
+    assert np.abs(a["G"] - b["F"][perm].transpose(0, 2, 1)).max() < 1e-13 * scale
+    bu = b["u"][perm].transpose(0, 2, 1)
+    assert np.allclose(a["u"], bu, rtol=1e-13, atol=1e-13)
+
+
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
 def test_x_only_advection_is_row_lax_wendroff(p):
     from fractions import Fraction as Fr
