@@ -225,7 +225,8 @@ acat_status acat_cfl_dt(const acat_problem* prob, const double* smax_dev, double
  * Batched step: nprob independent 1D problems with one flux, each with its
  * own cell count n[b], largest half-width P[b], boundary bc[b], spacing
  * dx[b] and time step dt[b], advanced together (one classification launch,
- * one persistent launch per order class over all problems).  Per problem
+ * one persistent flux launch over all problems and order classes, or one
+ * per order class with a launch table below).  Per problem
  * the result equals acat_step bit for bit.
  *   States: SoA over the concatenated cells, u[var][coff_b + i] with
  *   coff_b = n[0] + ... + n[b-1] (total C cells: arrays of nvar * C).
