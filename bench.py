@@ -38,11 +38,16 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel: str):
+COUNTER_WINDOW = (2048, 20, 5)     # grid size, timed steps, warm-up steps of the counter runs
+
+
+def traffic_from_profiles(kernel: str, n: int, steps: int, warmup: int):
     """HBM bytes per launch of `kernel` from the committed counter summary,
-    if it was taken on the current kernel source."""
+    if it was taken on the current kernel source and on the same grid and
+    step window (the class mix, and so the bytes per launch, change along
+    a run)."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_c3_counters.txt")
-    if not os.path.exists(path):
+    if (n, steps, warmup) != COUNTER_WINDOW or not os.path.exists(path):
         return None
     digest = kernel_source_digest()
     vals = {}
@@ -668,13 +673,13 @@ def main():
     dom = max((k for k in kernels if k.startswith("flux2d")), key=lambda k: kernels[k]["total_ms"])
     dom_launches = kernels[dom]["launches"]
     achieved = class_flops[dom] / (kernels[dom]["total_ms"] * 1e-3) / 1e12
-    traffic = traffic_from_profiles(dom)
+    traffic = traffic_from_profiles(dom, n, args.steps, args.warmup)
     alg_total = sum(class_flops.values()) + args.steps * cells * (F.classify_flops(P, 4, 2) + F.update_flops(4, 2))
     kern_ms = sum(v["total_ms"] for v in kernels.values())
     hist_cls = hist[:, :P * P].sum(0)
     peaks = measured_peaks(acat)
     out = {
-        "metric": "ACAT FP64 cell-updates/s, 2D Euler 2048^2",
+        "metric": f"ACAT FP64 cell-updates/s, 2D Euler {n}^2",
         "value": value,
         "unit": "cell-updates/s",
         "n_gpus": 1,
@@ -686,11 +691,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded generator, workloads.euler_2d)",
-        "config": {"workload": WORKLOAD, "nx": n, "ny": n, "P": P, "cfl": w["cfl"],
+        "config": {"workload": WORKLOAD.replace("2048x2048", f"{n}x{n}"), "nx": n, "ny": n, "P": P, "cfl": w["cfl"],
                    "first_timed_step": args.warmup},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": traffic, "launches": dom_launches,
+                     "traffic": traffic,
+                     "traffic_window": "2048^2, steps %d-%d (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated); "
+                                       "null for another grid or window" % (COUNTER_WINDOW[2],
+                                                                            sum(COUNTER_WINDOW[1:]) - 1),
+                     "launches": dom_launches,
                      "avg_launch_us": kernels[dom]["avg_us"],
                      "alg_flops_per_launch": class_flops[dom] / max(dom_launches, 1),
                      "frac_of_measured_fp64": achieved / peaks["fp64_fma_tflops"]},
