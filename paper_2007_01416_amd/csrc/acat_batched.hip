@@ -140,6 +140,7 @@ __device__ __forceinline__ void flux_b_body(const KBatch& bt, const KBStep& st, 
 #pragma unroll
       for (int ri = 0; ri < L; ++ri) {
         const int r = ri - p + 1;
+        if (TB.GT[p][kk - 1][ri] == 0.0) continue;   // zero weight: nothing to add
         double ph[NV];
         if (r == 0) {
 #pragma unroll
@@ -220,7 +221,7 @@ template <int FLUX, int NV>
 __global__ __launch_bounds__(BLOCK) void k_flux_b_all(KBatch bt, KBStep st) {
   __shared__ double xsmem[flux_b_all_lds<NV>()];
   // relative cost of one interface of order p (1D Euler flops of the recursion)
-  constexpr int64_t cost[BATCH_PMAX + 1] = {0, 172, 1268, 4650, 11528};
+  constexpr int64_t cost[BATCH_PMAX + 1] = {0, 172, 1212, 4482, 11192};
   const int units = (int)gridDim.x / NXCD;
   int64_t work[BATCH_PMAX + 1], total = 0;
   int nz = 0;

@@ -183,6 +183,9 @@ __global__ __launch_bounds__(BLOCK) void k_flux1d(KProb pb, KStep st) {
 #pragma unroll
         for (int ri = 0; ri < L; ++ri) {
           const int r = ri - p + 1;
+          // a time node whose weight is exactly zero adds nothing: its flux
+          // is not evaluated (the same sum for finite values)
+          if (TB.GT[p][kk - 1][ri] == 0.0) continue;
           double ph[NV];
           if (r == 0) {
 #pragma unroll
@@ -490,6 +493,10 @@ __device__ __forceinline__ void corner_pass(const Phys& ph, const double (&u)[NV
 #pragma unroll
     for (int ri = 0; ri < 2 * QT; ++ri) {
       const int r = ri - QT + 1;
+      // a time node whose weight is exactly zero adds nothing to Fh, Gh: its
+      // fluxes (and reciprocal density) are not evaluated (the same sums
+      // for finite values)
+      if (TB.GT[QT][kk - 1][ri] == 0.0) continue;
       double pf[NV], pg[NV];
       if (r == 0) {
 #pragma unroll

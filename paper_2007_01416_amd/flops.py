@@ -5,7 +5,13 @@ multiply-add counts 2.  The counts are those of the method's own steps for
 the order actually selected at each interface or corner (Sec. 2.2 recursion
 in 1D; Sec. 4 corner recursion on the rectangle J_q1 x J_q2, with the last
 recursion step restricted to the nodes the final fluxes read, i.e. row
-j2 = 0 for F and column j1 = 0 for G, as Sec. 4 allows).  The Taylor
+j2 = 0 for F and column j1 = 0 for G, as Sec. 4 allows).  A time node whose
+weight in the time-derivative approximation of a level is exactly zero (on
+the 2q nodes -q+1..q the even-order weights of node r = q vanish) adds
+nothing to that level's sum: its flux evaluation and weighted term are not
+counted, as the forward kernels skip them; its Taylor prediction is, since
+later levels read it.  The adjoint's count keeps every time node: its
+kernels evaluate them all.  The Taylor
 predictions u + sum_{l<k} (r dt)^l/l! u~^(l) at the time nodes are counted
 in their incremental form, one term added per level (the same sums: each
 level extends the previous level's partial sum), not re-summed from u at
@@ -36,10 +42,37 @@ counted.
 """
 from __future__ import annotations
 
+from fractions import Fraction
+from functools import lru_cache
+
 C_FG_EULER2D = 16
 C_F_EULER2D = 13
 C_F = {("euler", 1): 8, ("burgers", 1): 2, ("advection", 1): 1}
 V_FG_EULER2D = 58
+
+
+@lru_cache(maxsize=None)
+def time_nodes(qt: int, k: int):
+    """(weighted nodes, weighted nodes other than r = 0) of the order-k
+    time-derivative approximation at r = 0 on the nodes r = -qt+1..qt: the
+    weight of node r is k! times the x^k coefficient of its Lagrange basis
+    polynomial, computed exactly."""
+    nodes = list(range(-qt + 1, qt + 1))
+    nz = nzf = 0
+    for r in nodes:
+        poly = [Fraction(1)]                     # coefficients, lowest degree first
+        for m in nodes:
+            if m == r:
+                continue
+            nxt = [Fraction(0)] * (len(poly) + 1)
+            for i, a in enumerate(poly):         # poly * (x - m) / (r - m)
+                nxt[i + 1] += a / (r - m)
+                nxt[i] -= a * m / (r - m)
+            poly = nxt
+        if poly[k] != 0:
+            nz += 1
+            nzf += r != 0
+    return nz, nzf
 
 
 def _pass_2d(n1, n2, qt, do_f, do_g, s, cfg, cf):
@@ -50,10 +83,11 @@ def _pass_2d(n1, n2, qt, do_f, do_g, s, cfg, cf):
     total = 0
     for kk in range(2, T + 1):
         w_cost = 2 * s                           # one more term of the Taylor prediction of one state
+        nz, nzf = time_nodes(qt, kk - 1)
         if kk < T:
             total += R * u_cost
-            total += R * (T - 1) * (w_cost + cfg)
-            total += R * 2 * (2 * s * T)         # Fh and Gh time derivatives
+            total += R * ((T - 1) * w_cost + nzf * cfg)
+            total += R * 2 * (2 * s * nz)        # Fh and Gh time derivatives
         else:
             a1c = n1 // 2 - 1                    # column index of j1 = 0
             a2c = n2 // 2 - 1                    # row index of j2 = 0
@@ -64,8 +98,8 @@ def _pass_2d(n1, n2, qt, do_f, do_g, s, cfg, cf):
                     if not (need_f or need_g):
                         continue
                     total += u_cost
-                    total += (T - 1) * (w_cost + (cfg if (need_f and need_g) else cf))
-                    total += (int(need_f) + int(need_g)) * 2 * s * T
+                    total += (T - 1) * w_cost + nzf * (cfg if (need_f and need_g) else cf)
+                    total += (int(need_f) + int(need_g)) * 2 * s * nz
     if do_f:
         total += T * s * (2 * n1 + 2)            # sum_k (1/k!) sum_l eta_l Fh^{k-1}
     if do_g:
@@ -95,9 +129,10 @@ def interface_flops_1d(p: int, s: int, cf: int) -> int:
     n = T = 2 * p
     total = n * cf
     for kk in range(2, T + 1):
+        nz, nzf = time_nodes(p, kk - 1)
         total += n * s * (2 * n + 1)             # spatial derivative and scaling
-        total += n * (T - 1) * (2 * s + cf)      # one more prediction term, flux at the prediction
-        total += n * s * 2 * T
+        total += n * ((T - 1) * 2 * s + nzf * cf)   # one more prediction term; flux at the weighted ones
+        total += n * s * 2 * nz
     total += T * s * (2 * n + 2)
     if p == 1:
         total += cf + 10 * s
